@@ -1,0 +1,184 @@
+"""Pins of the oracle's mesh tables, EFIE matrix, far field and Mie reference (CPU)."""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import efie, mesh, mie
+from oracle.quadrature import gauss01
+
+
+def test_icosphere_counts_and_rwg_convention():
+    for s in range(4):
+        V, F = workloads.icosphere(s)
+        m = mesh.build(V, F)
+        assert m.nt == 20 * 4 ** s and m.ne == 30 * 4 ** s
+        # first-visit numbering: T+ is the lower-indexed triangle, ids increase with T+
+        assert np.all(m.edge_tri[:, 0] < m.edge_tri[:, 1])
+        assert np.all(np.diff(m.edge_tri[:, 0]) >= 0)
+        # every triangle's local edge a is opposite vertex a and signs match T+/T-
+        for e in range(0, m.ne, max(1, m.ne // 50)):
+            tp, tm = m.edge_tri[e]
+            ap, am = m.edge_loc[e]
+            assert m.tri_edge[tp, ap] == e and m.tri_sign[tp, ap] == 1
+            assert m.tri_edge[tm, am] == e and m.tri_sign[tm, am] == -1
+            assert m.F[tp, ap] not in m.F[tm] and m.F[tm, am] not in m.F[tp]
+
+
+def test_rwg_normal_flux_continuity_and_divergence():
+    """phi.n_edge is continuous across the edge (value l/(2A) * height = 1 at
+    the edge), and div phi integrates to zero over the support."""
+    V, F = workloads.icosphere(1)
+    m = mesh.build(V, F)
+    for e in range(0, m.ne, 7):
+        tp, tm = m.edge_tri[e]
+        ap, am = m.edge_loc[e]
+        a, b = m.F[tp, (ap + 1) % 3], m.F[tp, (ap + 2) % 3]
+        xm = 0.5 * (m.V[a] + m.V[b])
+        # in-plane unit vectors pointing across the edge, out of T+ and into T-
+        ep = m.V[b] - m.V[a]
+        np_ = np.cross(ep, m.normal[tp]); np_ /= np.linalg.norm(np_)
+        nm_ = np.cross(ep, m.normal[tm]); nm_ /= np.linalg.norm(nm_)
+        fp = mesh.rwg_eval(m, tp, ap, xm) @ np_
+        fm = mesh.rwg_eval(m, tm, am, xm) @ nm_
+        assert abs(fp - 1.0) < 1e-12 and abs(fm - 1.0) < 1e-12
+        assert abs(mesh.rwg_div(m, tp, ap) * m.area[tp] + mesh.rwg_div(m, tm, am) * m.area[tm]) < 1e-13
+
+
+@pytest.mark.parametrize("case", ["open", "nonmanifold", "flipped_one", "inward", "degenerate", "nan"])
+def test_mesh_validation_rejects(case):
+    V, F = workloads.icosphere(1)
+    V = V.copy()
+    F = F.copy()
+    if case == "open":
+        F = F[1:]
+    elif case == "nonmanifold":
+        F = np.vstack([F, F[:1]])
+    elif case == "flipped_one":
+        F[3] = F[3][[0, 2, 1]]
+    elif case == "inward":
+        F = F[:, [0, 2, 1]]
+    elif case == "degenerate":
+        V[F[0, 1]] = V[F[0, 0]] + 1e-18
+    elif case == "nan":
+        V[0, 0] = np.nan
+    with pytest.raises(mesh.MeshError):
+        mesh.build(V, F)
+
+
+def test_efie_reciprocity(oracle_levels):
+    """Z is complex symmetric: exactly (to rounding) on pairs integrated with the
+    symmetric 6-point rule, to quadrature tolerance on touching pairs whose two
+    orders are integrated independently."""
+    lv = oracle_levels(2)
+    Z = lv.Z
+    m = lv.mesh
+    asym = np.abs(Z - Z.T) / np.abs(Z).max()
+    assert asym.max() < 1e-6
+    # entries whose four triangle pairs are all non-touching are symmetric to rounding
+    P = set()
+    tp = mesh.touching_pairs(m)
+    for v in tp.values():
+        P.update(map(tuple, v.tolist()))
+    far = []
+    rng = np.random.default_rng(0)
+    for _ in range(400):
+        a, b = rng.integers(0, m.ne, 2)
+        if all((int(i), int(j)) not in P for i in m.edge_tri[a] for j in m.edge_tri[b]):
+            far.append((a, b))
+    far = np.array(far)
+    assert np.max(asym[far[:, 0], far[:, 1]]) < 1e-14
+
+
+def test_entries_one_by_one_match_assembly(oracle_levels):
+    lv = oracle_levels(1)
+    rng = np.random.default_rng(3)
+    r = rng.integers(0, lv.n, 30)
+    c = rng.integers(0, lv.n, 30)
+    r[:3] = c[:3]  # include diagonal (identical-pair) entries
+    got = efie.entries(lv.mesh, lv.k, r, c)
+    assert np.max(np.abs(got - lv.Z[r, c])) < 1e-15 * np.abs(lv.Z).max() * 10
+
+
+def test_mie_rayleigh_limit():
+    """ka -> 0: PEC sphere = electric dipole 4 pi a^3 E0 plus magnetic dipole
+    -2 pi a^3 H0, so F = 4 pi k^2 a^3 [(I - x x^T) e_x + x x e_y / 2]."""
+    a, k = 0.01, 1.0
+    xh = workloads.angles_xz(13)
+    F = mie.pec_far_field(k, a, xh)
+    ref = 4 * np.pi * k ** 2 * a ** 3 * ((np.eye(3)[0] - xh * xh[:, :1]) + 0.5 * np.cross(xh, np.eye(3)[1]))
+    assert np.max(np.abs(F - ref)) < 1e-4 * np.abs(ref).max()
+
+
+def _sphere_grid(n_t=48, n_p=96):
+    x, w = gauss01(n_t)
+    mu = 2 * x - 1
+    wt = 2 * w
+    ph = 2 * np.pi * np.arange(n_p) / n_p
+    MU, PH = np.meshgrid(mu, ph, indexing="ij")
+    st = np.sqrt(1 - MU ** 2)
+    pts = np.stack([st * np.cos(PH), st * np.sin(PH), MU], -1).reshape(-1, 3)
+    W = (wt[:, None] * np.full(n_p, 2 * np.pi / n_p)[None]).ravel()
+    return pts, W
+
+
+def test_mie_optical_theorem():
+    """(1/k) Im(p . F(d)) = (1/16 pi^2) int |F|^2 for a lossless scatterer."""
+    for k in (1.0, 3.0, 5.0):
+        pts, W = _sphere_grid()
+        F = mie.pec_far_field(k, 1.0, pts)
+        lhs = np.imag(mie.pec_far_field(k, 1.0, np.array([[0, 0, 1.0]]))[0, 0]) / k
+        rhs = np.sum(W * np.sum(np.abs(F) ** 2, 1)) / (16 * np.pi ** 2)
+        assert abs(lhs - rhs) < 1e-10 * rhs
+        qe, qs = mie.extinction_scattering(k, 1.0)
+        assert abs(qe - qs) < 1e-12 * qs
+        # extinction cross-section pi a^2 Q_ext = (4 pi / k) Im(p . f(d)) with f = F / (4 pi)
+        assert abs(np.pi * qe - lhs) < 1e-10 * lhs
+
+
+def test_bem_optical_theorem_and_mie_convergence(oracle_levels):
+    """First moment: far field converges to Mie at O(h^2) (the paper's sphere
+    experiment reports O(h^2) for the first moment); the discrete solution
+    also satisfies the optical theorem up to discretisation error."""
+    xh = workloads.angles_xz(181)
+    Fm = mie.pec_far_field(1.0, 1.0, xh)
+    errs = []
+    for s in (1, 2, 3):
+        lv = oracle_levels(s)
+        F = efie.far_field(lv.mesh, 1.0, lv.u, xh)
+        errs.append(np.linalg.norm(F - Fm) / np.linalg.norm(Fm))
+    rates = [errs[i] / errs[i + 1] for i in range(2)]
+    assert errs[-1] < 1e-2 and min(rates) > 3.5, (errs, rates)
+    lv = oracle_levels(3)
+    pts, W = _sphere_grid(24, 48)
+    F = efie.far_field(lv.mesh, 1.0, lv.u, pts)
+    lhs = np.imag(efie.far_field(lv.mesh, 1.0, lv.u, np.array([[0, 0, 1.0]]))[0, 0])
+    rhs = np.sum(W * np.sum(np.abs(F) ** 2, 1)) / (16 * np.pi ** 2)
+    assert abs(lhs - rhs) < 2e-2 * rhs
+
+
+def test_incident_rhs_matches_definition():
+    """b = -int E^inc . phi for a few RWGs, against an independent 16x refined
+    midpoint-subdivision rule on each support triangle (pins sign, polarisation
+    and basis orientation; the difference is the 6-point rule's error)."""
+    V, F = workloads.icosphere(2)
+    m = mesh.build(V, F)
+    k, d, p = 1.0, np.array([0.0, 0.6, 0.8]), np.array([1.0, 0.0, 0.0])
+    b = efie.incident_rhs(m, k, d, p)
+    # 256 sub-triangles per triangle, centroid rule
+    n = 16
+    bary = []
+    for i in range(n):
+        for j in range(n - i):
+            bary.append(((i + 1 / 3) / n, (j + 1 / 3) / n))
+            if i + j < n - 1:
+                bary.append(((i + 2 / 3) / n, (j + 2 / 3) / n))
+    bary = np.array(bary)
+    lam = np.stack([1 - bary.sum(1), bary[:, 0], bary[:, 1]], 1)
+    for e in (0, 17, 63, 401):
+        acc = 0.0
+        for t, a in zip(m.edge_tri[e], m.edge_loc[e]):
+            x = lam @ m.V[m.F[t]]
+            val = np.exp(1j * k * x @ d)[:, None] * p[None]
+            acc += -np.sum(m.area[t] / len(x) * np.einsum("qc,qc->q", val, mesh.rwg_eval(m, t, a, x)))
+        assert abs(acc - b[e]) < 1e-3 * abs(b[e])
