@@ -1,0 +1,271 @@
+"""Benchmark of the FOSB hot path on one MI355X.
+
+One step = one pass of the whole hot path over the workload "mixed_k5":
+unit icosphere levels s = 2..5 (480 / 1920 / 7680 / 30720 RWG), k = 5,
+plane wave d = e_z, p = e_x, radial Gaussian covariance (sigma 0.01, ell 0.5),
+combination technique L0 = 2, L = 5 (4 level pairs), 181 angles in the
+xz-plane:
+  EFIE assembly of every level -> LU + first moment + RHS weights of every
+  level -> RHS correlation and two-sided solve of every CT pair -> far-field
+  variance.
+Inputs (meshes, uploaded tables) and output buffers are resident on the GPU
+before the timed region.  The metric is level-pair solves per second of the
+mixed-precision path (FP32-complex MFMA LU + FP64 refinement); the FP64 path
+is timed too and reported next to it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision both|mixed|fp64]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "mixed": 157.3}          # dense MFMA TFLOP/s (FP64, FP32)
+HBM_PEAK = 8000.0                               # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
+    ap.add_argument("--max-level", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+class Workload:
+    def __init__(self, max_level: int):
+        import workloads
+        self.w = workloads.workload("mixed_k5", max_level=max_level)
+        self.xh = self.w.angles
+
+
+def gpu_setup(fosb, torch, ctx, W):
+    meshes = [fosb.Mesh(ctx, V, F) for V, F in W.w.meshes]
+    Z = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex128, device=ctx.torch_device) for m in meshes]
+    return meshes, Z
+
+
+def one_step(fosb, torch, ctx, W, meshes, Z, Zlow, precision, cov, opts, stage_ev=None):
+    w = W.w
+    k = w.k
+    L0, L = w.L0, w.L
+    ev = stage_ev
+    if ev:
+        ev[0].record()
+    for m, z in zip(meshes, Z):
+        fosb.assemble(ctx, m, k, opts, Z=z)
+    if ev:
+        ev[1].record()
+    levels = [fosb.Level(ctx, m, k, z, precision, w.dirs, w.pols, "radial", opts,
+                         Zlow=(zl if precision == fosb.MIXED else None))
+              for m, z, zl in zip(meshes, Z, Zlow)]
+    if ev:
+        ev[2].record()
+    st = fosb.Stats()
+    blocks = fosb.correlation(ctx, levels, L0, L, cov, 0, stats=st)
+    if ev:
+        ev[3].record()
+    var = fosb.far_field_moments(ctx, levels, L0, L, blocks, W.xh)
+    if ev:
+        ev[4].record()
+    return var, blocks, levels, st
+
+
+def algorithmic_flops(W):
+    """8 flop per complex multiply-add: LU (8/3) N^3 per level, two-sided solve
+    8 N1 N2 (N1 + N2) per pair, far-field contraction 24 n_a N1 N2 per pair."""
+    from paper_2308_01457_amd import fosb
+    N = {s: 30 * 4 ** s for s in W.w.levels}
+    lu = sum(8.0 / 3.0 * n ** 3 for n in N.values())
+    pairs = fosb.ct_pairs(W.w.L0, W.w.L)
+    solve = sum(8.0 * N[a] * N[b] * (N[a] + N[b]) for a, b, _, _ in pairs)
+    ff = sum(24.0 * W.w.n_angles * N[a] * N[b] for a, b, _, _ in pairs)
+    return lu, solve, ff, len(pairs)
+
+
+def run_gpu(args, W):
+    import torch
+    from paper_2308_01457_amd import fosb
+
+    ctx = fosb.Context(0)
+    cov = fosb.make_cov(W.w.cov_kind, W.w.sigma, W.w.ell)
+    opts = fosb.opts_default(ir_tol=1e-10, ir_max_sweeps=10)
+    meshes, Z = gpu_setup(fosb, torch, ctx, W)
+    precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    Zlow = [None] * len(meshes)
+    if "mixed" in precs:
+        Zlow = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex64, device=ctx.torch_device) for m in meshes]
+    lu_f, solve_f, ff_f, npairs = algorithmic_flops(W)
+    out = {}
+    for pname in precs:
+        prec = fosb.MIXED if pname == "mixed" else fosb.FP64
+        log(f"[bench] {pname}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            res = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts)
+            del res
+        torch.cuda.synchronize()
+        stage = np.zeros(4)
+        times = []
+        var = None
+        for i in range(args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            var, blocks, levels, st = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts, ev)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            times.append(dt)
+            stage += [ev[j].elapsed_time(ev[j + 1]) * 1e-3 for j in range(4)]
+            log(f"[bench] {pname} step {i}: {dt:.3f} s  (ir sweeps {st.ir_sweeps})")
+            keep_var = var.cpu().numpy()
+            del blocks, levels
+        stage /= max(1, args.steps)
+        t_step = float(np.mean(times))
+        rec = {"seconds_per_step": t_step, "pair_solves_per_s": npairs / t_step,
+               "stage_s": {"assemble": stage[0], "lu_first_moment": stage[1], "pairs": stage[2],
+                           "far_field": stage[3]},
+               "lu_tflops": lu_f / stage[1] / 1e12, "ir_sweeps": int(st.ir_sweeps), "var": keep_var}
+        if not args.no_profile:
+            log(f"[bench] {pname}: profiled step")
+            fosb.profile_enable(ctx, True)
+            res = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts)
+            prof = fosb.profile_read(ctx)
+            fosb.profile_enable(ctx, False)
+            del res
+            rec["profile"] = prof
+        out[pname] = rec
+    return out, (lu_f, solve_f, ff_f, npairs)
+
+
+def cpu_baseline(W):
+    """The oracle on a bounded sample of the same workload: levels s = 2, 3 of
+    the ladder (480 and 1920 RWG) timed stage by stage on the host, then
+    extrapolated to the full ladder with the stages' cost laws (regular
+    assembly ~ T^2, LU ~ N^3, pair solve ~ N1 N2 (N1 + N2), RHS correlation
+    ~ N1 N2, far field ~ N1 N2 n_a)."""
+    import scipy.linalg as sla
+
+    import workloads
+    from oracle import uq
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    w = W.w
+    xh = W.xh
+    t = {}
+    lv = {}
+    for s in (2, 3):
+        V, F = workloads.icosphere(s)
+        t0 = time.perf_counter()
+        from oracle import efie, mesh
+        m = mesh.build(V, F)
+        Z = efie.assemble(m, w.k)
+        t[("asm", s)] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        lv[s] = uq.make_level(V, F, w.k, Z=Z)
+        t[("lu", s)] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    C = uq.rhs_correlation(lv[3], lv[2], w.cov_kind, w.sigma, w.ell)
+    t_c = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    S = uq.two_sided_solve(lv[3], lv[2], C)
+    t_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    FF3 = uq.far_field_matrix(lv[3], xh)
+    FF2 = uq.far_field_matrix(lv[2], xh)
+    uq.pair_variance(FF3, S, FF2)
+    t_f = time.perf_counter() - t0
+    sample_s = sum(t.values()) + t_c + t_s + t_f
+    # extrapolation to the full ladder
+    N = {s: 30 * 4 ** s for s in w.levels}
+    T = {s: 20 * 4 ** s for s in w.levels}
+    proj = 0.0
+    for s in w.levels:
+        proj += t[("asm", 3)] * (T[s] / T[3]) ** 2 + t[("lu", 3)] * (N[s] / N[3]) ** 3
+    from paper_2308_01457_amd import fosb
+    pairs = fosb.ct_pairs(w.L0, w.L)
+    base_s = 8.0 * N[3] * N[2] * (N[3] + N[2])
+    for a, b, _, _ in pairs:
+        proj += t_s * 8.0 * N[a] * N[b] * (N[a] + N[b]) / base_s
+        proj += (t_c + t_f) * N[a] * N[b] / (N[3] * N[2])
+    return {"value": len(pairs) / proj, "unit": "level-pair solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle (numpy/scipy FP64) timed on levels s=2,3 of the ladder (assembly, LU + first moment, "
+                       f"the (3,2) RHS correlation, two-sided solve and far-field contraction; {sample_s:.1f} s), "
+                       f"extrapolated to s=2..5 by T^2 (assembly), N^3 (LU), N1 N2 (N1+N2) (pair solve); "
+                       f"projected {proj:.0f} s per step"),
+            "projected_seconds_per_step": proj}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    W = Workload(args.max_level)
+    gpu, (lu_f, solve_f, ff_f, npairs) = run_gpu(args, W)
+    head = "mixed" if "mixed" in gpu else "fp64"
+    h = gpu[head]
+    line = {
+        "metric": "Cor[u'] level-pair solves/sec + MFMA TFLOP/s, mixed vs FP64 at 1e-6 rel err",
+        "value": h["pair_solves_per_s"],
+        "unit": "level-pair solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["seconds_per_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if head == "mixed" else "c128",
+        "data": "synthetic",
+        "config": {"workload": f"mixed_k5: unit icosphere s={W.w.levels[0]}..{W.w.levels[-1]} "
+                               f"(N up to {30 * 4 ** W.w.levels[-1]}), k=5, Gaussian radial cov (0.01, 0.5), "
+                               f"L0={W.w.L0} L={W.w.L} ({npairs} pairs), {W.w.n_angles} angles",
+                   "precision": head},
+        "algorithmic_flop_per_step": {"lu": lu_f, "pair_solves": solve_f, "far_field": ff_f},
+    }
+    for pname, rec in gpu.items():
+        line[pname] = {k: v for k, v in rec.items() if k not in ("var", "profile")}
+    if "mixed" in gpu and "fp64" in gpu:
+        v64, v32 = gpu["fp64"]["var"], gpu["mixed"]["var"]
+        line["mixed_speedup_vs_fp64"] = gpu["fp64"]["seconds_per_step"] / gpu["mixed"]["seconds_per_step"]
+        line["mixed_vs_fp64_var_rel_err"] = float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64))
+    prof = h.get("profile")
+    if prof:
+        kname = "gemm_f32" if head == "mixed" else "gemm_f64"
+        n, sec, fl, by = prof[kname]
+        ach = fl / sec / 1e12 if sec > 0 else 0.0
+        line["roofline"] = {"kernel": f"k_gemm<{'float' if head == 'mixed' else 'double'}>", "bound": "mfma",
+                            "achieved": ach, "peak": PEAK[head], "unit": "TFLOP/s", "frac": ach / PEAK[head],
+                            "traffic": None, "launches": n, "avg_launch_us": sec / max(n, 1) * 1e6,
+                            "algorithmic_flop_per_launch": fl / max(n, 1)}
+        line["kernel_profile"] = {k: {"launches": v[0], "seconds": v[1], "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
+                                      "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof.items()}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        line["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

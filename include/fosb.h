@@ -1,0 +1,235 @@
+/*
+ * fosb.h -- C ABI of the MI355X (gfx950) FOSB hot path.
+ *
+ * The library computes the second moment of the shape derivative of the
+ * current on a perfectly conducting (PEC) scatterer with the first-order sparse
+ * boundary element method (arXiv 2308.01457): dense Galerkin EFIE matrices on
+ * RWG elements per mesh level, the two-sided solves Z_l1 Sigma Z_l2^H = C_l1l2
+ * over the combination technique's level pairs, and the far-field variance.
+ *
+ * Conventions shared by every entry point
+ *   - Complex arrays are interleaved (re, im) and row-major; complex128 unless
+ *     stated.  Sizes and leading dimensions are int64_t, in elements.
+ *   - "device" pointers are HIP device memory owned by the caller (typically
+ *     torch tensors); they must stay valid until the context's stream has run
+ *     the enqueued work.  "host" pointers are read during the call only.
+ *   - Handles (context, mesh, level) are owned by the library until *_destroy.
+ *     The library allocates its own O(N) tables and O(N*nrhs) work buffers with
+ *     hipMalloc on the context's device; O(N^2) matrices are always caller
+ *     buffers.
+ *   - All work is enqueued on the context's stream.  Calls that must inspect a
+ *     device result (pivot breakdown, refinement convergence) synchronise that
+ *     stream before returning.
+ *   - Errors: every call returns a fosb_status; nothing throws or aborts across
+ *     the ABI.  Arguments are validated on the host before any launch.  On an
+ *     error the outputs are unspecified (except FOSB_E_NOCONV, see below) and
+ *     fosb_last_error() returns a message (thread-local).
+ *
+ * Mesh and basis conventions (paper: Galerkin section, planar triangulations):
+ *   local edge a of triangle t is opposite vertex F[t][a]; edges are numbered in
+ *   first-visit order scanning t = 0..nt-1, a = 0,1,2; the triangle that visits
+ *   an edge first is T+, the other T-; the RWG function of an edge of length l
+ *   is +l/(2A+) (x - p+) on T+ and -l/(2A-) (x - p-) on T- (p = free vertex).
+ */
+#ifndef FOSB_H
+#define FOSB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fosb_context fosb_context;
+typedef struct fosb_mesh fosb_mesh;
+typedef struct fosb_level fosb_level;
+
+typedef enum fosb_status {
+  FOSB_OK = 0,
+  FOSB_E_INVALID = 1,     /* bad argument or invalid mesh                       */
+  FOSB_E_SINGULAR = 2,    /* exactly zero pivot; fosb_last_error names its index */
+  FOSB_E_NOCONV = 3,      /* refinement did not reach its tolerance; outputs hold
+                             the last iterate and fosb_stats the achieved values  */
+  FOSB_E_WORKSPACE = 4,   /* a caller buffer / leading dimension is too small    */
+  FOSB_E_OOM = 5,         /* device allocation failed                            */
+  FOSB_E_DEVICE = 6,      /* HIP runtime error                                   */
+  FOSB_E_UNSUPPORTED = 7  /* valid request this build does not implement         */
+} fosb_status;
+
+typedef enum fosb_precision {
+  FOSB_PREC_FP64 = 0,  /* complex128 LU and solves                                */
+  FOSB_PREC_MIXED = 1  /* complex64 LU on FP32 MFMA + FP64 iterative refinement   */
+} fosb_precision;
+
+/* Covariance M2[v_r](x, y) of the scalar perturbation amplitude, r = |x - y|. */
+typedef enum fosb_cov_kind {
+  FOSB_COV_GAUSSIAN = 0,   /* sigma^2 exp(-r^2 / (2 ell^2))                        */
+  FOSB_COV_MATERN32 = 1,   /* sigma^2 (1 + sqrt3 r/ell) exp(-sqrt3 r/ell)          */
+  FOSB_COV_CONSTANT = 2,   /* sigma^2 (random change of scale)                     */
+  FOSB_COV_NORMAL_DOT = 3  /* sigma^2 n(x).n(y) (rigid translation, c ~ N(0,s^2 I)) */
+} fosb_cov_kind;
+
+/* How the scalar amplitude v_r becomes the normal velocity v_n. */
+typedef enum fosb_field {
+  FOSB_FIELD_RADIAL = 0,   /* v = v_r x/|x|, v_n = v_r (x/|x|).n                   */
+  FOSB_FIELD_NORMAL = 1    /* v_n = v_r                                            */
+} fosb_field;
+
+typedef struct fosb_cov {
+  int32_t kind;   /* fosb_cov_kind                                                */
+  int32_t pad;
+  double sigma;   /* amplitude (standard deviation), >= 0                          */
+  double ell;     /* correlation length, > 0 (ignored by CONSTANT, NORMAL_DOT)     */
+} fosb_cov;
+
+typedef struct fosb_opts {
+  int32_t n_gauss_singular; /* Gauss-Legendre points per dimension of the
+                               Sauter-Schwab rules on touching pairs (1..12; 5)   */
+  int32_t ir_max_sweeps;    /* refinement sweeps of the MIXED path (0..50; 10)     */
+  double ir_tol;            /* stop when ||dX||_F <= ir_tol ||X||_F (1e-10)        */
+} fosb_opts;
+
+typedef struct fosb_stats {
+  int32_t ir_sweeps;        /* largest number of refinement sweeps used            */
+  int32_t n_solves;         /* level-pair solves performed                         */
+  double ir_rel_correction; /* largest final ||dX||/||X||                          */
+} fosb_stats;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* fosb_last_error(void);
+/* Fills *opts with the defaults listed in fosb_opts. */
+fosb_status fosb_opts_default(fosb_opts* opts);
+
+/* ---------------------------------------------------------------- context */
+/* Binds HIP device `device` and stream `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  The stream is borrowed, not destroyed. */
+fosb_status fosb_context_create(int32_t device, void* hip_stream, fosb_context** out);
+fosb_status fosb_context_destroy(fosb_context* ctx);
+fosb_status fosb_context_synchronize(fosb_context* ctx);
+
+/* ---------------------------------------------------------------- mesh */
+/* Host-only check (no device work): V (host, nv x 3 float64), F (host, nt x 3
+ * int32).  The surface must be closed, 2-manifold, consistently oriented with
+ * outward normals (positive enclosed volume) and free of degenerate triangles;
+ * otherwise FOSB_E_INVALID.  *n_edges receives the RWG count (may be NULL). */
+fosb_status fosb_mesh_validate(const double* V, int64_t nv, const int32_t* F, int64_t nt,
+                               int64_t* n_edges);
+/* Validates as above, builds the RWG, quadrature and touching-pair tables and
+ * uploads them to the context's device. */
+fosb_status fosb_mesh_create(fosb_context* ctx, const double* V, int64_t nv, const int32_t* F,
+                             int64_t nt, fosb_mesh** out);
+fosb_status fosb_mesh_info(const fosb_mesh* mesh, int64_t* n_triangles, int64_t* n_edges,
+                           int64_t* n_touching_pairs);
+fosb_status fosb_mesh_destroy(fosb_mesh* mesh);
+
+/* ---------------------------------------------------------------- assembly */
+/* Galerkin EFIE matrix (problem setting: EFIO T_k, EFIE T_k j = gamma_D E^inc;
+ * Galerkin section: Z u = b):
+ *   Z[m][n] = int int G_k(x,y) [ -i k phi_m(x).phi_n(y) + (i/k) div phi_m div phi_n ],
+ *   G_k = exp(i k |x-y|) / (4 pi |x-y|),
+ * with the symmetric 6-point degree-4 rule on both triangles of non-touching
+ * triangle pairs and Sauter-Schwab rules (opts->n_gauss_singular points per
+ * dimension) on identical, edge- and vertex-adjacent pairs.  FP64 throughout.
+ * Z: device, N x N complex128, row stride ldz >= N (N = number of edges).
+ * k > 0.  opts may be NULL (defaults). */
+fosb_status fosb_assemble(fosb_context* ctx, const fosb_mesh* mesh, double k, const fosb_opts* opts,
+                          void* Z, int64_t ldz);
+
+/* ---------------------------------------------------------------- level */
+/* A mesh level ready for the tensor solves: LU factorisation with partial
+ * pivoting (tournament pivoting per 32-column panel), the first moment
+ * u = Z^{-1} b for each plane wave E^inc = p exp(i k d.x)
+ * (b[m] = -int E^inc . phi_m), and the shape-derivative right-hand-side weights
+ *   b'_m = int v_n [ (i/k) div j div phi_m - i k j . phi_m ]   (FOA section)
+ * of each first moment j.
+ *   precision FP64 : Z (device complex128, assembled, ldz) is overwritten by
+ *                    its LU factors; Zlow must be NULL.
+ *   precision MIXED: Z is kept read-only for FP64 refinement residuals and
+ *                    must outlive the level; Zlow (device complex64, N x N,
+ *                    ldzlow) receives the FP32 LU factors.
+ * dirs, pols: host, n_dirs x 3 float64 (unit incidence direction, real
+ * polarisation).  field: fosb_field.  On an exactly zero pivot returns
+ * FOSB_E_SINGULAR. */
+fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k, int32_t precision,
+                              void* Z, int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs,
+                              const double* pols, int64_t n_dirs, int32_t field,
+                              const fosb_opts* opts, fosb_level** out);
+fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precision, int64_t* n_dirs);
+/* B <- Z^{-1} B (device complex128, N x nrhs, row stride ldb >= nrhs).  MIXED
+ * levels refine in FP64 against the kept Z.  stats may be NULL. */
+fosb_status fosb_level_solve(fosb_context* ctx, const fosb_level* level, void* B, int64_t ldb,
+                             int64_t nrhs, fosb_stats* stats);
+/* Copies the first-moment coefficients of direction dir into u (device, N complex128). */
+fosb_status fosb_level_first_moment(fosb_context* ctx, const fosb_level* level, int64_t dir, void* u);
+fosb_status fosb_level_destroy(fosb_level* level);
+
+/* ---------------------------------------------------------------- tensor equation */
+/* RHS correlation C = E[b'_l1 b'_l2^H] = Wgt_l1 K Wgt_l2^H (FOA section,
+ * second-moment tensor equation; combination-technique sub-systems), with K
+ * the covariance of the amplitude at the quadrature nodes of both levels.
+ * C: device, N1 x N2 complex128, row stride ldc >= N2.  dir selects the
+ * incidence (first moment) of both levels. */
+fosb_status fosb_rhs_correlation(fosb_context* ctx, const fosb_level* l1, const fosb_level* l2,
+                                 const fosb_cov* cov, int64_t dir, void* C, int64_t ldc);
+/* In place: C (N1 x N2) <- Sigma with Z1 Sigma Z2^H = C, i.e. the sub-system
+ * (Z_l1 (x) conj Z_l2) Sigma = C of the combination technique. */
+fosb_status fosb_two_sided_solve(fosb_context* ctx, const fosb_level* l1, const fosb_level* l2,
+                                 void* C, int64_t ldc, fosb_stats* stats);
+/* Hermitian-reduced combination-technique index set Lambda_H(L0, L):
+ * pairs (l1 >= l2) with l1 + l2 = L + L0 (sign +1) or L + L0 - 1 (sign -1),
+ * mult = 2 when l1 != l2 (the transposed pair is the conjugate transpose).
+ * Arrays (host) must hold L - L0 + 1 entries; *n_pairs receives the count.
+ * Order: sign +1 first, then decreasing l1. */
+fosb_status fosb_ct_pairs(int32_t L0, int32_t L, int32_t* l1, int32_t* l2, int32_t* sign,
+                          int32_t* mult, int32_t* n_pairs);
+/* All Sigma blocks of Lambda_H for direction dir.  levels[i] is level L0 + i
+ * (n_levels = L - L0 + 1); blocks[p] (device, N_l1 x N_l2 complex128, row
+ * stride ldb[p]) receives the block of pair p in fosb_ct_pairs order. */
+fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                             int32_t L0, int32_t L, const fosb_cov* cov, int64_t dir,
+                             void* const* blocks, const int64_t* ldb, fosb_stats* stats);
+
+/* ---------------------------------------------------------------- far field */
+/* Far-field map of a level (problem setting, far-field expansion):
+ *   F_c(x) = sum_m FF[c*n_a + i][m] u_m,  FF = -i k (I - x x^T) int phi_m(y) exp(-i k x.y) dy.
+ * xhat: host, n_a x 3 unit vectors.  FF: device, (3 n_a) x N complex128. */
+fosb_status fosb_far_field_matrix(fosb_context* ctx, const fosb_level* level, const double* xhat,
+                                  int64_t n_a, void* FF);
+/* Combination-technique far-field variance
+ *   var[c*n_a + i] = sum_{Lambda_H} sign mult Re (FF_l1 Sigma FF_l2^H)[(c,i),(c,i)]
+ * (device, 3 n_a float64), from the blocks of fosb_correlation.  mean_F
+ * (device, 3 n_a complex128, may be NULL) receives the first-moment far field of
+ * the finest level. */
+fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* levels,
+                                   int32_t n_levels, int32_t L0, int32_t L, void* const* blocks,
+                                   const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir,
+                                   double* var, void* mean_F);
+
+/* ---------------------------------------------------------------- profiling */
+/* Kernel classes timed by the profiler. */
+typedef enum fosb_kernel_class {
+  FOSB_K_GEMM_F64 = 0,      /* complex128 GEMM (LU updates, TRSM couplings, residuals) */
+  FOSB_K_GEMM_F32 = 1,      /* complex64 GEMM (mixed-precision LU and solves)           */
+  FOSB_K_ASSEMBLE = 2,      /* EFIE regular + singular pair integration and gather      */
+  FOSB_K_PANEL = 3,         /* LU panel factorisation (tournament, swaps, L21)          */
+  FOSB_K_TRSM_LEAF = 4,     /* diagonal-block inverse applications                      */
+  FOSB_K_RHS = 5,           /* RHS correlation, weights, far-field kernels              */
+  FOSB_K_COUNT = 6
+} fosb_kernel_class;
+
+/* on != 0: from now on every launch of an instrumented kernel on this context
+ * is bracketed by HIP events (adds a few microseconds of host work per launch);
+ * previous records are discarded.  on == 0: stop recording (records are kept). */
+fosb_status fosb_profile_enable(fosb_context* ctx, int32_t on);
+/* Synchronises the context's stream and returns, for kernel class `cls`, the
+ * number of recorded launches, their summed device time (s) and the summed
+ * algorithmic work of those launches: flops counts 8 per complex
+ * multiply-add (GEMM) and bytes counts the operands each launch must move
+ * at least once.  Any output pointer may be NULL. */
+fosb_status fosb_profile_read(fosb_context* ctx, int32_t cls, int64_t* launches, double* seconds,
+                              double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOSB_H */

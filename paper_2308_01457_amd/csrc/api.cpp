@@ -1,0 +1,585 @@
+// C ABI of the library (declared in include/fosb.h): argument validation,
+// object lifetimes, and the host-side orchestration of the kernels.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "common.h"
+
+namespace fosb {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+void fail(fosb_status s, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Error(s, buf);
+}
+
+static void check_opts(const fosb_opts& o) {
+  if (o.n_gauss_singular < 1 || o.n_gauss_singular > 12) fail(FOSB_E_INVALID, "opts: n_gauss_singular must be 1..12");
+  if (o.ir_max_sweeps < 0 || o.ir_max_sweeps > 50) fail(FOSB_E_INVALID, "opts: ir_max_sweeps must be 0..50");
+  if (!(o.ir_tol > 0.0) || !std::isfinite(o.ir_tol)) fail(FOSB_E_INVALID, "opts: ir_tol must be positive");
+}
+
+static fosb_opts opts_or_default(const fosb_opts* o) {
+  fosb_opts r;
+  r.n_gauss_singular = 5;
+  r.ir_max_sweeps = 10;
+  r.ir_tol = 1e-10;
+  if (o) r = *o;
+  check_opts(r);
+  return r;
+}
+
+static void bind(Context& ctx) { FOSB_HIP(hipSetDevice(ctx.device)); }
+
+// ------------------------------------------------------------------ level solve
+// B <- Z^{-1} B for a factorised level; MIXED levels refine in FP64.
+void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st) {
+  hipStream_t s = ctx.stream;
+  const int64_t n = L.n;
+  if (nrhs <= 0) return;
+  const size_t bytes128 = (size_t)n * nrhs * sizeof(c128);
+  ctx.scratch[1].reserve(bytes128);
+  c128* T = ctx.scratch[1].as<c128>();
+  if (L.precision == FOSB_PREC_FP64) {
+    permute_rows_gather(s, L.d_perm.as<int32_t>(), B, ldb, T, nrhs, n, nrhs);
+    const c128* A = static_cast<const c128*>(L.Z);
+    trsm_lower_unit<double>(ctx, A, L.ldz, L.dinv_L.as<c128>(), 0, n, T, nrhs, nrhs);
+    trsm_upper<double>(ctx, A, L.ldz, L.dinv_U.as<c128>(), 0, n, T, nrhs, nrhs);
+    copy_c128(s, T, nrhs, B, ldb, n, nrhs);
+    if (st) st->ir_sweeps = std::max(st->ir_sweeps, 0);
+    return;
+  }
+  // mixed: FP32 LU solves + FP64 residuals against the kept complex128 Z
+  ctx.scratch[2].reserve(bytes128);
+  ctx.scratch[3].reserve(bytes128);
+  ctx.scratch[4].reserve((size_t)n * nrhs * sizeof(c64));
+  ctx.norms.reserve(2 * sizeof(double));
+  c128* Bo = ctx.scratch[2].as<c128>();
+  c128* X = ctx.scratch[3].as<c128>();
+  c64* R32 = ctx.scratch[4].as<c64>();
+  const c64* A32 = static_cast<const c64*>(L.Zlow);
+  const c128* Z64 = static_cast<const c128*>(L.Z);
+  copy_c128(s, B, ldb, Bo, nrhs, n, nrhs);
+  const c128* R = Bo;  // first residual is B itself
+  double prev = INFINITY, rel = INFINITY;
+  int sweeps = 0;
+  for (int it = 0;; ++it) {
+    permute_rows_gather(s, L.d_perm.as<int32_t>(), R, nrhs, T, nrhs, n, nrhs);
+    copy_c128_to_c64(s, T, nrhs, R32, nrhs, n, nrhs);
+    trsm_lower_unit<float>(ctx, A32, L.ldzlow, L.dinv_L.as<c64>(), 0, n, R32, nrhs, nrhs);
+    trsm_upper<float>(ctx, A32, L.ldzlow, L.dinv_U.as<c64>(), 0, n, R32, nrhs, nrhs);
+    copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
+    if (it == 0) {
+      copy_c128(s, T, nrhs, X, nrhs, n, nrhs);
+    } else {
+      axpy_c128(s, T, nrhs, X, nrhs, n, nrhs);
+    }
+    norms2_c128(s, T, nrhs, X, nrhs, n, nrhs, ctx.norms.as<double>());
+    double nn[2];
+    FOSB_HIP(hipMemcpyAsync(nn, ctx.norms.p, sizeof(nn), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+    rel = nn[1] > 0 ? std::sqrt(nn[0] / nn[1]) : 0.0;
+    if (it > 0) sweeps = it;
+    if (rel <= L.opts.ir_tol || it >= L.opts.ir_max_sweeps || (it > 1 && rel >= prev)) break;
+    prev = rel;
+    // residual R = Bo - Z64 X in FP64 (scratch[5]; the next gather reads it into scratch[1])
+    ctx.scratch[5].reserve(bytes128);
+    c128* Rw = ctx.scratch[5].as<c128>();
+    copy_c128(s, Bo, nrhs, Rw, nrhs, n, nrhs);
+    gemm<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
+    R = Rw;
+  }
+  copy_c128(s, X, nrhs, B, ldb, n, nrhs);
+  if (st) {
+    st->ir_sweeps = std::max(st->ir_sweeps, sweeps);
+    st->ir_rel_correction = std::max(st->ir_rel_correction, rel);
+  }
+  if (rel > L.opts.ir_tol && L.opts.ir_max_sweeps > 0) {
+    FOSB_HIP(hipStreamSynchronize(s));
+    fail(FOSB_E_NOCONV, "refinement stopped at relative correction %.3e after %d sweeps (tol %.1e)", rel, sweeps,
+         L.opts.ir_tol);
+  }
+}
+
+static void two_sided(Context& ctx, const Level& l1, const Level& l2, c128* C, int64_t ldc, fosb_stats* st) {
+  const int64_t n1 = l1.n, n2 = l2.n;
+  // stage 1: Y = Z1^{-1} C   (n1 x n2)
+  level_solve_inplace(ctx, l1, C, ldc, n2, st);
+  // stage 2: Sigma^H = Z2^{-1} Y^H  (n2 x n1)
+  DevBuf& tb = ctx.scratch[0];
+  tb.reserve((size_t)n1 * n2 * sizeof(c128));
+  c128* Tt = tb.as<c128>();
+  conj_transpose_c128(ctx.stream, C, ldc, Tt, n1, n1, n2);
+  level_solve_inplace(ctx, l2, Tt, n1, n1, st);
+  conj_transpose_c128(ctx.stream, Tt, n1, C, ldc, n2, n1);
+  if (st) st->n_solves += 1;
+}
+
+}  // namespace fosb
+
+using namespace fosb;
+
+struct fosb_context : fosb::Context {};
+struct fosb_mesh : fosb::Mesh {};
+struct fosb_level : fosb::Level {};
+
+#define API_BEGIN try {
+#define API_END                                                   \
+  }                                                               \
+  catch (const fosb::Error& e) {                                  \
+    set_last_error(e.what());                                     \
+    return e.status;                                              \
+  }                                                               \
+  catch (const std::bad_alloc&) {                                 \
+    set_last_error("host allocation failed");                     \
+    return FOSB_E_OOM;                                            \
+  }                                                               \
+  catch (const std::exception& e) {                               \
+    set_last_error(e.what());                                     \
+    return FOSB_E_DEVICE;                                         \
+  }                                                               \
+  catch (...) {                                                   \
+    set_last_error("unknown error");                              \
+    return FOSB_E_DEVICE;                                         \
+  }                                                               \
+  set_last_error("");                                             \
+  return FOSB_OK;
+
+#define REQUIRE(cond, ...) \
+  do {                     \
+    if (!(cond)) fail(FOSB_E_INVALID, __VA_ARGS__); \
+  } while (0)
+
+extern "C" {
+
+const char* fosb_last_error(void) { return g_last_error.c_str(); }
+
+fosb_status fosb_opts_default(fosb_opts* opts) {
+  API_BEGIN
+  REQUIRE(opts, "opts is NULL");
+  *opts = opts_or_default(nullptr);
+  API_END
+}
+
+fosb_status fosb_context_create(int32_t device, void* hip_stream, fosb_context** out) {
+  API_BEGIN
+  REQUIRE(out, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  FOSB_HIP(hipGetDeviceCount(&count));
+  REQUIRE(device >= 0 && device < count, "device %d out of range (%d devices)", device, count);
+  FOSB_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  FOSB_HIP(hipGetDeviceProperties(&prop, device));
+  std::unique_ptr<fosb_context> c(new fosb_context());
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->n_cu = prop.multiProcessorCount;
+  c->max_lds = prop.sharedMemPerBlock;
+  *out = c.release();
+  API_END
+}
+
+fosb_status fosb_context_destroy(fosb_context* ctx) {
+  API_BEGIN
+  if (!ctx) return FOSB_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  API_END
+}
+
+fosb_status fosb_context_synchronize(fosb_context* ctx) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  bind(*ctx);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  API_END
+}
+
+fosb_status fosb_mesh_validate(const double* V, int64_t nv, const int32_t* F, int64_t nt, int64_t* n_edges) {
+  API_BEGIN
+  MeshHost h;
+  mesh_build_host(V, nv, F, nt, h);
+  if (n_edges) *n_edges = h.ne;
+  API_END
+}
+
+fosb_status fosb_mesh_create(fosb_context* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nt,
+                             fosb_mesh** out) {
+  API_BEGIN
+  REQUIRE(ctx && out, "ctx/out is NULL");
+  *out = nullptr;
+  std::unique_ptr<fosb_mesh> m(new fosb_mesh());
+  mesh_build_host(V, nv, F, nt, m->h);
+  mesh_touching_pairs(m->h);
+  bind(*ctx);
+  m->ctx = ctx;
+  mesh_upload(*m);
+  *out = m.release();
+  API_END
+}
+
+fosb_status fosb_mesh_info(const fosb_mesh* mesh, int64_t* n_triangles, int64_t* n_edges, int64_t* n_touching) {
+  API_BEGIN
+  REQUIRE(mesh, "mesh is NULL");
+  if (n_triangles) *n_triangles = mesh->h.nt;
+  if (n_edges) *n_edges = mesh->h.ne;
+  if (n_touching) *n_touching = (int64_t)mesh->h.tp_i.size();
+  API_END
+}
+
+fosb_status fosb_mesh_destroy(fosb_mesh* mesh) {
+  API_BEGIN
+  if (!mesh) return FOSB_OK;
+  (void)hipSetDevice(mesh->ctx->device);
+  delete mesh;
+  API_END
+}
+
+fosb_status fosb_assemble(fosb_context* ctx, const fosb_mesh* mesh, double k, const fosb_opts* opts, void* Z,
+                          int64_t ldz) {
+  API_BEGIN
+  REQUIRE(ctx && mesh, "ctx/mesh is NULL");
+  REQUIRE(mesh->ctx == ctx, "mesh belongs to another context");
+  REQUIRE(std::isfinite(k) && k > 0, "wavenumber must be positive and finite");
+  REQUIRE(Z, "Z is NULL");
+  if (ldz < mesh->h.ne) fail(FOSB_E_WORKSPACE, "ldz (%lld) < N (%lld)", (long long)ldz, (long long)mesh->h.ne);
+  fosb_opts o = opts_or_default(opts);
+  bind(*ctx);
+  {
+    const double nt = (double)mesh->h.nt;
+    ProfScope prof(*ctx, FOSB_K_ASSEMBLE, 0.0, 16.0 * (double)mesh->h.ne * (double)mesh->h.ne + 0.0 * nt);
+    assemble_efie(*ctx, *mesh, k, o.n_gauss_singular, static_cast<c128*>(Z), ldz);
+  }
+  API_END
+}
+
+fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k, int32_t precision, void* Z,
+                              int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs, const double* pols,
+                              int64_t n_dirs, int32_t field, const fosb_opts* opts, fosb_level** out) {
+  API_BEGIN
+  REQUIRE(ctx && mesh && out, "ctx/mesh/out is NULL");
+  *out = nullptr;
+  REQUIRE(mesh->ctx == ctx, "mesh belongs to another context");
+  REQUIRE(std::isfinite(k) && k > 0, "wavenumber must be positive and finite");
+  REQUIRE(precision == FOSB_PREC_FP64 || precision == FOSB_PREC_MIXED, "unknown precision %d", precision);
+  REQUIRE(field == FOSB_FIELD_RADIAL || field == FOSB_FIELD_NORMAL, "unknown field %d", field);
+  REQUIRE(Z, "Z is NULL");
+  REQUIRE(dirs && pols && n_dirs >= 1 && n_dirs <= 4096, "need 1..4096 incidence directions");
+  const int64_t n = mesh->h.ne;
+  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz < N");
+  if (precision == FOSB_PREC_MIXED) {
+    REQUIRE(Zlow, "MIXED precision needs the complex64 buffer Zlow");
+    if (ldzlow < n) fail(FOSB_E_WORKSPACE, "ldzlow < N");
+  } else {
+    REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
+  }
+  for (int64_t d = 0; d < n_dirs; ++d) {
+    double nd = 0, np = 0, dp = 0;
+    for (int c = 0; c < 3; ++c) {
+      REQUIRE(std::isfinite(dirs[3 * d + c]) && std::isfinite(pols[3 * d + c]), "non-finite direction/polarisation");
+      nd += dirs[3 * d + c] * dirs[3 * d + c];
+      np += pols[3 * d + c] * pols[3 * d + c];
+      dp += dirs[3 * d + c] * pols[3 * d + c];
+    }
+    REQUIRE(std::fabs(nd - 1.0) < 1e-9, "direction %lld is not a unit vector", (long long)d);
+    REQUIRE(np > 0, "polarisation %lld is zero", (long long)d);
+    (void)dp;
+  }
+  fosb_opts o = opts_or_default(opts);
+  bind(*ctx);
+  hipStream_t s = ctx->stream;
+  std::unique_ptr<fosb_level> L(new fosb_level());
+  L->ctx = ctx;
+  L->mesh = mesh;
+  L->k = k;
+  L->precision = precision;
+  L->n = n;
+  L->Z = Z;
+  L->ldz = ldz;
+  L->Zlow = Zlow;
+  L->ldzlow = ldzlow;
+  L->n_dirs = n_dirs;
+  L->field = field;
+  L->opts = o;
+  const int64_t nblk = (n + kPanel - 1) / kPanel;
+  int64_t info = 0;
+  if (precision == FOSB_PREC_FP64) {
+    L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
+    L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
+    info = lu_factor<double>(*ctx, static_cast<c128*>(Z), n, ldz, L->dinv_L.as<c128>(), L->dinv_U.as<c128>(), L->perm);
+  } else {
+    L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
+    L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
+    copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
+    info = lu_factor<float>(*ctx, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
+                            L->perm);
+  }
+  if (info != 0) fail(FOSB_E_SINGULAR, "exactly zero pivot at index %lld", (long long)(info - 1));
+  upload(L->d_perm, L->perm, s);
+  // quadrature nodes, first moments and RHS weights
+  L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));
+  quad_nodes(s, *mesh, L->qx.as<double>());
+  std::vector<double> dp(dirs, dirs + 3 * n_dirs), pp(pols, pols + 3 * n_dirs);
+  DevBuf ddir, dpol;
+  upload(ddir, dp, s);
+  upload(dpol, pp, s);
+  L->u.alloc((size_t)n * n_dirs * sizeof(c128));
+  incident_rhs(s, *mesh, k, ddir.as<double>(), dpol.as<double>(), (int)n_dirs, L->u.as<c128>());
+  level_solve_inplace(*ctx, *L, L->u.as<c128>(), n_dirs, n_dirs, nullptr);
+  L->W.alloc((size_t)n_dirs * mesh->h.nt * 18 * sizeof(c128));
+  for (int64_t d = 0; d < n_dirs; ++d)
+    rhs_weights(s, *mesh, k, field, L->u.as<c128>() + d, n_dirs, L->W.as<c128>() + d * mesh->h.nt * 18);
+  FOSB_HIP(hipStreamSynchronize(s));
+  *out = L.release();
+  API_END
+}
+
+fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precision, int64_t* n_dirs) {
+  API_BEGIN
+  REQUIRE(level, "level is NULL");
+  if (n) *n = level->n;
+  if (precision) *precision = level->precision;
+  if (n_dirs) *n_dirs = level->n_dirs;
+  API_END
+}
+
+fosb_status fosb_level_solve(fosb_context* ctx, const fosb_level* level, void* B, int64_t ldb, int64_t nrhs,
+                             fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && level && B, "ctx/level/B is NULL");
+  REQUIRE(level->ctx == ctx, "level belongs to another context");
+  REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+  if (ldb < nrhs) fail(FOSB_E_WORKSPACE, "ldb < nrhs");
+  bind(*ctx);
+  level_solve_inplace(*ctx, *level, static_cast<c128*>(B), ldb, nrhs, stats);
+  API_END
+}
+
+fosb_status fosb_level_first_moment(fosb_context* ctx, const fosb_level* level, int64_t dir, void* u) {
+  API_BEGIN
+  REQUIRE(ctx && level && u, "ctx/level/u is NULL");
+  REQUIRE(dir >= 0 && dir < level->n_dirs, "dir out of range");
+  bind(*ctx);
+  copy_c128(ctx->stream, level->u.as<c128>() + dir, level->n_dirs, static_cast<c128*>(u), 1, level->n, 1);
+  API_END
+}
+
+fosb_status fosb_level_destroy(fosb_level* level) {
+  API_BEGIN
+  if (!level) return FOSB_OK;
+  (void)hipSetDevice(level->ctx->device);
+  (void)hipStreamSynchronize(level->ctx->stream);
+  delete level;
+  API_END
+}
+
+static void check_pair(const fosb_context* ctx, const fosb_level* a, const fosb_level* b) {
+  REQUIRE(a && b, "level is NULL");
+  REQUIRE(a->ctx == ctx && b->ctx == ctx, "level belongs to another context");
+  REQUIRE(a->k == b->k, "levels have different wavenumbers");
+  REQUIRE(a->n_dirs == b->n_dirs, "levels have different incidence sets");
+  REQUIRE(a->field == b->field, "levels use different perturbation fields");
+}
+
+static void check_cov(const fosb_cov* cov) {
+  REQUIRE(cov, "cov is NULL");
+  REQUIRE(cov->kind >= FOSB_COV_GAUSSIAN && cov->kind <= FOSB_COV_NORMAL_DOT, "unknown covariance kind %d", cov->kind);
+  REQUIRE(std::isfinite(cov->sigma) && cov->sigma >= 0, "sigma must be >= 0");
+  if (cov->kind == FOSB_COV_GAUSSIAN || cov->kind == FOSB_COV_MATERN32)
+    REQUIRE(std::isfinite(cov->ell) && cov->ell > 0, "ell must be > 0");
+}
+
+fosb_status fosb_rhs_correlation(fosb_context* ctx, const fosb_level* l1, const fosb_level* l2, const fosb_cov* cov,
+                                 int64_t dir, void* C, int64_t ldc) {
+  API_BEGIN
+  REQUIRE(ctx && C, "ctx/C is NULL");
+  check_pair(ctx, l1, l2);
+  check_cov(cov);
+  REQUIRE(dir >= 0 && dir < l1->n_dirs, "dir out of range");
+  if (ldc < l2->n) fail(FOSB_E_WORKSPACE, "ldc < N2");
+  bind(*ctx);
+  rhs_correlation_kernel(ctx->stream, *l1, *l2, *cov, dir, static_cast<c128*>(C), ldc);
+  API_END
+}
+
+fosb_status fosb_two_sided_solve(fosb_context* ctx, const fosb_level* l1, const fosb_level* l2, void* C, int64_t ldc,
+                                 fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && C, "ctx/C is NULL");
+  check_pair(ctx, l1, l2);
+  if (ldc < l2->n) fail(FOSB_E_WORKSPACE, "ldc < N2");
+  bind(*ctx);
+  two_sided(*ctx, *l1, *l2, static_cast<c128*>(C), ldc, stats);
+  API_END
+}
+
+static std::vector<std::array<int32_t, 4>> ct_pairs_vec(int32_t L0, int32_t L) {
+  std::vector<std::array<int32_t, 4>> out;
+  const int32_t tots[2] = {L + L0, L + L0 - 1};
+  const int32_t sg[2] = {1, -1};
+  for (int q = 0; q < 2; ++q)
+    for (int32_t l1 = L; l1 >= L0; --l1) {
+      const int32_t l2 = tots[q] - l1;
+      if (l2 >= L0 && l2 <= l1) out.push_back({l1, l2, sg[q], l1 == l2 ? 1 : 2});
+    }
+  return out;
+}
+
+fosb_status fosb_ct_pairs(int32_t L0, int32_t L, int32_t* l1, int32_t* l2, int32_t* sign, int32_t* mult,
+                          int32_t* n_pairs) {
+  API_BEGIN
+  REQUIRE(L0 >= 0 && L >= L0 && L - L0 < 64, "need 0 <= L0 <= L < L0 + 64");
+  REQUIRE(n_pairs, "n_pairs is NULL");
+  auto v = ct_pairs_vec(L0, L);
+  *n_pairs = (int32_t)v.size();
+  for (size_t p = 0; p < v.size(); ++p) {
+    if (l1) l1[p] = v[p][0];
+    if (l2) l2[p] = v[p][1];
+    if (sign) sign[p] = v[p][2];
+    if (mult) mult[p] = v[p][3];
+  }
+  API_END
+}
+
+fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels, int32_t L0,
+                             int32_t L, const fosb_cov* cov, int64_t dir, void* const* blocks, const int64_t* ldb,
+                             fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && levels && blocks && ldb, "NULL argument");
+  REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  check_cov(cov);
+  for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
+  auto v = ct_pairs_vec(L0, L);
+  for (size_t p = 0; p < v.size(); ++p) {
+    REQUIRE(blocks[p], "block %zu is NULL", p);
+    if (ldb[p] < levels[v[p][1] - L0]->n) fail(FOSB_E_WORKSPACE, "ldb[%zu] < N_l2", p);
+  }
+  bind(*ctx);
+  for (size_t p = 0; p < v.size(); ++p) {
+    const fosb_level* a = levels[v[p][0] - L0];
+    const fosb_level* b = levels[v[p][1] - L0];
+    c128* C = static_cast<c128*>(blocks[p]);
+    {
+      ProfScope prof(*ctx, FOSB_K_RHS, 0.0, 16.0 * (double)a->n * (double)b->n);
+      rhs_correlation_kernel(ctx->stream, *a, *b, *cov, dir, C, ldb[p]);
+    }
+    two_sided(*ctx, *a, *b, C, ldb[p], stats);
+  }
+  API_END
+}
+
+fosb_status fosb_far_field_matrix(fosb_context* ctx, const fosb_level* level, const double* xhat, int64_t n_a,
+                                  void* FF) {
+  API_BEGIN
+  REQUIRE(ctx && level && xhat && FF, "NULL argument");
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  bind(*ctx);
+  std::vector<double> x(xhat, xhat + 3 * n_a);
+  DevBuf dx;
+  upload(dx, x, ctx->stream);
+  far_field_matrix_kernel(ctx->stream, *level->mesh, level->k, dx.as<double>(), n_a, static_cast<c128*>(FF));
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  API_END
+}
+
+fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels, int32_t L0,
+                                   int32_t L, void* const* blocks, const int64_t* ldb, const double* xhat,
+                                   int64_t n_a, int64_t dir, double* var, void* mean_F) {
+  API_BEGIN
+  REQUIRE(ctx && levels && blocks && ldb && xhat && var, "NULL argument");
+  REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
+  for (int64_t i = 0; i < n_a; ++i) {
+    double nn = xhat[3 * i] * xhat[3 * i] + xhat[3 * i + 1] * xhat[3 * i + 1] + xhat[3 * i + 2] * xhat[3 * i + 2];
+    REQUIRE(std::fabs(nn - 1.0) < 1e-9, "xhat[%lld] is not a unit vector", (long long)i);
+  }
+  auto v = ct_pairs_vec(L0, L);
+  for (size_t p = 0; p < v.size(); ++p) {
+    REQUIRE(blocks[p], "block %zu is NULL", p);
+    if (ldb[p] < levels[v[p][1] - L0]->n) fail(FOSB_E_WORKSPACE, "ldb[%zu] < N_l2", p);
+  }
+  bind(*ctx);
+  hipStream_t s = ctx->stream;
+  std::vector<double> x(xhat, xhat + 3 * n_a);
+  DevBuf dx;
+  upload(dx, x, s);
+  const int64_t rows = 3 * n_a;
+  std::vector<DevBuf> FF(n_levels);
+  for (int32_t i = 0; i < n_levels; ++i) {
+    FF[i].alloc((size_t)rows * levels[i]->n * sizeof(c128));
+    far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
+  }
+  FOSB_HIP(hipMemsetAsync(var, 0, rows * sizeof(double), s));
+  int64_t maxn2 = 0;
+  for (auto& q : v) maxn2 = std::max(maxn2, levels[q[1] - L0]->n);
+  DevBuf P((size_t)rows * maxn2 * sizeof(c128));
+  for (size_t p = 0; p < v.size(); ++p) {
+    const int i1 = v[p][0] - L0, i2 = v[p][1] - L0;
+    const int64_t n1 = levels[i1]->n, n2 = levels[i2]->n;
+    gemm<double>(*ctx, rows, n2, n1, 1.0, FF[i1].as<c128>(), n1, static_cast<const c128*>(blocks[p]), ldb[p], 0.0,
+                 P.as<c128>(), n2);
+    row_dot_re_accumulate(s, P.as<c128>(), FF[i2].as<c128>(), rows, n2, (double)(v[p][2] * v[p][3]), var);
+  }
+  if (mean_F) {
+    const int iL = n_levels - 1;
+    ctx->scratch[1].reserve((size_t)levels[iL]->n * sizeof(c128));
+    copy_c128(s, levels[iL]->u.as<c128>() + dir, levels[iL]->n_dirs, ctx->scratch[1].as<c128>(), 1, levels[iL]->n, 1);
+    matvec_rows(s, FF[iL].as<c128>(), rows, levels[iL]->n, ctx->scratch[1].as<c128>(), static_cast<c128*>(mean_F));
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+fosb_status fosb_profile_enable(fosb_context* ctx, int32_t on) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  bind(*ctx);
+  if (on) {
+    FOSB_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->recs.clear();
+  }
+  ctx->prof_on = on != 0;
+  API_END
+}
+
+fosb_status fosb_profile_read(fosb_context* ctx, int32_t cls, int64_t* launches, double* seconds, double* flops,
+                              double* bytes) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  REQUIRE(cls >= 0 && cls < FOSB_K_COUNT, "unknown kernel class %d", cls);
+  bind(*ctx);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  int64_t cnt = 0;
+  double sec = 0, fl = 0, by = 0;
+  for (const ProfRec& r : ctx->recs) {
+    if (r.cls != cls) continue;
+    float ms = 0.f;
+    FOSB_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[r.ev], ctx->ev_pool[r.ev + 1]));
+    ++cnt;
+    sec += 1e-3 * ms;
+    fl += r.flops;
+    by += r.bytes;
+  }
+  if (launches) *launches = cnt;
+  if (seconds) *seconds = sec;
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,346 @@
+// EFIE Galerkin assembly on RWG elements (FP64).
+//
+//   Z[m][n] = sum over the triangle pairs (T, T') of the supports of phi_m, phi_n of
+//     int_T int_T' G_k(x,y) [ -i k phi_m(x).phi_n(y) + (i/k) div phi_m div phi_n ]
+//
+// Every ordered triangle pair is integrated once ("unassembled" 3x3 block of the
+// three local RWG functions of each triangle); the blocks of a band of column
+// triangles are written to a scratch matrix Zc (3 nt rows x 3 band columns) and
+// then gathered onto the RWG indices.  The gather writes each Z entry from a
+// fixed-order sum (store on the band of the edge's T+, add on the band of its T-
+// when that lies in a later band), so results are deterministic.
+//
+// Per triangle pair the integrand is reduced to eight moments (relative to the
+// two centroids c, c'):
+//   I0 = sum w w' G,  Ix = sum w w' G x~,  Iy = sum w w' G y~,  Ixy = sum w w' G x~.y~
+// because phi_a(x).phi_b(y) = (alpha_a beta_b / 4) (x~ - P~_a).(y~ - Q~_b) and
+// div phi_a = alpha_a, alpha_a = sign * length / area of local RWG a.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace fosb {
+
+struct Rule6 {
+  double l[6][3];
+  double w[6];
+};
+
+static constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
+
+__device__ __forceinline__ void write_local_block(const MeshDev& md, int i, int j, int jj, double k,
+                                                  const double Li[3][3], const double Lj[3][3], double I0r,
+                                                  double I0i, const double Ixr[3], const double Ixi[3],
+                                                  const double Iyr[3], const double Iyi[3], double Ixyr,
+                                                  double Ixyi, c128* __restrict__ Zc, int64_t ldc) {
+  const int nt = md.nt;
+  const double ik = 1.0 / k;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double al = md.alpha[a * nt + i];
+    const double Pa0 = Li[a][0], Pa1 = Li[a][1], Pa2 = Li[a][2];
+    const double PIyr = Pa0 * Iyr[0] + Pa1 * Iyr[1] + Pa2 * Iyr[2];
+    const double PIyi = Pa0 * Iyi[0] + Pa1 * Iyi[1] + Pa2 * Iyi[2];
+    c128* row = Zc + (int64_t)(3 * i + a) * ldc + 3 * jj;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double be = md.alpha[b * nt + j];
+      const double Qb0 = Lj[b][0], Qb1 = Lj[b][1], Qb2 = Lj[b][2];
+      const double PQ = Pa0 * Qb0 + Pa1 * Qb1 + Pa2 * Qb2;
+      const double Mr = Ixyr - (Ixr[0] * Qb0 + Ixr[1] * Qb1 + Ixr[2] * Qb2) - PIyr + PQ * I0r;
+      const double Mi = Ixyi - (Ixi[0] * Qb0 + Ixi[1] * Qb1 + Ixi[2] * Qb2) - PIyi + PQ * I0i;
+      // -i k M / 4 + (i / k) I0
+      const double zr = 0.25 * k * Mi - I0i * ik;
+      const double zi = -0.25 * k * Mr + I0r * ik;
+      const double sc = al * be;
+      row[b] = c128{zr * sc, zi * sc};
+    }
+  }
+}
+
+__device__ __forceinline__ void load_tri(const MeshDev& md, int t, double P[3][3], double c[3]) {
+  const int nt = md.nt;
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) P[v][q] = md.vtx[(v * 3 + q) * nt + t];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) c[q] = (P[0][q] + P[1][q] + P[2][q]) * (1.0 / 3.0);
+}
+
+// One thread per ordered non-touching triangle pair (i, j0 + jj).
+__global__ __launch_bounds__(256) void k_assemble_regular(MeshDev md, Rule6 R, double k, int j0, int jc,
+                                                          c128* __restrict__ Zc, int64_t ldc) {
+  const int jj = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (jj >= jc || i >= md.nt) return;
+  const int j = j0 + jj;
+  const int nt = md.nt;
+  {
+    const int a0 = md.fv[i], a1 = md.fv[nt + i], a2 = md.fv[2 * nt + i];
+    const int b0 = md.fv[j], b1 = md.fv[nt + j], b2 = md.fv[2 * nt + j];
+    if (a0 == b0 || a0 == b1 || a0 == b2 || a1 == b0 || a1 == b1 || a1 == b2 || a2 == b0 || a2 == b1 ||
+        a2 == b2)
+      return;  // touching pair: integrated by the singular kernel
+  }
+  double Pi[3][3], Pj[3][3], ci[3], cj[3];
+  load_tri(md, i, Pi, ci);
+  load_tri(md, j, Pj, cj);
+  double Li[3][3], Lj[3][3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      Li[v][q] = Pi[v][q] - ci[q];
+      Lj[v][q] = Pj[v][q] - cj[q];
+    }
+  const double Ai = md.area[i], Aj = md.area[j];
+  double yq[6][3], wq[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) yq[q][c] = R.l[q][0] * Lj[0][c] + R.l[q][1] * Lj[1][c] + R.l[q][2] * Lj[2][c];
+    wq[q] = R.w[q] * Aj * kInv4Pi;
+  }
+  const double dc0 = ci[0] - cj[0], dc1 = ci[1] - cj[1], dc2 = ci[2] - cj[2];
+  double I0r = 0, I0i = 0, Ixyr = 0, Ixyi = 0;
+  double Ixr[3] = {0, 0, 0}, Ixi[3] = {0, 0, 0}, Iyr[3] = {0, 0, 0}, Iyi[3] = {0, 0, 0};
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    double xp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xp[c] = R.l[p][0] * Li[0][c] + R.l[p][1] * Li[1][c] + R.l[p][2] * Li[2][c];
+    const double wp = R.w[p] * Ai;
+    const double e0 = xp[0] + dc0, e1 = xp[1] + dc1, e2 = xp[2] + dc2;
+    double Sr = 0, Si = 0, Syr[3] = {0, 0, 0}, Syi[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double d0 = e0 - yq[q][0], d1 = e1 - yq[q][1], d2 = e2 - yq[q][2];
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double ir = rsqrt(r2);
+      const double r = r2 * ir;
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      const double g = wq[q] * ir;
+      const double gr = cs * g, gi = sn * g;
+      Sr += gr;
+      Si += gi;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Syr[c] += gr * yq[q][c];
+        Syi[c] += gi * yq[q][c];
+      }
+    }
+    I0r += wp * Sr;
+    I0i += wp * Si;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Ixr[c] += wp * Sr * xp[c];
+      Ixi[c] += wp * Si * xp[c];
+      Iyr[c] += wp * Syr[c];
+      Iyi[c] += wp * Syi[c];
+    }
+    Ixyr += wp * (xp[0] * Syr[0] + xp[1] * Syr[1] + xp[2] * Syr[2]);
+    Ixyi += wp * (xp[0] * Syi[0] + xp[1] * Syi[1] + xp[2] * Syi[2]);
+  }
+  write_local_block(md, i, j, jj, k, Li, Lj, I0r, I0i, Ixr, Ixi, Iyr, Iyi, Ixyr, Ixyi, Zc, ldc);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wavefront per touching ordered pair; lanes stride over the Sauter-Schwab points.
+__global__ __launch_bounds__(256) void k_assemble_singular(MeshDev md, const int32_t* __restrict__ tp_i,
+                                                           const int32_t* __restrict__ tp_j,
+                                                           const int32_t* __restrict__ tp_kind,
+                                                           const int32_t* __restrict__ tp_ord, int pbeg, int pend,
+                                                           const double* __restrict__ ss, int off0, int off1,
+                                                           int off2, int cnt0, int cnt1, int cnt2, double k, int j0,
+                                                           c128* __restrict__ Zc, int64_t ldc) {
+  const int p = pbeg + blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= pend) return;
+  const int i = tp_i[p], j = tp_j[p], kind = tp_kind[p];
+  const int* ord = tp_ord + 6 * p;
+  double Pi[3][3], Pj[3][3], ci[3], cj[3];
+  load_tri(md, i, Pi, ci);
+  load_tri(md, j, Pj, cj);
+  double Li[3][3], Lj[3][3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      Li[v][q] = Pi[v][q] - ci[q];
+      Lj[v][q] = Pj[v][q] - cj[q];
+    }
+  // Sauter-Schwab vertex order (local coordinates)
+  double S0[3], S1[3], S2[3], T0[3], T1[3], T2[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    S0[q] = Li[ord[0]][q]; S1[q] = Li[ord[1]][q] - Li[ord[0]][q]; S2[q] = Li[ord[2]][q] - Li[ord[1]][q];
+    T0[q] = Lj[ord[3]][q]; T1[q] = Lj[ord[4]][q] - Lj[ord[3]][q]; T2[q] = Lj[ord[5]][q] - Lj[ord[4]][q];
+  }
+  const double jac = 4.0 * md.area[i] * md.area[j] * kInv4Pi;
+  const double dc0 = ci[0] - cj[0], dc1 = ci[1] - cj[1], dc2 = ci[2] - cj[2];
+  const int off = kind == 0 ? off0 : (kind == 1 ? off1 : off2);
+  const int cnt = kind == 0 ? cnt0 : (kind == 1 ? cnt1 : cnt2);
+  double I0r = 0, I0i = 0, Ixyr = 0, Ixyi = 0;
+  double Ixr[3] = {0, 0, 0}, Ixi[3] = {0, 0, 0}, Iyr[3] = {0, 0, 0}, Iyi[3] = {0, 0, 0};
+  for (int m = lane; m < cnt; m += 64) {
+    const double* pt = ss + 5 * (int64_t)(off + m);
+    const double x1 = pt[0], x2 = pt[1], y1 = pt[2], y2 = pt[3], w = pt[4];
+    double x[3], y[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      x[q] = S0[q] + x1 * S1[q] + x2 * S2[q];
+      y[q] = T0[q] + y1 * T1[q] + y2 * T2[q];
+    }
+    const double d0 = x[0] - y[0] + dc0, d1 = x[1] - y[1] + dc1, d2 = x[2] - y[2] + dc2;
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const double g = w * jac * ir;
+    const double gr = cs * g, gi = sn * g;
+    I0r += gr;
+    I0i += gi;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      Ixr[q] += gr * x[q];
+      Ixi[q] += gi * x[q];
+      Iyr[q] += gr * y[q];
+      Iyi[q] += gi * y[q];
+    }
+    const double xy = x[0] * y[0] + x[1] * y[1] + x[2] * y[2];
+    Ixyr += gr * xy;
+    Ixyi += gi * xy;
+  }
+  I0r = wave_sum(I0r);
+  I0i = wave_sum(I0i);
+  Ixyr = wave_sum(Ixyr);
+  Ixyi = wave_sum(Ixyi);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    Ixr[q] = wave_sum(Ixr[q]);
+    Ixi[q] = wave_sum(Ixi[q]);
+    Iyr[q] = wave_sum(Iyr[q]);
+    Iyi[q] = wave_sum(Iyi[q]);
+  }
+  if (lane == 0) write_local_block(md, i, j, j - j0, k, Li, Lj, I0r, I0i, Ixr, Ixi, Iyr, Iyi, Ixyr, Ixyi, Zc, ldc);
+}
+
+// Z[m][n] for the columns n listed for this band: sum of the (up to) four local
+// blocks of the band; store when the band holds T+ of n, add otherwise.
+__global__ __launch_bounds__(256) void k_assemble_gather(int ne, const int32_t* __restrict__ edge_tri,
+                                                         const int32_t* __restrict__ edge_loc, int j0, int j1,
+                                                         const int32_t* __restrict__ cols, int ncols,
+                                                         const c128* __restrict__ Zc, int64_t ldc,
+                                                         c128* __restrict__ Z, int64_t ldz) {
+  const int ci = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (ci >= ncols || m >= ne) return;
+  const int n = cols[ci];
+  const int tp = edge_tri[n], tm = edge_tri[ne + n];
+  const int64_t rp = 3 * (int64_t)edge_tri[m] + edge_loc[m];
+  const int64_t rm = 3 * (int64_t)edge_tri[ne + m] + edge_loc[ne + m];
+  double sr = 0.0, si = 0.0;
+  const bool has_p = tp >= j0 && tp < j1;
+  if (has_p) {
+    const int64_t c = 3 * (int64_t)(tp - j0) + edge_loc[n];
+    const c128 u = Zc[rp * ldc + c], v = Zc[rm * ldc + c];
+    sr += u.re + v.re;
+    si += u.im + v.im;
+  }
+  if (tm >= j0 && tm < j1) {
+    const int64_t c = 3 * (int64_t)(tm - j0) + edge_loc[ne + n];
+    const c128 u = Zc[rp * ldc + c], v = Zc[rm * ldc + c];
+    sr += u.re + v.re;
+    si += u.im + v.im;
+  }
+  c128* z = Z + (int64_t)m * ldz + n;
+  if (has_p) {
+    *z = c128{sr, si};
+  } else {
+    c128 o = *z;
+    *z = c128{o.re + sr, o.im + si};
+  }
+}
+
+static void ensure_ss_table(Context& ctx, int n) {
+  if (ctx.ss[n].p) return;
+  std::vector<double> all, part;
+  for (int kind = 0; kind < 3; ++kind) {
+    sauter_schwab_points(kind, n, part);
+    ctx.ss_off[n][kind] = (int)(all.size() / 5);
+    ctx.ss_cnt[n][kind] = (int)(part.size() / 5);
+    all.insert(all.end(), part.begin(), part.end());
+  }
+  upload(ctx.ss[n], all, ctx.stream);
+  FOSB_HIP(hipStreamSynchronize(ctx.stream));
+}
+
+void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz) {
+  hipStream_t s = ctx.stream;
+  const MeshHost& h = m.h;
+  const int nt = (int)h.nt, ne = (int)h.ne;
+  ensure_ss_table(ctx, n_gauss);
+  Rule6 R;
+  rule6(R.l, R.w);
+  // band width: scratch Zc of 3nt x 3jc complex128 limited to ~512 MB
+  const int64_t budget = (int64_t)512 << 20;
+  int jc = (int)std::max<int64_t>(1, std::min<int64_t>(nt, budget / (9LL * nt * (int64_t)sizeof(c128))));
+  if (jc < nt) jc = std::max(64, jc / 64 * 64);
+  jc = std::min(jc, nt);
+  const int64_t ldc = 3LL * jc;
+  ctx.scratch[0].reserve((size_t)(3LL * nt) * ldc * sizeof(c128));
+  c128* Zc = ctx.scratch[0].as<c128>();
+  // column lists per band (host): edges whose T+ or T- lies in the band
+  std::vector<int32_t> cols;
+  std::vector<int64_t> cbeg;
+  for (int j0 = 0; j0 < nt; j0 += jc) {
+    const int j1 = std::min(nt, j0 + jc);
+    cbeg.push_back((int64_t)cols.size());
+    for (int e = 0; e < ne; ++e) {
+      int tp = h.edge_tri[2 * e], tm = h.edge_tri[2 * e + 1];
+      if ((tp >= j0 && tp < j1) || (tm >= j0 && tm < j1)) cols.push_back(e);
+    }
+  }
+  cbeg.push_back((int64_t)cols.size());
+  DevBuf dcols;
+  upload(dcols, cols, s);
+  const MeshDev md = m.dev();
+  int band = 0;
+  for (int j0 = 0; j0 < nt; j0 += jc, ++band) {
+    const int j1 = std::min(nt, j0 + jc);
+    const int w = j1 - j0;
+    dim3 g1((w + 63) / 64, (nt + 3) / 4);
+    hipLaunchKernelGGL(k_assemble_regular, g1, dim3(256), 0, s, md, R, k, j0, w, Zc, ldc);
+    FOSB_LAUNCH_CHECK();
+    const int pb = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j0) - h.tp_j.begin());
+    const int pe = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j1) - h.tp_j.begin());
+    if (pe > pb) {
+      dim3 g2((pe - pb + 3) / 4);
+      hipLaunchKernelGGL(k_assemble_singular, g2, dim3(256), 0, s, md, m.tp_i.as<int32_t>(), m.tp_j.as<int32_t>(),
+                         m.tp_kind.as<int32_t>(), m.tp_ord.as<int32_t>(), pb, pe, ctx.ss[n_gauss].as<double>(),
+                         ctx.ss_off[n_gauss][0], ctx.ss_off[n_gauss][1], ctx.ss_off[n_gauss][2],
+                         ctx.ss_cnt[n_gauss][0], ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], k, j0, Zc, ldc);
+      FOSB_LAUNCH_CHECK();
+    }
+    const int nc = (int)(cbeg[band + 1] - cbeg[band]);
+    if (nc > 0) {
+      dim3 g3((nc + 63) / 64, (ne + 3) / 4);
+      hipLaunchKernelGGL(k_assemble_gather, g3, dim3(256), 0, s, ne, md.edge_tri, md.edge_loc, j0, j1,
+                         dcols.as<int32_t>() + cbeg[band], nc, Zc, ldc, Z, ldz);
+      FOSB_LAUNCH_CHECK();
+    }
+  }
+  // dcols must live until the kernels ran
+  FOSB_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace fosb

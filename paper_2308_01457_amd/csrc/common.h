@@ -1,0 +1,245 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fosb.h"
+
+namespace fosb {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  fosb_status status;
+  Error(fosb_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] void fail(fosb_status s, const char* fmt, ...);
+void set_last_error(const std::string& msg);
+
+#define FOSB_HIP(call)                                                                         \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      ::fosb::fail(e_ == hipErrorOutOfMemory ? FOSB_E_OOM : FOSB_E_DEVICE, "%s failed: %s (%s:%d)", \
+                   #call, hipGetErrorString(e_), __FILE__, __LINE__);                          \
+  } while (0)
+
+#define FOSB_LAUNCH_CHECK() FOSB_HIP(hipGetLastError())
+
+// ------------------------------------------------------------------ complex storage
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T re, im;
+};
+using c128 = cplx<double>;
+using c64 = cplx<float>;
+
+// ------------------------------------------------------------------ device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    FOSB_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  // grow-only reallocation (contents are not preserved)
+  void reserve(size_t n) { if (n > bytes) alloc(n); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+inline void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  b.alloc(v.size() * sizeof(T));
+  if (!v.empty()) FOSB_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ------------------------------------------------------------------ profiling records
+struct ProfRec {
+  int cls;
+  int ev;          // index of the start event in the pool (stop = ev + 1)
+  double flops, bytes;
+};
+
+// ------------------------------------------------------------------ context
+struct Context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 256;
+  size_t max_lds = 65536;
+  // reusable scratch (grow-only); each user documents which slot it uses
+  DevBuf scratch[6];
+  DevBuf counters;    // int32 tree counters for panel factorisation
+  DevBuf small;       // small per-panel buffers
+  // Sauter-Schwab point tables per Gauss order n (1..12): 5 doubles per point,
+  // kinds 0/1/2 concatenated; offsets and counts in points.
+  DevBuf norms;       // 2 doubles for refinement norms
+  DevBuf ss[13];
+  int ss_off[13][3] = {};
+  int ss_cnt[13][3] = {};
+  // profiler (fosb_profile_*): event pool and records of the current session
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfRec> recs;
+  ~Context();
+};
+
+// Brackets the launches issued during its lifetime with a pair of events when
+// the context's profiler is on.
+struct ProfScope {
+  Context& ctx;
+  int idx = -1;
+  ProfScope(Context& c, int cls, double flops, double bytes);
+  ~ProfScope();
+};
+
+// ------------------------------------------------------------------ mesh
+struct MeshHost {
+  int64_t nv = 0, nt = 0, ne = 0;
+  std::vector<double> V;           // nv*3
+  std::vector<int32_t> F;          // nt*3
+  std::vector<double> area;        // nt
+  std::vector<double> normal;      // nt*3
+  std::vector<int32_t> tri_edge;   // nt*3
+  std::vector<double> tri_sign;    // nt*3
+  std::vector<double> edge_len;    // ne
+  std::vector<int32_t> edge_tri;   // ne*2 (T+, T-)
+  std::vector<int32_t> edge_loc;   // ne*2
+  // touching ordered pairs (i, j), sorted by j then i
+  std::vector<int32_t> tp_i, tp_j, tp_kind;   // kind: 0 identical, 1 edge, 2 vertex
+  std::vector<int32_t> tp_ord;                // 6 per pair: local slots of (P0,P1,P2) in i, then in j
+};
+
+// Structure-of-arrays device view of a mesh (passed by value to kernels).
+struct MeshDev {
+  int nt, ne;
+  const double* vtx;      // [9][nt]: component (v*3+c) of triangle t at vtx[(v*3+c)*nt + t]
+  const double* area;     // [nt]
+  const double* nrm;      // [3][nt]
+  const double* alpha;    // [3][nt]: sign * edge length / area of local RWG a
+  const int32_t* fv;      // [3][nt] vertex ids
+  const int32_t* tri_edge;// [3][nt]
+  const int32_t* edge_tri;// [2][ne]
+  const int32_t* edge_loc;// [2][ne]
+};
+
+struct Mesh {
+  Context* ctx = nullptr;
+  MeshHost h;
+  DevBuf vtx, area, nrm, alpha, fv, tri_edge, edge_tri, edge_loc;
+  DevBuf tp_i, tp_j, tp_kind, tp_ord;
+  MeshDev dev() const {
+    return MeshDev{(int)h.nt, (int)h.ne, vtx.as<double>(), area.as<double>(), nrm.as<double>(),
+                   alpha.as<double>(), fv.as<int32_t>(), tri_edge.as<int32_t>(),
+                   edge_tri.as<int32_t>(), edge_loc.as<int32_t>()};
+  }
+};
+
+void mesh_build_host(const double* V, int64_t nv, const int32_t* F, int64_t nt, MeshHost& out);
+void mesh_touching_pairs(MeshHost& m);
+void mesh_upload(Mesh& m);
+
+// ------------------------------------------------------------------ quadrature (host-built tables)
+// 6-point degree-4 rule: barycentric coordinates (6x3) and weights (6), per unit area.
+void rule6(double bary[6][3], double w[6]);
+// Gauss-Legendre on [0,1].
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
+// Sauter-Schwab points for kind 0/1/2: xhat (2 per point), yhat (2 per point), weight.
+void sauter_schwab_points(int kind, int n, std::vector<double>& pts /* 5 per point: x1,x2,y1,y2,w */);
+
+// ------------------------------------------------------------------ level
+struct Level {
+  Context* ctx = nullptr;
+  const Mesh* mesh = nullptr;
+  double k = 1.0;
+  int precision = FOSB_PREC_FP64;
+  int64_t n = 0;
+  void* Z = nullptr;        // FP64: LU factors; MIXED: the FP64 matrix (read-only)
+  int64_t ldz = 0;
+  void* Zlow = nullptr;     // MIXED: complex64 LU factors
+  int64_t ldzlow = 0;
+  int64_t n_dirs = 0;
+  int field = FOSB_FIELD_RADIAL;
+  fosb_opts opts{};
+  std::vector<int32_t> perm;   // host: row permutation (position i holds original row perm[i])
+  DevBuf d_perm;               // int32 [n]
+  DevBuf dinv_L, dinv_U;       // inverted nb x nb diagonal blocks of L and U (LU precision)
+  DevBuf u;                    // c128 [n_dirs][n]
+  DevBuf W;                    // c128 [n_dirs][nt][3][6] RHS weights
+  DevBuf qx;                   // double [3][6*nt] quadrature nodes (component-major)
+  const void* lu() const { return precision == FOSB_PREC_FP64 ? Z : Zlow; }
+};
+
+constexpr int kPanel = 32;   // LU panel width / TRSM diagonal block size
+
+// ------------------------------------------------------------------ kernels (host launchers)
+// assemble.hip
+void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz);
+// gemm.hip: C = beta*C + alpha*A*B, complex, row-major.
+template <typename T>
+void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
+          const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc);
+// lu.hip
+template <typename T>
+int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
+                  std::vector<int32_t>& perm);
+template <typename T>
+void trsm_lower_unit(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0,
+                     int64_t n, cplx<T>* B, int64_t ldb, int64_t nrhs);
+template <typename T>
+void trsm_upper(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvU, int64_t k0, int64_t n,
+                cplx<T>* B, int64_t ldb, int64_t nrhs);
+void permute_rows_gather(hipStream_t s, const int32_t* perm, const c128* src, int64_t lds, c128* dst,
+                         int64_t ldd, int64_t n, int64_t ncols);
+void copy_c128_to_c64(hipStream_t s, const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int64_t cols);
+void copy_c64_to_c128(hipStream_t s, const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int64_t cols);
+void copy_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int64_t cols);
+void conj_transpose_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows,
+                         int64_t cols);
+void axpy_c128(hipStream_t s, const c128* x, int64_t ldx, c128* y, int64_t ldy, int64_t rows, int64_t cols);
+// squared Frobenius norms of x and of y (two doubles written to out, device)
+void norms2_c128(hipStream_t s, const c128* x, int64_t ldx, const c128* y, int64_t ldy, int64_t rows,
+                 int64_t cols, double* out);
+// uq.hip
+// b[m * ndir + d] = -int p_d exp(i k d_d . x) . phi_m  (dirs/pols: device, ndir x 3)
+void incident_rhs(hipStream_t s, const Mesh& m, double k, const double* dirs_dev, const double* pols_dev, int ndir,
+                  c128* b);
+void quad_nodes(hipStream_t s, const Mesh& m, double* qx);
+// u: first-moment coefficients of one direction, u[e * ustride]
+void rhs_weights(hipStream_t s, const Mesh& m, double k, int field, const c128* u, int64_t ustride, c128* W);
+void rhs_correlation_kernel(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t dir,
+                            c128* C, int64_t ldc);
+void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a,
+                             c128* FF);
+void row_dot_re_accumulate(hipStream_t s, const c128* P, const c128* FF2, int64_t rows, int64_t n, double scale,
+                           double* var);
+void matvec_rows(hipStream_t s, const c128* FF, int64_t rows, int64_t n, const c128* u, c128* out);
+
+// level-wide solves (api.cpp helpers)
+void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st);
+
+}  // namespace fosb

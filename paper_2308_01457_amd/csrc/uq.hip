@@ -1,0 +1,364 @@
+// Right-hand sides, shape-derivative weights, RHS correlation and far-field
+// kernels (FP64).
+//
+// On triangle t the RWG function of local edge a is phi = (alpha_a / 2)(x - P_a)
+// with alpha_a = sign * length / area (sign +1 on T+, -1 on T-) and P_a the
+// vertex opposite the edge; div phi = alpha_a.  All surface integrals use the
+// symmetric 6-point rule.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace fosb {
+
+struct Rule6Q {
+  double l[6][3];
+  double w[6];
+};
+
+static Rule6Q make_rule() {
+  Rule6Q r;
+  rule6(r.l, r.w);
+  return r;
+}
+
+__device__ __forceinline__ void tri_vertices(const MeshDev& md, int t, double P[3][3]) {
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) P[v][c] = md.vtx[(v * 3 + c) * md.nt + t];
+}
+
+// b[dir][m] = -int p exp(i k d.x) . phi_m(x) dx
+__global__ void k_incident_rhs(MeshDev md, Rule6Q R, double k, const double* __restrict__ dirs,
+                               const double* __restrict__ pols, int ndir, c128* __restrict__ b) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int dr = blockIdx.y;
+  if (m >= md.ne || dr >= ndir) return;
+  const double d0 = dirs[3 * dr], d1 = dirs[3 * dr + 1], d2 = dirs[3 * dr + 2];
+  const double p0 = pols[3 * dr], p1 = pols[3 * dr + 1], p2 = pols[3 * dr + 2];
+  double sr = 0, si = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int t = md.edge_tri[side * md.ne + m];
+    const int a = md.edge_loc[side * md.ne + m];
+    double P[3][3];
+    tri_vertices(md, t, P);
+    const double half_alpha = 0.5 * md.alpha[a * md.nt + t];
+    const double At = md.area[t];
+    for (int q = 0; q < 6; ++q) {
+      double x[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x[c] = R.l[q][0] * P[0][c] + R.l[q][1] * P[1][c] + R.l[q][2] * P[2][c];
+      double sn, cs;
+      sincos(k * (d0 * x[0] + d1 * x[1] + d2 * x[2]), &sn, &cs);
+      const double pdot = p0 * (x[0] - P[a][0]) + p1 * (x[1] - P[a][1]) + p2 * (x[2] - P[a][2]);
+      const double f = R.w[q] * At * half_alpha * pdot;
+      sr += f * cs;
+      si += f * sn;
+    }
+  }
+  b[(int64_t)m * ndir + dr] = c128{-sr, -si};
+}
+
+void incident_rhs(hipStream_t s, const Mesh& m, double k, const double* dirs_dev, const double* pols_dev, int ndir,
+                  c128* b) {
+  dim3 g((unsigned)((m.h.ne + 255) / 256), (unsigned)ndir);
+  hipLaunchKernelGGL(k_incident_rhs, g, dim3(256), 0, s, m.dev(), make_rule(), k, dirs_dev, pols_dev, ndir, b);
+  FOSB_LAUNCH_CHECK();
+}
+
+// qx[c][6t + q]: physical 6-point nodes
+__global__ void k_quad_nodes(MeshDev md, Rule6Q R, double* __restrict__ qx) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= md.nt) return;
+  double P[3][3];
+  tri_vertices(md, t, P);
+  const int64_t Q = 6LL * md.nt;
+  for (int q = 0; q < 6; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      qx[c * Q + 6LL * t + q] = R.l[q][0] * P[0][c] + R.l[q][1] * P[1][c] + R.l[q][2] * P[2][c];
+}
+
+void quad_nodes(hipStream_t s, const Mesh& m, double* qx) {
+  hipLaunchKernelGGL(k_quad_nodes, dim3((unsigned)((m.h.nt + 255) / 256)), dim3(256), 0, s, m.dev(), make_rule(),
+                     qx);
+  FOSB_LAUNCH_CHECK();
+}
+
+// Shape-derivative RHS weights (FOA section, PEC shape derivative with
+// E_n = (i/k) div j and gamma_T H = n x j):
+//   W[t][a][q] = w_q A_t nu(x_q) [ (i/k) div j(t) div phi_a - i k j(x_q) . phi_a(x_q) ]
+// nu = (x/|x|).n for the radial field, 1 for the normal field.
+__global__ void k_rhs_weights(MeshDev md, Rule6Q R, double k, int field, const c128* __restrict__ u,
+                              int64_t ustride, c128* __restrict__ W) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= md.nt) return;
+  const int nt = md.nt;
+  double P[3][3];
+  tri_vertices(md, t, P);
+  double al[3];
+  c128 ue[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    al[b] = md.alpha[b * nt + t];
+    ue[b] = u[(int64_t)md.tri_edge[b * nt + t] * ustride];
+  }
+  double djr = 0, dji = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    djr += ue[b].re * al[b];
+    dji += ue[b].im * al[b];
+  }
+  const double n0 = md.nrm[t], n1 = md.nrm[nt + t], n2 = md.nrm[2 * nt + t];
+  const double At = md.area[t];
+  for (int q = 0; q < 6; ++q) {
+    double x[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[c] = R.l[q][0] * P[0][c] + R.l[q][1] * P[1][c] + R.l[q][2] * P[2][c];
+    double nu = 1.0;
+    if (field == FOSB_FIELD_RADIAL) {
+      const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      nu = (x[0] * n0 + x[1] * n1 + x[2] * n2) / r;
+    }
+    // j(x) = sum_b u_b (alpha_b / 2)(x - P_b)
+    double jr[3] = {0, 0, 0}, ji[3] = {0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double ph = 0.5 * al[b] * (x[c] - P[b][c]);
+        jr[c] += ue[b].re * ph;
+        ji[c] += ue[b].im * ph;
+      }
+    const double wq = R.w[q] * At * nu;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double dr = 0, di = 0;  // j . phi_a
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double ph = 0.5 * al[a] * (x[c] - P[a][c]);
+        dr += jr[c] * ph;
+        di += ji[c] * ph;
+      }
+      // (i/k) divj alpha_a - i k (j.phi_a)
+      const double re = -dji * al[a] / k + k * di;
+      const double im = djr * al[a] / k - k * dr;
+      W[((int64_t)t * 3 + a) * 6 + q] = c128{wq * re, wq * im};
+    }
+  }
+}
+
+void rhs_weights(hipStream_t s, const Mesh& m, double k, int field, const c128* u, int64_t ustride, c128* W) {
+  hipLaunchKernelGGL(k_rhs_weights, dim3((unsigned)((m.h.nt + 255) / 256)), dim3(256), 0, s, m.dev(), make_rule(), k,
+                     field, u, ustride, W);
+  FOSB_LAUNCH_CHECK();
+}
+
+// C[m][n] = sum_{q in supp m} sum_{q' in supp n} W1[m,q] K(x_q, y_q') conj(W2[n,q'])
+// one thread per entry; the 12 nodes and weights of each row/column RWG are
+// staged in LDS (16 x 16 entries per block).
+struct CovParams {
+  int kind;
+  double s2;       // sigma^2
+  double inv2l2;   // 1 / (2 ell^2)
+  double s3l;      // sqrt(3) / ell
+};
+
+__device__ __forceinline__ double cov_eval(const CovParams& cp, double r2, double ndot) {
+  switch (cp.kind) {
+    case FOSB_COV_GAUSSIAN: return cp.s2 * exp(-r2 * cp.inv2l2);
+    case FOSB_COV_MATERN32: {
+      const double a = sqrt(r2) * cp.s3l;
+      return cp.s2 * (1.0 + a) * exp(-a);
+    }
+    case FOSB_COV_CONSTANT: return cp.s2;
+    default: return cp.s2 * ndot;
+  }
+}
+
+struct EdgeSide {
+  const int32_t* edge_tri;
+  const int32_t* edge_loc;
+  const double* nrm;
+  const double* qx;
+  const c128* W;
+  int ne, nt;
+};
+
+__device__ void stage_edge(const EdgeSide& L, int e, double (*x)[3], c128* w, double (*nn)[3]) {
+  // 12 nodes: 6 on T+ then 6 on T-
+  const int64_t Q = 6LL * L.nt;
+  for (int side = 0; side < 2; ++side) {
+    const int t = L.edge_tri[side * L.ne + e];
+    const int a = L.edge_loc[side * L.ne + e];
+    for (int q = 0; q < 6; ++q) {
+      const int64_t id = 6LL * t + q;
+      x[side * 6 + q][0] = L.qx[id];
+      x[side * 6 + q][1] = L.qx[Q + id];
+      x[side * 6 + q][2] = L.qx[2 * Q + id];
+      w[side * 6 + q] = L.W[((int64_t)t * 3 + a) * 6 + q];
+    }
+    nn[side][0] = L.nrm[t];
+    nn[side][1] = L.nrm[L.nt + t];
+    nn[side][2] = L.nrm[2 * L.nt + t];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rhs_correlation(EdgeSide A, EdgeSide B, CovParams cp, c128* __restrict__ C,
+                                                         int64_t ldc) {
+  __shared__ double xa[16][12][3], xb[16][12][3];
+  __shared__ c128 wa[16][12], wb[16][12];
+  __shared__ double na[16][2][3], nb[16][2][3];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
+  if (threadIdx.x < 16) {
+    const int e = m0 + threadIdx.x;
+    if (e < A.ne) stage_edge(A, e, xa[threadIdx.x], wa[threadIdx.x], na[threadIdx.x]);
+  } else if (threadIdx.x < 32) {
+    const int r = threadIdx.x - 16;
+    const int e = n0 + r;
+    if (e < B.ne) stage_edge(B, e, xb[r], wb[r], nb[r]);
+  }
+  __syncthreads();
+  const int m = m0 + ty, n = n0 + tx;
+  if (m >= A.ne || n >= B.ne) return;
+  double cr = 0, ci = 0;
+  for (int q = 0; q < 12; ++q) {
+    const double x0 = xa[ty][q][0], x1 = xa[ty][q][1], x2 = xa[ty][q][2];
+    const double* nx = na[ty][q / 6];
+    double ar = 0, ai = 0;  // sum_q' K conj(W2)
+#pragma unroll 4
+    for (int p = 0; p < 12; ++p) {
+      const double d0 = x0 - xb[tx][p][0], d1 = x1 - xb[tx][p][1], d2 = x2 - xb[tx][p][2];
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double* ny = nb[tx][p / 6];
+      const double kv = cov_eval(cp, r2, nx[0] * ny[0] + nx[1] * ny[1] + nx[2] * ny[2]);
+      ar += kv * wb[tx][p].re;
+      ai -= kv * wb[tx][p].im;
+    }
+    const c128 w = wa[ty][q];
+    cr += w.re * ar - w.im * ai;
+    ci += w.re * ai + w.im * ar;
+  }
+  C[(int64_t)m * ldc + n] = c128{cr, ci};
+}
+
+void rhs_correlation_kernel(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t dir,
+                            c128* C, int64_t ldc) {
+  const Mesh& m1 = *l1.mesh;
+  const Mesh& m2 = *l2.mesh;
+  EdgeSide A{m1.edge_tri.as<int32_t>(), m1.edge_loc.as<int32_t>(), m1.nrm.as<double>(), l1.qx.as<double>(),
+             l1.W.as<c128>() + dir * m1.h.nt * 18, (int)m1.h.ne, (int)m1.h.nt};
+  EdgeSide B{m2.edge_tri.as<int32_t>(), m2.edge_loc.as<int32_t>(), m2.nrm.as<double>(), l2.qx.as<double>(),
+             l2.W.as<c128>() + dir * m2.h.nt * 18, (int)m2.h.ne, (int)m2.h.nt};
+  CovParams cp;
+  cp.kind = cov.kind;
+  cp.s2 = cov.sigma * cov.sigma;
+  cp.inv2l2 = cov.ell > 0 ? 1.0 / (2.0 * cov.ell * cov.ell) : 0.0;
+  cp.s3l = cov.ell > 0 ? std::sqrt(3.0) / cov.ell : 0.0;
+  dim3 g((unsigned)((m2.h.ne + 15) / 16), (unsigned)((m1.h.ne + 15) / 16));
+  hipLaunchKernelGGL(k_rhs_correlation, g, dim3(256), 0, s, A, B, cp, C, ldc);
+  FOSB_LAUNCH_CHECK();
+}
+
+// FF[(c*n_a + i)][m] = -i k [(I - x x^T) int phi_m(y) exp(-i k x.y) dy]_c
+__global__ void k_far_field_matrix(MeshDev md, Rule6Q R, double k, const double* __restrict__ xh, int n_a,
+                                   c128* __restrict__ FF) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (m >= md.ne || i >= n_a) return;
+  const double x0 = xh[3 * i], x1 = xh[3 * i + 1], x2 = xh[3 * i + 2];
+  double Jr[3] = {0, 0, 0}, Ji[3] = {0, 0, 0};
+  for (int side = 0; side < 2; ++side) {
+    const int t = md.edge_tri[side * md.ne + m];
+    const int a = md.edge_loc[side * md.ne + m];
+    double P[3][3];
+    tri_vertices(md, t, P);
+    const double ha = 0.5 * md.alpha[a * md.nt + t] * md.area[t];
+    for (int q = 0; q < 6; ++q) {
+      double y[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = R.l[q][0] * P[0][c] + R.l[q][1] * P[1][c] + R.l[q][2] * P[2][c];
+      double sn, cs;
+      sincos(-k * (x0 * y[0] + x1 * y[1] + x2 * y[2]), &sn, &cs);
+      const double f = R.w[q] * ha;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double ph = f * (y[c] - P[a][c]);
+        Jr[c] += ph * cs;
+        Ji[c] += ph * sn;
+      }
+    }
+  }
+  const double dr = x0 * Jr[0] + x1 * Jr[1] + x2 * Jr[2];
+  const double di = x0 * Ji[0] + x1 * Ji[1] + x2 * Ji[2];
+  const double xv[3] = {x0, x1, x2};
+  for (int c = 0; c < 3; ++c) {
+    const double pr = Jr[c] - xv[c] * dr, pi = Ji[c] - xv[c] * di;
+    // -i k (pr + i pi) = k pi - i k pr
+    FF[((int64_t)c * n_a + i) * md.ne + m] = c128{k * pi, -k * pr};
+  }
+}
+
+void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a, c128* FF) {
+  dim3 g((unsigned)((m.h.ne + 255) / 256), (unsigned)n_a);
+  hipLaunchKernelGGL(k_far_field_matrix, g, dim3(256), 0, s, m.dev(), make_rule(), k, xhat_dev, (int)n_a, FF);
+  FOSB_LAUNCH_CHECK();
+}
+
+// var[r] += scale * Re sum_n P[r][n] conj(F2[r][n]); one block per row, fixed order.
+__global__ __launch_bounds__(256) void k_row_dot_re(const c128* __restrict__ P, const c128* __restrict__ F2, int64_t n,
+                                                    double scale, double* __restrict__ var) {
+  __shared__ double sm[256];
+  const int64_t r = blockIdx.x;
+  double acc = 0;
+  for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+    const c128 a = P[r * n + c], b = F2[r * n + c];
+    acc += a.re * b.re + a.im * b.im;
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) var[r] += scale * sm[0];
+}
+
+void row_dot_re_accumulate(hipStream_t s, const c128* P, const c128* FF2, int64_t rows, int64_t n, double scale,
+                           double* var) {
+  hipLaunchKernelGGL(k_row_dot_re, dim3((unsigned)rows), dim3(256), 0, s, P, FF2, n, scale, var);
+  FOSB_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_matvec_rows(const c128* __restrict__ FF, int64_t n, const c128* __restrict__ u,
+                                                     c128* __restrict__ out) {
+  __shared__ double sr[256], si[256];
+  const int64_t r = blockIdx.x;
+  double ar = 0, ai = 0;
+  for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+    const c128 a = FF[r * n + c], b = u[c];
+    ar += a.re * b.re - a.im * b.im;
+    ai += a.re * b.im + a.im * b.re;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      si[threadIdx.x] += si[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = c128{sr[0], si[0]};
+}
+
+void matvec_rows(hipStream_t s, const c128* FF, int64_t rows, int64_t n, const c128* u, c128* out) {
+  hipLaunchKernelGGL(k_matvec_rows, dim3((unsigned)rows), dim3(256), 0, s, FF, n, u, out);
+  FOSB_LAUNCH_CHECK();
+}
+
+}  // namespace fosb

@@ -1,0 +1,377 @@
+"""Thin Python binding of libfosb.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module only converts
+torch tensors / numpy arrays to the C ABI's pointers and sizes, allocates
+output tensors with torch on the context's device, and turns non-OK
+statuses into FosbError.  The names mirror include/fosb.h.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import sys
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfosb.so")
+
+FP64, MIXED = 0, 1
+GAUSSIAN, MATERN32, CONSTANT, NORMAL_DOT = 0, 1, 2, 3
+RADIAL, NORMAL = 0, 1
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SINGULAR", 3: "E_NOCONV", 4: "E_WORKSPACE", 5: "E_OOM",
+          6: "E_DEVICE", 7: "E_UNSUPPORTED"}
+COV_KINDS = {"gaussian": GAUSSIAN, "matern32": MATERN32, "constant": CONSTANT, "normal_dot": NORMAL_DOT}
+FIELDS = {"radial": RADIAL, "normal": NORMAL}
+
+
+class FosbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Opts(C.Structure):
+    _fields_ = [("n_gauss_singular", C.c_int32), ("ir_max_sweeps", C.c_int32), ("ir_tol", C.c_double)]
+
+
+class Cov(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("sigma", C.c_double), ("ell", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("ir_sweeps", C.c_int32), ("n_solves", C.c_int32), ("ir_rel_correction", C.c_double)]
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+_D = C.c_double
+_SIGS = {
+    "fosb_last_error": (C.c_char_p, []),
+    "fosb_opts_default": (C.c_int, [C.POINTER(Opts)]),
+    "fosb_context_create": (C.c_int, [_I32, _P, C.POINTER(_P)]),
+    "fosb_context_destroy": (C.c_int, [_P]),
+    "fosb_context_synchronize": (C.c_int, [_P]),
+    "fosb_mesh_validate": (C.c_int, [_P, _I64, _P, _I64, C.POINTER(_I64)]),
+    "fosb_mesh_create": (C.c_int, [_P, _P, _I64, _P, _I64, C.POINTER(_P)]),
+    "fosb_mesh_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "fosb_mesh_destroy": (C.c_int, [_P]),
+    "fosb_assemble": (C.c_int, [_P, _P, _D, C.POINTER(Opts), _P, _I64]),
+    "fosb_level_create": (C.c_int, [_P, _P, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64, _I32, C.POINTER(Opts),
+                                    C.POINTER(_P)]),
+    "fosb_level_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
+    "fosb_level_solve": (C.c_int, [_P, _P, _P, _I64, _I64, C.POINTER(Stats)]),
+    "fosb_level_first_moment": (C.c_int, [_P, _P, _I64, _P]),
+    "fosb_level_destroy": (C.c_int, [_P]),
+    "fosb_rhs_correlation": (C.c_int, [_P, _P, _P, C.POINTER(Cov), _I64, _P, _I64]),
+    "fosb_two_sided_solve": (C.c_int, [_P, _P, _P, _P, _I64, C.POINTER(Stats)]),
+    "fosb_ct_pairs": (C.c_int, [_I32, _I32, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
+                                C.POINTER(_I32)]),
+    "fosb_correlation": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _I64, C.POINTER(_P),
+                                   C.POINTER(_I64), C.POINTER(Stats)]),
+    "fosb_far_field_matrix": (C.c_int, [_P, _P, _P, _I64, _P]),
+    "fosb_far_field_moments": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64), _P,
+                                         _I64, _I64, _P, _P]),
+    "fosb_profile_enable": (C.c_int, [_P, _I32]),
+    "fosb_profile_read": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
+}
+
+KERNEL_CLASSES = {"gemm_f64": 0, "gemm_f32": 1, "assemble": 2, "panel": 3, "trsm_leaf": 4, "rhs": 5}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libfosb.so (built in-tree).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2308_01457_amd.build` "
+                               "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise FosbError(status, lib().fosb_last_error().decode())
+
+
+def _host_f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _host_i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _dev(t, dtype=None):
+    """Device pointer of a contiguous torch CUDA tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch tensor on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def opts_default(**kw) -> Opts:
+    o = Opts()
+    _check(lib().fosb_opts_default(C.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mesh_validate(V, F) -> int:
+    """Host-only validation; returns the number of RWG functions (edges)."""
+    V = _host_f64(V)
+    F = _host_i32(F)
+    ne = _I64()
+    _check(lib().fosb_mesh_validate(V.ctypes.data_as(_P), V.shape[0], F.ctypes.data_as(_P), F.shape[0], C.byref(ne)))
+    return ne.value
+
+
+def ct_pairs(L0: int, L: int) -> list[tuple[int, int, int, int]]:
+    n = L - L0 + 1
+    a, b, s, m = ((_I32 * n)() for _ in range(4))
+    cnt = _I32()
+    _check(lib().fosb_ct_pairs(L0, L, a, b, s, m, C.byref(cnt)))
+    return [(a[i], b[i], s[i], m[i]) for i in range(cnt.value)]
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = _P()
+        _check(lib().fosb_context_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def synchronize(self):
+        _check(lib().fosb_context_synchronize(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fosb_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():   # process teardown: the driver reclaims everything
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile_enable(ctx: "Context", on: bool = True) -> None:
+    _check(lib().fosb_profile_enable(ctx.h, 1 if on else 0))
+
+
+def profile_read(ctx: "Context") -> dict:
+    """{class: (launches, seconds, flops, bytes)} of the recorded launches."""
+    out = {}
+    for name, cls in KERNEL_CLASSES.items():
+        n, s, f, b = _I64(), _D(), _D(), _D()
+        _check(lib().fosb_profile_read(ctx.h, cls, C.byref(n), C.byref(s), C.byref(f), C.byref(b)))
+        out[name] = (n.value, s.value, f.value, b.value)
+    return out
+
+
+class Mesh:
+    def __init__(self, ctx: Context, V, F):
+        self.ctx = ctx
+        V = _host_f64(V)
+        F = _host_i32(F)
+        h = _P()
+        _check(lib().fosb_mesh_create(ctx.h, V.ctypes.data_as(_P), V.shape[0], F.ctypes.data_as(_P), F.shape[0],
+                                      C.byref(h)))
+        self.h = h
+        nt, ne, ntp = _I64(), _I64(), _I64()
+        _check(lib().fosb_mesh_info(h, C.byref(nt), C.byref(ne), C.byref(ntp)))
+        self.n_triangles, self.n_edges, self.n_touching = nt.value, ne.value, ntp.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fosb_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():   # process teardown: the driver reclaims everything
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def assemble(ctx: Context, mesh: Mesh, k: float, opts: Opts | None = None, Z=None):
+    """fosb_assemble: returns the N x N complex128 EFIE matrix (torch, on device)."""
+    import torch
+    n = mesh.n_edges
+    if Z is None:
+        Z = torch.empty((n, n), dtype=torch.complex128, device=ctx.torch_device)
+    _check(lib().fosb_assemble(ctx.h, mesh.h, float(k), C.byref(opts) if opts else None, _dev(Z, torch.complex128),
+                               Z.stride(0)))
+    return Z
+
+
+class Level:
+    """fosb_level_create.  FP64: Z is factorised in place.  MIXED: Z is kept and
+    a complex64 copy (allocated here unless given) receives the FP32 LU."""
+
+    def __init__(self, ctx: Context, mesh: Mesh, k: float, Z, precision: int = FP64, dirs=((0.0, 0.0, 1.0),),
+                 pols=((1.0, 0.0, 0.0),), field: str | int = "radial", opts: Opts | None = None, Zlow=None):
+        import torch
+        self.ctx, self.mesh, self.k, self.Z = ctx, mesh, float(k), Z
+        self.precision = precision
+        n = mesh.n_edges
+        if precision == MIXED and Zlow is None:
+            Zlow = torch.empty((n, n), dtype=torch.complex64, device=ctx.torch_device)
+        self.Zlow = Zlow
+        d = _host_f64(dirs).reshape(-1, 3)
+        p = _host_f64(pols).reshape(-1, 3)
+        fld = FIELDS[field] if isinstance(field, str) else int(field)
+        h = _P()
+        _check(lib().fosb_level_create(ctx.h, mesh.h, self.k, precision, _dev(Z, torch.complex128), Z.stride(0),
+                                       _dev(Zlow, torch.complex64) if Zlow is not None else None,
+                                       Zlow.stride(0) if Zlow is not None else 0, d.ctypes.data_as(_P),
+                                       p.ctypes.data_as(_P), d.shape[0], fld, C.byref(opts) if opts else None,
+                                       C.byref(h)))
+        self.h = h
+        self.n = n
+        self.n_dirs = d.shape[0]
+
+    def solve(self, B, stats: Stats | None = None):
+        import torch
+        st = stats if stats is not None else Stats()
+        B2 = B if B.dim() == 2 else B.view(-1, 1)
+        _check(lib().fosb_level_solve(self.ctx.h, self.h, _dev(B2, torch.complex128), B2.stride(0), B2.shape[1],
+                                      C.byref(st)))
+        return B
+
+    def first_moment(self, dir: int = 0):
+        import torch
+        u = torch.empty(self.n, dtype=torch.complex128, device=self.ctx.torch_device)
+        _check(lib().fosb_level_first_moment(self.ctx.h, self.h, dir, _dev(u)))
+        return u
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fosb_level_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():   # process teardown: the driver reclaims everything
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_cov(kind: str | int, sigma: float, ell: float = 1.0) -> Cov:
+    c = Cov()
+    c.kind = COV_KINDS[kind] if isinstance(kind, str) else int(kind)
+    c.sigma = float(sigma)
+    c.ell = float(ell)
+    return c
+
+
+def rhs_correlation(ctx: Context, l1: Level, l2: Level, cov: Cov, dir: int = 0, C_out=None):
+    import torch
+    if C_out is None:
+        C_out = torch.empty((l1.n, l2.n), dtype=torch.complex128, device=ctx.torch_device)
+    _check(lib().fosb_rhs_correlation(ctx.h, l1.h, l2.h, C.byref(cov), dir, _dev(C_out, torch.complex128),
+                                      C_out.stride(0)))
+    return C_out
+
+
+def two_sided_solve(ctx: Context, l1: Level, l2: Level, C_io, stats: Stats | None = None):
+    import torch
+    st = stats if stats is not None else Stats()
+    _check(lib().fosb_two_sided_solve(ctx.h, l1.h, l2.h, _dev(C_io, torch.complex128), C_io.stride(0), C.byref(st)))
+    return C_io
+
+
+def correlation(ctx: Context, levels: list[Level], L0: int, L: int, cov: Cov, dir: int = 0, blocks=None,
+                stats: Stats | None = None):
+    """All Sigma blocks of the Hermitian-reduced CT index set, in ct_pairs order."""
+    import torch
+    pairs = ct_pairs(L0, L)
+    if blocks is None:
+        blocks = [torch.empty((levels[a - L0].n, levels[b - L0].n), dtype=torch.complex128, device=ctx.torch_device)
+                  for a, b, _, _ in pairs]
+    st = stats if stats is not None else Stats()
+    lv = (_P * len(levels))(*[l.h for l in levels])
+    bp = (_P * len(blocks))(*[_dev(b, torch.complex128) for b in blocks])
+    ld = (_I64 * len(blocks))(*[b.stride(0) for b in blocks])
+    _check(lib().fosb_correlation(ctx.h, lv, len(levels), L0, L, C.byref(cov), dir, bp, ld, C.byref(st)))
+    return blocks
+
+
+def far_field_matrix(ctx: Context, level: Level, xhat):
+    import torch
+    x = _host_f64(xhat).reshape(-1, 3)
+    FF = torch.empty((3 * x.shape[0], level.n), dtype=torch.complex128, device=ctx.torch_device)
+    _check(lib().fosb_far_field_matrix(ctx.h, level.h, x.ctypes.data_as(_P), x.shape[0], _dev(FF)))
+    return FF
+
+
+def far_field_moments(ctx: Context, levels: list[Level], L0: int, L: int, blocks, xhat, dir: int = 0,
+                      with_mean: bool = False):
+    """CT far-field variance (3, n_a) float64 on device [and the finest level's mean far field (3, n_a)]."""
+    import torch
+    x = _host_f64(xhat).reshape(-1, 3)
+    n_a = x.shape[0]
+    var = torch.empty(3 * n_a, dtype=torch.float64, device=ctx.torch_device)
+    mean = torch.empty(3 * n_a, dtype=torch.complex128, device=ctx.torch_device) if with_mean else None
+    lv = (_P * len(levels))(*[l.h for l in levels])
+    bp = (_P * len(blocks))(*[_dev(b, torch.complex128) for b in blocks])
+    ld = (_I64 * len(blocks))(*[b.stride(0) for b in blocks])
+    _check(lib().fosb_far_field_moments(ctx.h, lv, len(levels), L0, L, bp, ld, x.ctypes.data_as(_P), n_a, dir,
+                                        _dev(var, torch.float64), _dev(mean) if mean is not None else None))
+    var = var.view(3, n_a)
+    return (var, mean.view(3, n_a)) if with_mean else var
+
+
+@dataclass
+class PipelineResult:
+    var: object            # (3, n_a) float64 device tensor
+    blocks: list           # Sigma blocks (device)
+    levels: list           # Level handles (keep alive with the blocks)
+    meshes: list
+    stats: Stats
+
+
+def run_pipeline(ctx: Context, meshes_VF, k: float, L0: int, L: int, cov: Cov, xhat, precision: int = FP64,
+                 dirs=((0.0, 0.0, 1.0),), pols=((1.0, 0.0, 0.0),), field="radial", opts: Opts | None = None,
+                 dir: int = 0) -> PipelineResult:
+    """One pass of the hot path: assemble every level (L0..L), factorise and solve
+    the first moments, then all CT level-pair solves and the far-field variance.
+    meshes_VF: list of (V, F) for levels L0..L."""
+    meshes = [Mesh(ctx, V, F) for V, F in meshes_VF]
+    levels = []
+    for m in meshes:
+        Z = assemble(ctx, m, k, opts)
+        levels.append(Level(ctx, m, k, Z, precision, dirs, pols, field, opts))
+    st = Stats()
+    blocks = correlation(ctx, levels, L0, L, cov, dir, stats=st)
+    var = far_field_moments(ctx, levels, L0, L, blocks, xhat, dir)
+    return PipelineResult(var, blocks, levels, meshes, st)
