@@ -10,8 +10,9 @@
 // owns a 64 x 32 sub-tile = 4 x 2 MFMA 16x16 blocks; K is staged 16 at a time
 // through LDS in planar (re/im) layout, A stored k-major so that a fragment
 // load is 16 consecutive rows.  Operand fragments (16x16x4): lane l holds
-// A[l%16][k0 + l/16] and B[k0 + l/16][l%16]; the accumulator holds
-// D[4*(l/16) + v][l%16], v = 0..3.
+// A[l%16][k0 + l/16] and B[k0 + l/16][l%16]; accumulator element v (0..3) of
+// lane l is D[row][l%16] with row = 4*(l/16) + v for the FP32 instruction and
+// row = l/16 + 4*v for the FP64 one.
 #include <algorithm>
 
 #include "common.h"
@@ -27,6 +28,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
 };
 
 template <>
@@ -35,6 +37,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
 };
 
 constexpr int BM = 128, BN = 64, BK = 16;
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wr * 64 + i * 16 + 4 * kq + v;
+        const int64_t row = m0 + wr * 64 + i * 16 + Mfma<T>::row(kq, v);
         const int64_t col = n0 + wc * 32 + j * 16 + r16;
         if (row < M && col < N) {
           const T cr = t1[i][j][v] - t2[i][j][v];
