@@ -107,7 +107,7 @@ def run_gpu(args, W):
 
     ctx = fosb.Context(0)
     cov = fosb.make_cov(W.w.cov_kind, W.w.sigma, W.w.ell)
-    opts = fosb.opts_default(ir_tol=1e-10, ir_max_sweeps=10)
+    opts = fosb.opts_default(ir_tol=1e-7, ir_max_sweeps=10)
     meshes, Z = gpu_setup(fosb, torch, ctx, W)
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     Zlow = [None] * len(meshes)

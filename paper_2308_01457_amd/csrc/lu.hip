@@ -43,236 +43,255 @@ __device__ __forceinline__ T cabs1(cplx<T> a) {
   return fabs(a.re) + fabs(a.im);
 }
 
-// Gaussian elimination with partial pivoting on an nr x w block in LDS
-// (nr <= 64, w <= 32), rows carrying their global index in idx[].  After the
-// call rows 0..min(nr,w)-1 are the pivot rows in order, holding L (strictly
-// below the diagonal, unit diagonal implied) and U.  Returns (to all threads)
-// the first column with an exactly zero pivot, or -1.
+// Tournament pivoting.  A tree node holds up to NODE candidate rows of the
+// panel, one row per thread of a 4-wavefront workgroup, each row's w <= 32
+// entries in registers.  Gaussian elimination with partial pivoting on the
+// node picks, at step j, the largest |re|+|im| in column j among the rows not
+// chosen yet, broadcasts that row through LDS and eliminates column j from the
+// remaining rows.  The pivot search reduces one 64-bit key per row,
+// (float(|re|+|im|) bits << 32) | ~row, so the maximum key is the largest
+// modulus with ties going to the lowest row; a wave butterfly is followed by a
+// maximum over the four waves' keys in LDS.  Broadcast slots are double
+// buffered, so a step needs two barriers.  The step loop is unrolled, which
+// keeps every register index constant; the row chosen at step j then holds
+// row j of the node's L\U factors and writes it to lu[j][*] (LDS).
+constexpr int NODE = 256;         // rows per tree node = threads per workgroup
+constexpr int NWAVE = NODE / 64;
+constexpr int FANIN = NODE / NB;  // children merged per node (8)
+
 template <typename T>
-__device__ int gepp_lds(cplx<T> (*sa)[SLD], int* idx, int nr, int w, int* s_piv) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
+__device__ __forceinline__ unsigned long long pivot_key(cplx<T> v, int row) {
+  const float m = (float)cabs1(v);
+  return ((unsigned long long)__float_as_uint(m) << 32) | (unsigned long long)(~(unsigned)row);
+}
+
+template <typename T>
+__device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvalid, int w, int tid, int& step,
+                                         cplx<T> (*prow)[NB], cplx<T> (*lu)[NB + 1],
+                                         unsigned long long (*skey)[NWAVE]) {
+  // a[0] is always the current column j: after each step a row rotates left
+  // by one and its multiplier enters the last slot, so the row chosen at step
+  // j holds U[j][j..] in its leading slots and L[j][0..j-1] in its trailing ones.
   int zero_col = -1;
-  const int steps = min(nr, w);
+  const int steps = min(nvalid, w);
+  const int lane = tid & 63, wave = tid >> 6;
+  step = -1;
   for (int j = 0; j < steps; ++j) {
-    if (tid < 64) {
-      T v = (lane >= j && lane < nr) ? cabs1(sa[lane][j]) : T(-1);
-      int r = lane;
+    const int b = j & 1;
+    unsigned long long key = (valid && step < 0) ? pivot_key(a[0], tid) : 0ull;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        T ov = __shfl_xor(v, off, 64);
-        int orr = __shfl_xor(r, off, 64);
-        if (ov > v || (ov == v && orr < r)) {
-          v = ov;
-          r = orr;
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(key, off, 64);
+      key = o > key ? o : key;
+    }
+    if (lane == 0) skey[b][wave] = key;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) {
+      const unsigned long long o = skey[b][q];
+      key = o > key ? o : key;
+    }
+    const int r = (int)(~(unsigned)(key & 0xffffffffull));
+    if (tid == r) {
+      step = j;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        prow[b][c] = a[c];
+        const int col = c < NB - j ? j + c : c - (NB - j);
+        lu[j][col] = a[c];
+      }
+    }
+    __syncthreads();
+    const cplx<T> piv = prow[b][0];
+    if (piv.re == T(0) && piv.im == T(0) && zero_col < 0) zero_col = j;
+    if (valid && step < 0) {
+      const cplx<T> l = cmul(a[0], cinv(piv));
+      const int wr = w - j;  // live columns of this step
+#pragma unroll
+      for (int c = 1; c < NB; ++c) {
+        if (c < wr) {
+          const cplx<T> u = prow[b][c];
+          a[c].re -= l.re * u.re - l.im * u.im;
+          a[c].im -= l.re * u.im + l.im * u.re;
         }
       }
-      if (lane == 0) *s_piv = r;
+#pragma unroll
+      for (int c = 0; c < NB - 1; ++c) a[c] = a[c + 1];
+      a[NB - 1] = l;
     }
-    __syncthreads();
-    const int p = *s_piv;
-    if (p != j) {
-      if (tid < w) {
-        cplx<T> t = sa[j][tid];
-        sa[j][tid] = sa[p][tid];
-        sa[p][tid] = t;
-      } else if (tid == w) {
-        int t = idx[j];
-        idx[j] = idx[p];
-        idx[p] = t;
-      }
-    }
-    __syncthreads();
-    const cplx<T> piv = sa[j][j];
-    if (piv.re == T(0) && piv.im == T(0) && zero_col < 0) zero_col = j;
-    const cplx<T> inv = cinv(piv);
-    for (int r = j + 1 + tid; r < nr; r += blockDim.x) sa[r][j] = cmul(sa[r][j], inv);
-    __syncthreads();
-    const int wc = w - j - 1;
-    if (wc > 0) {
-      const int tot = (nr - j - 1) * wc;
-      for (int e = tid; e < tot; e += blockDim.x) {
-        const int r = j + 1 + e / wc;
-        const int c = j + 1 + e % wc;
-        const cplx<T> l = sa[r][j], u = sa[j][c];
-        cplx<T> a = sa[r][c];
-        a.re -= l.re * u.re - l.im * u.im;
-        a.im -= l.re * u.im + l.im * u.re;
-        sa[r][c] = a;
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
   return zero_col;
 }
 
-struct PanelWork {
-  int32_t* cand;      // candidate row indices, per tree level and node (NB each)
-  int32_t* counters;  // one per tree node
-  int32_t* lvl_cand;  // offset (in nodes) of each level in cand, [levels+1]
-  int32_t* lvl_size;  // nodes per level
-  int nlevels;
-  int32_t* plist;     // [0] = count, then pairs (src, dst)
-  int32_t* ipiv;      // global pivot positions (n)
+struct PanelOut {
+  int32_t* moves;     // per panel: [0] = count, then pairs (src row, dst position), 1 + 4*NB ints
   int32_t* info;      // first zero pivot (1-based), 0 if none
 };
 
 template <typename T>
-__device__ void load_rows(const cplx<T>* A, int64_t lda, int64_t col0, int w, const int* rows, int nr,
-                          cplx<T> (*sa)[SLD]) {
-  for (int e = threadIdx.x; e < nr * w; e += blockDim.x) {
-    const int r = e / w, c = e % w;
-    sa[r][c] = A[(int64_t)rows[r] * lda + col0 + c];
+__device__ __forceinline__ void load_row(const cplx<T>* A, int64_t lda, int64_t col0, int w, int row,
+                                         cplx<T> (&a)[NB]) {
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    a[c] = (row >= 0 && c < w) ? A[(int64_t)row * lda + col0 + c] : cplx<T>{T(0), T(0)};
+}
+
+// Root of the tournament: lu[][] holds L11 \ U11 of the chosen rows (in pivot
+// order) and win[] their row indices.  Writes the top block, the inverses of
+// both diagonal factors (one column per thread, in registers), the row moves
+// and the first zero pivot.  Row moves: pivot r goes to position k + r; the
+// rows that held positions k..k+wk-1 and are not pivots go, in increasing row
+// order, to the positions the pivots below the block vacate (in increasing
+// order).
+template <typename T>
+__device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win, int wk, int w, int zc, int64_t k,
+                                           int tid, int32_t* __restrict__ moves, int32_t* __restrict__ info,
+                                           cplx<T>* __restrict__ top, cplx<T>* __restrict__ invL,
+                                           cplx<T>* __restrict__ invU) {
+  __shared__ int inblk[NB];   // 1 if row k + r is itself a pivot
+  __shared__ int s_cnt[2];
+  for (int e = tid; e < NB * NB; e += NODE) {
+    const int r = e / NB, c = e % NB;
+    if (r >= wk || c >= w) tb[r][c] = cplx<T>{T(0), T(0)};
+  }
+  if (tid < NB) inblk[tid] = 0;
+  __syncthreads();
+  if (tid < wk && win[tid] < k + wk) inblk[win[tid] - k] = 1;
+  for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
+  if (zc >= 0 && tid == 0) atomicMin(info, (int)(k + zc + 1));
+  // inverses of the diagonal factors by Gauss-Jordan sweeps over the whole
+  // workgroup (identity beyond wk):  L X = I forward, U X = I backward
+  __shared__ cplx<T> sx[NB][NB + 1];
+  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  __syncthreads();
+  for (int r = 0; r < wk; ++r) {
+    // rows i > r: X[i][c] -= L[i][r] X[r][c], c <= r
+    const int cols = r + 1, rows = wk - r - 1;
+    for (int e = tid; e < rows * cols; e += NODE) {
+      const int i = r + 1 + e / cols, c = e % cols;
+      const cplx<T> l = tb[i][r], x = sx[r][c];
+      sx[i][c].re -= l.re * x.re - l.im * x.im;
+      sx[i][c].im -= l.re * x.im + l.im * x.re;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += NODE) invL[e] = sx[e / NB][e % NB];
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  __syncthreads();
+  for (int r = wk - 1; r >= 0; --r) {
+    const cplx<T> inv = cinv(tb[r][r]);
+    if (tid >= r && tid < wk) sx[r][tid] = cmul(sx[r][tid], inv);  // row r scaled: X[r][c], c >= r
+    __syncthreads();
+    // rows i < r: X[i][c] -= U[i][r] X[r][c], c >= r
+    const int cols = wk - r;
+    for (int e = tid; e < r * cols; e += NODE) {
+      const int i = e / cols, c = r + e % cols;
+      const cplx<T> u = tb[i][r], x = sx[r][c];
+      sx[i][c].re -= u.re * x.re - u.im * x.im;
+      sx[i][c].im -= u.re * x.im + u.im * x.re;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += NODE) invU[e] = sx[e / NB][e % NB];
+  // move list, built by the first wavefront (every thread reaches the barrier)
+  __shared__ int vsorted[NB];
+  const int lane = tid;  // meaningful for tid < 64 only
+  bool vac = false;
+  if (tid < 64) {
+    vac = lane < wk && win[lane] >= k + wk;
+    if (vac) {
+      int rank_v = 0;
+      for (int q = 0; q < wk; ++q)
+        if (win[q] >= k + wk && win[q] < win[lane]) ++rank_v;
+      vsorted[rank_v] = win[lane];
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // pivots: win[r] -> k + r
+    const bool mv = lane < wk && win[lane] != k + lane;
+    const unsigned long long m1 = __ballot(mv);
+    const int n1 = __popcll(m1);
+    if (mv) {
+      const int b = __popcll(m1 & ((1ull << lane) - 1ull));
+      moves[1 + 2 * b] = win[lane];
+      moves[2 + 2 * b] = (int)(k + lane);
+    }
+    // displaced rows (positions k..k+wk-1 not holding a pivot), increasing order, to the vacated positions
+    const bool disp = lane < wk && !inblk[lane];
+    const unsigned long long md = __ballot(disp);
+    if (disp) {
+      const int rd = __popcll(md & ((1ull << lane) - 1ull));
+      moves[1 + 2 * (n1 + rd)] = (int)(k + lane);
+      moves[2 + 2 * (n1 + rd)] = vsorted[rd];
+    }
+    if (lane == 0) moves[0] = n1 + __popcll(md);
   }
 }
 
-// Tournament pivoting of the panel rows [k, n) x columns [k, k + w).
+// Tree node of the tournament over panel rows [k, n) x columns [k, k + w).
+// Leaf nodes (cand_in == nullptr) take NODE consecutive rows; inner nodes take
+// the candidates of up to FANIN children of the previous level.  Candidates
+// of node p are written to cand_out[p*NB .. p*NB + NB) (-1 = none).
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel_tslu(const cplx<T>* __restrict__ A, int64_t lda, int64_t n, int64_t k,
-                                                    int w, PanelWork pw, cplx<T>* __restrict__ top,
-                                                    cplx<T>* __restrict__ invL, cplx<T>* __restrict__ invU) {
-  __shared__ cplx<T> sa[RB][SLD];
-  __shared__ cplx<T> sinv[NB][SLD];
-  __shared__ int idx[RB];
-  __shared__ int s_piv, s_flag;
+__global__ __launch_bounds__(NODE) void k_tslu_node(const cplx<T>* __restrict__ A, int64_t lda, int64_t n, int64_t k,
+                                                    int w, const int32_t* __restrict__ cand_in, int n_in,
+                                                    int32_t* __restrict__ cand_out, int is_root,
+                                                    int32_t* __restrict__ moves, int32_t* __restrict__ info,
+                                                    cplx<T>* __restrict__ top, cplx<T>* __restrict__ invL,
+                                                    cplx<T>* __restrict__ invU) {
+  __shared__ cplx<T> prow[2][NB];
+  __shared__ cplx<T> lu[NB][NB + 1];
+  __shared__ int sidx[NODE];
+  __shared__ int win[NB];
+  __shared__ unsigned long long skey[2][NWAVE];
+  __shared__ int scnt[NWAVE];
+  __shared__ int s_cnt;
   const int tid = threadIdx.x;
-  const int64_t m = n - k;
-  int node = blockIdx.x;
-  // leaf: GEPP on this block's rows
-  int nr = (int)min<int64_t>(RB, m - (int64_t)node * RB);
-  for (int r = tid; r < nr; r += blockDim.x) idx[r] = (int)(k + (int64_t)node * RB + r);
-  __syncthreads();
-  load_rows(A, lda, k, w, idx, nr, sa);
-  __syncthreads();
-  int zc = gepp_lds(sa, idx, nr, w, &s_piv);
-  int ncand = min(nr, w);
-  for (int level = 0; level < pw.nlevels - 1; ++level) {
-    // publish this node's candidates
-    int32_t* mine = pw.cand + (int64_t)(pw.lvl_cand[level] + node) * NB;
-    for (int r = tid; r < NB; r += blockDim.x) mine[r] = r < ncand ? idx[r] : -1;
-    const int parent = node >> 1;
-    const int sib = node ^ 1;
-    if (sib >= pw.lvl_size[level]) {  // no sibling: carry the candidates up unchanged
-      node = parent;
-      __syncthreads();
-      continue;
-    }
-    __threadfence();
+  const int p = blockIdx.x;
+  int nvalid = 0;
+  if (cand_in == nullptr) {
+    nvalid = (int)min<int64_t>(NODE, n - k - (int64_t)p * NODE);
+    if (tid < nvalid) sidx[tid] = (int)(k + (int64_t)p * NODE + tid);
+  } else {
+    // compact the children's candidate lists (ids >= 0) in order: ballot per wave, prefix over waves
+    const int c0 = p * FANIN;
+    const int nch = min(FANIN, n_in - c0);
+    const int id = tid < nch * NB ? cand_in[(int64_t)c0 * NB + tid] : -1;
+    const unsigned long long mask = __ballot(id >= 0);
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane == 0) scnt[wave] = __popcll(mask);
     __syncthreads();
+    int off = 0;
+    for (int q = 0; q < wave; ++q) off += scnt[q];
+    if (id >= 0) sidx[off + __popcll(mask & ((1ull << lane) - 1ull))] = id;
     if (tid == 0) {
-      int old = __hip_atomic_fetch_add(pw.counters + pw.lvl_cand[level + 1] + parent, 1, __ATOMIC_ACQ_REL,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-      s_flag = old;
-      if (old == 1)
-        __hip_atomic_store(pw.counters + pw.lvl_cand[level + 1] + parent, 0, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      int tot = 0;
+      for (int q = 0; q < NWAVE; ++q) tot += scnt[q];
+      s_cnt = tot;
     }
     __syncthreads();
-    if (s_flag == 0) return;  // first to arrive: the sibling merges
-    __threadfence();
-    // merge: candidates of both children, original values
-    const int32_t* c0 = pw.cand + (int64_t)(pw.lvl_cand[level] + 2 * parent) * NB;
-    const int32_t* c1 = c0 + NB;
-    if (tid == 0) {
-      int cnt = 0;
-      for (int r = 0; r < NB; ++r) {
-        int v = __hip_atomic_load(c0 + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (v >= 0) idx[cnt++] = v;
-      }
-      for (int r = 0; r < NB; ++r) {
-        int v = __hip_atomic_load(c1 + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (v >= 0) idx[cnt++] = v;
-      }
-      s_piv = cnt;
-    }
-    __syncthreads();
-    nr = s_piv;
-    __syncthreads();
-    load_rows(A, lda, k, w, idx, nr, sa);
-    __syncthreads();
-    zc = gepp_lds(sa, idx, nr, w, &s_piv);
-    ncand = min(nr, w);
-    node = parent;
-  }
-  // root: rows 0..w-1 of sa hold L11 \ U11 of the chosen pivot rows
-  const int wk = min(w, ncand);
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, c = e % NB;
-    top[e] = (r < wk && c < w) ? sa[r][c] : cplx<T>{T(0), T(0)};
-  }
-  if (zc >= 0 && tid == 0) atomicMin(pw.info, (int)(k + zc + 1));
-  // inverse of the unit lower factor (column c per thread)
-  if (tid < NB) {
-    const int c = tid;
-    for (int r = 0; r < NB; ++r) {
-      cplx<T> x{r == c ? T(1) : T(0), T(0)};
-      if (r < wk) {
-        for (int t = c; t < r; ++t) {
-          const cplx<T> l = sa[r][t], y = sinv[t][c];
-          x.re -= l.re * y.re - l.im * y.im;
-          x.im -= l.re * y.im + l.im * y.re;
-        }
-      }
-      sinv[r][c] = (r < c) ? cplx<T>{T(0), T(0)} : x;
-    }
+    nvalid = s_cnt;
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += blockDim.x) invL[e] = sinv[e / NB][e % NB];
-  __syncthreads();
-  // inverse of the upper factor
-  if (tid < NB) {
-    const int c = tid;
-    for (int r = NB - 1; r >= 0; --r) {
-      cplx<T> x{r == c ? T(1) : T(0), T(0)};
-      if (r < wk) {
-        for (int t = r + 1; t <= c && t < wk; ++t) {
-          const cplx<T> u = sa[r][t], y = sinv[t][c];
-          x.re -= u.re * y.re - u.im * y.im;
-          x.im -= u.re * y.im + u.im * y.re;
-        }
-        x = cmul(x, cinv(sa[r][r]));
-      }
-      sinv[r][c] = (r > c) ? cplx<T>{T(0), T(0)} : x;
-    }
+  const bool valid = tid < nvalid;
+  const int row = valid ? sidx[tid] : -1;
+  cplx<T> a[NB];
+  load_row(A, lda, k, w, row, a);
+  int step;
+  const int zc = gepp_node(a, valid, nvalid, w, tid, step, prow, lu, skey);
+  const int ncand = min(nvalid, w);
+  if (is_root) {
+    if (step >= 0) win[step] = row;
+    __syncthreads();
+    panel_root(lu, win, ncand, w, zc, k, tid, moves, info, top, invL, invU);
+    return;
   }
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += blockDim.x) invU[e] = sinv[e / NB][e % NB];
-  // row interchanges: pivot r goes to position k + r (sequential swap semantics)
-  if (tid == 0) {
-    int pos[2 * NB], con[2 * NB];   // touched positions and their current original row
-    int np = 0;
-    auto find_pos = [&](int row) {  // current position of original row
-      for (int q = 0; q < np; ++q)
-        if (con[q] == row) return pos[q];
-      return row;
-    };
-    auto slot = [&](int p) {
-      for (int q = 0; q < np; ++q)
-        if (pos[q] == p) return q;
-      pos[np] = p;
-      con[np] = p;
-      return np++;
-    };
-    for (int r = 0; r < wk; ++r) {
-      const int target = (int)(k + r);
-      const int cur = find_pos(idx[r]);
-      pw.ipiv[target] = cur;
-      if (cur != target) {
-        const int a = slot(target), b = slot(cur);
-        const int t = con[a];
-        con[a] = con[b];
-        con[b] = t;
-      }
-    }
-    int cnt = 0;
-    for (int q = 0; q < np; ++q)
-      if (con[q] != pos[q]) {
-        pw.plist[1 + 2 * cnt] = con[q];  // source row (original content)
-        pw.plist[2 + 2 * cnt] = pos[q];  // destination position
-        ++cnt;
-      }
-    pw.plist[0] = cnt;
-  }
+  int32_t* out = cand_out + (int64_t)p * NB;
+  if (step >= 0) out[step] = row;
+  if (tid >= ncand && tid < NB) out[tid] = -1;
 }
 
 // Apply the listed row moves to the full matrix width (column stripes of 64).
@@ -324,28 +343,87 @@ __global__ __launch_bounds__(256) void k_panel_finish(cplx<T>* __restrict__ A, i
   }
 }
 
-// B (nr x nrhs, nr <= 32) <- Inv(nr x nr of a 32x32 block) * B.
-template <typename T>
-__global__ __launch_bounds__(256) void k_apply_inv(const cplx<T>* __restrict__ inv, int nr, cplx<T>* __restrict__ B,
-                                                   int64_t ldb, int64_t nrhs) {
+// Triangular solve on a diagonal block of up to NL rows in one launch:
+// rows [k0, k0 + n) of B <- op(T)^{-1} B, where T is the unit lower (LOWER) or
+// upper factor stored in A and its 32x32 diagonal blocks are applied through
+// their stored inverses.  Each workgroup owns a stripe of CS right-hand sides
+// held in LDS; after each diagonal block the coupling to the remaining rows
+// of the leaf is subtracted with the off-diagonal factor entries.
+constexpr int NL = 256;
+template <typename T> struct LeafCS { static constexpr int v = 16; };
+template <> struct LeafCS<double> { static constexpr int v = 8; };
+
+template <typename T, bool LOWER, int CS>
+__global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A, int64_t lda,
+                                                   const cplx<T>* __restrict__ dinv, int64_t k0, int n,
+                                                   cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs) {
+  constexpr int XPT = (NB * CS + 255) / 256;
+  __shared__ cplx<T> sb[NL][CS + 1];
   __shared__ cplx<T> si[NB][NB + 1];
-  __shared__ cplx<T> sb[NB][65];
-  const int64_t c0 = (int64_t)blockIdx.x * 64;
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) si[e / NB][e % NB] = inv[e];
-  for (int e = threadIdx.x; e < NB * 64; e += blockDim.x) {
-    const int r = e / 64, c = e % 64;
-    sb[r][c] = (r < nr && c0 + c < nrhs) ? B[(int64_t)r * ldb + c0 + c] : cplx<T>{T(0), T(0)};
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * CS;
+  for (int e = tid; e < NL * CS; e += 256) {  // rows >= n are zero (they meet zero factor entries)
+    const int r = e / CS, c = e % CS;
+    sb[r][c] = (r < n && c0 + c < nrhs) ? B[(int64_t)r * ldb + c0 + c] : cplx<T>{T(0), T(0)};
+  }
+  const int nblk = (n + NB - 1) / NB;
+  for (int bi = 0; bi < nblk; ++bi) {
+    const int b = LOWER ? bi : nblk - 1 - bi;
+    const int r0 = b * NB, rn = min(NB, n - r0);
+    __syncthreads();
+    const cplx<T>* inv = dinv + (k0 / NB + b) * NB * NB;
+    for (int e = tid; e < NB * NB; e += 256) si[e / NB][e % NB] = inv[e];
+    __syncthreads();
+    cplx<T> xv[XPT];
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int e = tid + 256 * q;
+      T xr = 0, xi = 0;
+      if (e < rn * CS) {
+        const int r = e / CS, c = e % CS;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          if (t < rn) {
+            const cplx<T> u = si[r][t], v = sb[r0 + t][c];
+            xr += u.re * v.re - u.im * v.im;
+            xi += u.re * v.im + u.im * v.re;
+          }
+        }
+      }
+      xv[q] = cplx<T>{xr, xi};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int e = tid + 256 * q;
+      if (e < rn * CS) sb[r0 + e / CS][e % CS] = xv[q];
+    }
+    __syncthreads();
+    const int u0 = LOWER ? r0 + rn : 0;
+    const int u1 = LOWER ? n : r0;
+    if (tid >= u0 && tid < u1) {  // one thread per remaining row: its factor segment once, all CS columns
+      const cplx<T>* arow = A + (k0 + tid) * lda + k0 + r0;
+      cplx<T> l[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) l[t] = t < rn ? arow[t] : cplx<T>{T(0), T(0)};
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        T xr = 0, xi = 0;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          const cplx<T> v = sb[r0 + t][c];
+          xr += l[t].re * v.re - l[t].im * v.im;
+          xi += l[t].re * v.im + l[t].im * v.re;
+        }
+        sb[tid][c].re -= xr;
+        sb[tid][c].im -= xi;
+      }
+    }
   }
   __syncthreads();
-  const int c = threadIdx.x & 63;
-  for (int r = threadIdx.x >> 6; r < nr; r += 4) {
-    T xr = 0, xi = 0;
-    for (int t = 0; t < nr; ++t) {
-      const cplx<T> a = si[r][t], b = sb[t][c];
-      xr += a.re * b.re - a.im * b.im;
-      xi += a.re * b.im + a.im * b.re;
-    }
-    if (c0 + c < nrhs) B[(int64_t)r * ldb + c0 + c] = cplx<T>{xr, xi};
+  for (int e = tid; e < n * CS; e += 256) {
+    const int r = e / CS, c = e % CS;
+    if (c0 + c < nrhs) B[(int64_t)r * ldb + c0 + c] = sb[r][c];
   }
 }
 
@@ -357,13 +435,14 @@ struct LuRun {
   int64_t n, lda;
   cplx<T>* dinvL;
   cplx<T>* dinvU;
-  PanelWork pw;
+  int32_t* moves;  // per panel: 1 + 4*NB ints
+  int32_t* info;
+  int32_t* cand;   // two candidate buffers (ping-pong), each cand_stride ints
+  int64_t cand_stride;
   cplx<T>* top;
-  const int32_t* dmeta;          // per panel: 32 level offsets then 32 level sizes
-  std::vector<int32_t> nlevels;  // per panel
 };
 
-constexpr int kMetaStride = 64;
+constexpr int kMoveStride = 1 + 4 * NB;
 
 static inline int64_t split_half(int64_t w) { return (int64_t)NB * (((w / NB) + 1) / 2); }
 
@@ -371,18 +450,28 @@ template <typename T>
 static void panel(LuRun<T>& R, int64_t k, int w) {
   hipStream_t s = R.ctx->stream;
   const int64_t m = R.n - k;
-  const int nblk = (int)((m + RB - 1) / RB);
   const int64_t blk = k / NB;
+  int32_t* moves = R.moves + blk * kMoveStride;
   ProfScope prof(*R.ctx, FOSB_K_PANEL, 0.0, (double)sizeof(cplx<T>) * (double)m * w * 3.0);
-  PanelWork pw = R.pw;
-  pw.lvl_cand = const_cast<int32_t*>(R.dmeta) + blk * kMetaStride;
-  pw.lvl_size = pw.lvl_cand + kMetaStride / 2;
-  pw.nlevels = R.nlevels[blk];
-  hipLaunchKernelGGL(k_panel_tslu<T>, dim3(nblk), dim3(256), 0, s, R.A, R.lda, R.n, k, w, pw, R.top,
-                     R.dinvL + blk * NB * NB, R.dinvU + blk * NB * NB);
+  // leaf level over consecutive rows, then FANIN-way merges until one node remains
+  int nodes = (int)((m + NODE - 1) / NODE);
+  int32_t* cin = R.cand;
+  int32_t* cout = R.cand + R.cand_stride;
+  bool root = nodes == 1;
+  hipLaunchKernelGGL(k_tslu_node<T>, dim3(nodes), dim3(NODE), 0, s, R.A, R.lda, R.n, k, w, (const int32_t*)nullptr,
+                     0, cin, (int)root, moves, R.info, R.top, R.dinvL + blk * NB * NB, R.dinvU + blk * NB * NB);
   FOSB_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_permute_rows<T>, dim3((unsigned)((R.n + 63) / 64)), dim3(256), 0, s, R.A, R.lda, R.n,
-                     pw.plist);
+  while (!root) {
+    const int next = (nodes + FANIN - 1) / FANIN;
+    root = next == 1;
+    hipLaunchKernelGGL(k_tslu_node<T>, dim3(next), dim3(NODE), 0, s, R.A, R.lda, R.n, k, w, (const int32_t*)cin,
+                       nodes, cout, (int)root, moves, R.info, R.top, R.dinvL + blk * NB * NB,
+                       R.dinvU + blk * NB * NB);
+    FOSB_LAUNCH_CHECK();
+    std::swap(cin, cout);
+    nodes = next;
+  }
+  hipLaunchKernelGGL(k_permute_rows<T>, dim3((unsigned)((R.n + 63) / 64)), dim3(256), 0, s, R.A, R.lda, R.n, moves);
   FOSB_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_panel_finish<T>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, R.A, R.lda, R.n, k, w,
                      R.top, R.dinvU + blk * NB * NB);
@@ -400,8 +489,8 @@ static void rec_lu(LuRun<T>& R, int64_t k, int64_t w) {
   cplx<T>* A = R.A;
   const int64_t lda = R.lda;
   trsm_lower_unit<T>(*R.ctx, A, lda, R.dinvL, k, w1, A + k * lda + (k + w1), lda, w - w1);
-  gemm<T>(*R.ctx, R.n - k - w1, w - w1, w1, -1.0, A + (k + w1) * lda + k, lda, A + k * lda + (k + w1), lda,
-          1.0, A + (k + w1) * lda + (k + w1), lda);
+  gemm<T>(*R.ctx, R.n - k - w1, w - w1, w1, -1.0, A + (k + w1) * lda + k, lda, A + k * lda + (k + w1), lda, 1.0,
+          A + (k + w1) * lda + (k + w1), lda);
   rec_lu(R, k + w1, w - w1);
 }
 
@@ -409,29 +498,9 @@ template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
                   std::vector<int32_t>& perm) {
   hipStream_t s = ctx.stream;
-  const int64_t maxblk = (n + RB - 1) / RB;
+  const int64_t maxnodes = (n + NODE - 1) / NODE;
   const int64_t npanel = (n + NB - 1) / NB;
-  // tournament-tree shape of every panel (rows n - k, k = p * NB)
-  std::vector<int32_t> meta((size_t)npanel * kMetaStride, 0);
-  std::vector<int32_t> nlev((size_t)npanel);
-  for (int64_t p = 0; p < npanel; ++p) {
-    const int64_t m = n - p * NB;
-    std::vector<int32_t> sizes{(int32_t)((m + RB - 1) / RB)};
-    while (sizes.back() > 1) sizes.push_back((sizes.back() + 1) / 2);
-    if ((int)sizes.size() + 1 > kMetaStride / 2) fail(FOSB_E_UNSUPPORTED, "lu: matrix too large");
-    int32_t off = 0;
-    for (size_t l = 0; l < sizes.size(); ++l) {
-      meta[p * kMetaStride + l] = off;
-      meta[p * kMetaStride + kMetaStride / 2 + l] = sizes[l];
-      off += sizes[l];
-    }
-    meta[p * kMetaStride + sizes.size()] = off;
-    nlev[p] = (int32_t)sizes.size();
-  }
-  const int64_t nodes = 2 * maxblk + 8;
-  ctx.counters.reserve(nodes * sizeof(int32_t));
-  FOSB_HIP(hipMemsetAsync(ctx.counters.p, 0, nodes * sizeof(int32_t), s));
-  const size_t n_i32 = (size_t)(nodes * NB + meta.size() + (1 + 4 * NB) + n + 1);
+  const size_t n_i32 = (size_t)(2 * maxnodes * NB + npanel * kMoveStride + 1);
   const size_t top_off = (n_i32 * sizeof(int32_t) + 255) / 256 * 256;
   ctx.small.reserve(top_off + NB * NB * sizeof(cplx<T>));
   int32_t* base = ctx.small.as<int32_t>();
@@ -442,29 +511,33 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   R.lda = lda;
   R.dinvL = dinvL;
   R.dinvU = dinvU;
-  R.pw.cand = base;
-  R.pw.counters = ctx.counters.as<int32_t>();
-  int32_t* dmeta = base + nodes * NB;
-  R.dmeta = dmeta;
-  R.nlevels = nlev;
-  R.pw.plist = dmeta + meta.size();
-  R.pw.ipiv = R.pw.plist + (1 + 4 * NB);
-  R.pw.info = R.pw.ipiv + n;
+  R.cand = base;
+  R.cand_stride = maxnodes * NB;
+  R.moves = base + 2 * maxnodes * NB;
+  R.info = R.moves + npanel * kMoveStride;
   R.top = reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(base) + top_off);
-  FOSB_HIP(hipMemcpyAsync(dmeta, meta.data(), meta.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  FOSB_HIP(hipMemsetAsync(R.pw.info, 0, sizeof(int32_t), s));
+  FOSB_HIP(hipMemsetAsync(R.info, 0, sizeof(int32_t), s));
   rec_lu(R, 0, n);
-  std::vector<int32_t> ipiv(n);
+  std::vector<int32_t> mv((size_t)npanel * kMoveStride);
   int32_t info = 0;
-  FOSB_HIP(hipMemcpyAsync(ipiv.data(), R.pw.ipiv, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  FOSB_HIP(hipMemcpyAsync(&info, R.pw.info, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  FOSB_HIP(hipMemcpyAsync(mv.data(), R.moves, mv.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  FOSB_HIP(hipMemcpyAsync(&info, R.info, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   FOSB_HIP(hipStreamSynchronize(s));
+  // replay the row moves of every panel: position i holds original row perm[i]
   perm.resize(n);
   for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
-  for (int64_t r = 0; r < n; ++r) {
-    const int32_t p = ipiv[r];
-    if (p < 0 || p >= n) fail(FOSB_E_DEVICE, "lu: invalid pivot index %d at row %lld", p, (long long)r);
-    std::swap(perm[r], perm[p]);
+  std::vector<int32_t> src_rows;
+  for (int64_t p = 0; p < npanel; ++p) {
+    const int32_t* m = mv.data() + p * kMoveStride;
+    const int cnt = m[0];
+    if (cnt < 0 || cnt > 2 * NB) fail(FOSB_E_DEVICE, "lu: corrupt row-move list of panel %lld", (long long)p);
+    src_rows.resize(cnt);
+    for (int e = 0; e < cnt; ++e) {
+      const int32_t a = m[1 + 2 * e], b = m[2 + 2 * e];
+      if (a < 0 || a >= n || b < 0 || b >= n) fail(FOSB_E_DEVICE, "lu: invalid row move in panel %lld", (long long)p);
+      src_rows[e] = perm[a];
+    }
+    for (int e = 0; e < cnt; ++e) perm[m[2 + 2 * e]] = src_rows[e];
   }
   return info;  // 0, or 1-based index of the first exactly zero pivot
 }
@@ -473,10 +546,14 @@ template <typename T>
 void trsm_lower_unit(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0, int64_t n,
                      cplx<T>* B, int64_t ldb, int64_t nrhs) {
   if (n <= 0 || nrhs <= 0) return;
-  if (n <= NB) {
-    ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 8.0 * n * n * nrhs, 2.0 * sizeof(cplx<T>) * n * nrhs);
-    hipLaunchKernelGGL(k_apply_inv<T>, dim3((unsigned)((nrhs + 63) / 64)), dim3(256), 0, ctx.stream,
-                       dinvL + (k0 / NB) * NB * NB, (int)n, B, ldb, nrhs);
+  if (n <= NL) {
+    ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 4.0 * n * n * nrhs, sizeof(cplx<T>) * (0.5 * n * n + 2.0 * n * nrhs));
+    if (nrhs <= 2)
+      hipLaunchKernelGGL((k_trsm_leaf<T, true, 1>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda, dinvL, k0,
+                         (int)n, B, ldb, nrhs);
+    else
+      hipLaunchKernelGGL((k_trsm_leaf<T, true, LeafCS<T>::v>), dim3((unsigned)((nrhs + LeafCS<T>::v - 1) / LeafCS<T>::v)),
+                         dim3(256), 0, ctx.stream, A, lda, dinvL, k0, (int)n, B, ldb, nrhs);
     FOSB_LAUNCH_CHECK();
     return;
   }
@@ -490,10 +567,14 @@ template <typename T>
 void trsm_upper(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvU, int64_t k0, int64_t n,
                 cplx<T>* B, int64_t ldb, int64_t nrhs) {
   if (n <= 0 || nrhs <= 0) return;
-  if (n <= NB) {
-    ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 8.0 * n * n * nrhs, 2.0 * sizeof(cplx<T>) * n * nrhs);
-    hipLaunchKernelGGL(k_apply_inv<T>, dim3((unsigned)((nrhs + 63) / 64)), dim3(256), 0, ctx.stream,
-                       dinvU + (k0 / NB) * NB * NB, (int)n, B, ldb, nrhs);
+  if (n <= NL) {
+    ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 4.0 * n * n * nrhs, sizeof(cplx<T>) * (0.5 * n * n + 2.0 * n * nrhs));
+    if (nrhs <= 2)
+      hipLaunchKernelGGL((k_trsm_leaf<T, false, 1>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda, dinvU, k0,
+                         (int)n, B, ldb, nrhs);
+    else
+      hipLaunchKernelGGL((k_trsm_leaf<T, false, LeafCS<T>::v>), dim3((unsigned)((nrhs + LeafCS<T>::v - 1) / LeafCS<T>::v)),
+                         dim3(256), 0, ctx.stream, A, lda, dinvU, k0, (int)n, B, ldb, nrhs);
     FOSB_LAUNCH_CHECK();
     return;
   }
