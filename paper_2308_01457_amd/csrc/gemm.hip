@@ -7,8 +7,8 @@
 // the operand sums being formed in registers from the staged tiles.
 //
 // Tiling: 256 threads (4 wave64) per workgroup, 128 x 64 output tile, each wave
-// owns a 64 x 32 sub-tile = 4 x 2 MFMA 16x16 blocks; K is staged 16 at a time
-// through LDS in planar (re/im) layout, A stored k-major so that a fragment
+// owns a 64 x 32 sub-tile = 4 x 2 MFMA 16x16 blocks; K is staged in slices
+// through double-buffered LDS in planar (re/im) layout, A stored k-major so that a fragment
 // load is 16 consecutive rows.  Operand fragments (16x16x4): lane l holds
 // A[l%16][k0 + l/16] and B[k0 + l/16][l%16]; accumulator element v (0..3) of
 // lane l is D[row][l%16] with row = 4*(l/16) + v for the FP32 instruction and
@@ -40,18 +40,25 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
 };
 
-constexpr int BM = 128, BN = 64, BK = 16;
+constexpr int BM = 128, BN = 64;
 constexpr int PADA = 4, PADB = 4;
+// K slice staged per LDS buffer: 16 (FP32) / 8 (FP64), two buffers, so one
+// barrier per slice and the next slice's global loads overlap the MFMAs.
+template <typename T> struct Slice { static constexpr int BK = 16; };
+template <> struct Slice<double> { static constexpr int BK = 8; };
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, const cplx<T>* __restrict__ A,
                                               int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb, T beta,
                                               cplx<T>* __restrict__ C, int64_t ldc) {
   using V4 = typename Mfma<T>::v4;
-  __shared__ T AsR[BK][BM + PADA];
-  __shared__ T AsI[BK][BM + PADA];
-  __shared__ T BsR[BK][BN + PADB];
-  __shared__ T BsI[BK][BN + PADB];
+  constexpr int BK = Slice<T>::BK;
+  constexpr int AE = BM * BK / 256;  // A elements staged per thread
+  constexpr int BE = BN * BK / 256;  // B elements staged per thread
+  __shared__ T AsR[2][BK][BM + PADA];
+  __shared__ T AsI[2][BK][BM + PADA];
+  __shared__ T BsR[2][BK][BN + PADB];
+  __shared__ T BsI[2][BK][BN + PADB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -62,36 +69,36 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   const int64_t n0 = (int64_t)blockIdx.x * BN;
 
   // global -> register staging assignment
-  const int a_row = tid >> 1;        // 0..127
-  const int a_k = (tid & 1) * 8;     // 0 or 8
-  const int b_k = tid >> 4;          // 0..15
-  const int b_col = (tid & 15) * 4;  // 0..60
+  const int a_row = tid / (BK / AE);
+  const int a_k = (tid % (BK / AE)) * AE;
+  const int b_k = tid / (BN / BE);
+  const int b_col = (tid % (BN / BE)) * BE;
 
-  cplx<T> ra[8], rb[4];
+  cplx<T> ra[AE], rb[BE];
   auto load_tiles = [&](int64_t k0) {
     const int64_t gr = m0 + a_row;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < AE; ++e) {
       const int64_t gk = k0 + a_k + e;
       ra[e] = (gr < M && gk < K) ? A[gr * lda + gk] : cplx<T>{T(0), T(0)};
     }
     const int64_t gk = k0 + b_k;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < BE; ++e) {
       const int64_t gc = n0 + b_col + e;
       rb[e] = (gk < K && gc < N) ? B[gk * ldb + gc] : cplx<T>{T(0), T(0)};
     }
   };
-  auto store_tiles = [&]() {
+  auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      AsR[a_k + e][a_row] = ra[e].re;
-      AsI[a_k + e][a_row] = ra[e].im;
+    for (int e = 0; e < AE; ++e) {
+      AsR[buf][a_k + e][a_row] = ra[e].re;
+      AsI[buf][a_k + e][a_row] = ra[e].im;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      BsR[b_k][b_col + e] = rb[e].re;
-      BsI[b_k][b_col + e] = rb[e].im;
+    for (int e = 0; e < BE; ++e) {
+      BsR[buf][b_k][b_col + e] = rb[e].re;
+      BsI[buf][b_k][b_col + e] = rb[e].im;
     }
   };
 
@@ -107,25 +114,20 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
 
   const int r16 = lane & 15;
   const int kq = lane >> 4;
-  load_tiles(0);
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();
-    store_tiles();
-    __syncthreads();
-    if (k0 + BK < K) load_tiles(k0 + BK);  // prefetch next tile into registers
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T ar[4], ai[4], as[4], br[2], bi[2], bs[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        ar[i] = AsR[kk + kq][wr * 64 + i * 16 + r16];
-        ai[i] = AsI[kk + kq][wr * 64 + i * 16 + r16];
+        ar[i] = AsR[buf][kk + kq][wr * 64 + i * 16 + r16];
+        ai[i] = AsI[buf][kk + kq][wr * 64 + i * 16 + r16];
         as[i] = ar[i] + ai[i];
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        br[j] = BsR[kk + kq][wc * 32 + j * 16 + r16];
-        bi[j] = BsI[kk + kq][wc * 32 + j * 16 + r16];
+        br[j] = BsR[buf][kk + kq][wc * 32 + j * 16 + r16];
+        bi[j] = BsI[buf][kk + kq][wc * 32 + j * 16 + r16];
         bs[j] = br[j] + bi[j];
       }
 #pragma unroll
@@ -136,6 +138,21 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
           t2[i][j] = Mfma<T>::op(ai[i], bi[j], t2[i][j]);
           t3[i][j] = Mfma<T>::op(as[i], bs[j], t3[i][j]);
         }
+    }
+  };
+
+  if (K > 0) {
+    load_tiles(0);
+    store_tiles(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+      const bool more = k0 + BK < K;
+      if (more) load_tiles(k0 + BK);  // next slice in flight during the MFMAs
+      compute(buf);
+      if (more) store_tiles(buf ^ 1);  // the other buffer was last read before the previous barrier
+      __syncthreads();
+      buf ^= 1;
     }
   }
 

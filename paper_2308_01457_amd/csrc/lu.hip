@@ -59,6 +59,38 @@ constexpr int NODE = 256;         // rows per tree node = threads per workgroup
 constexpr int NWAVE = NODE / 64;
 constexpr int FANIN = NODE / NB;  // children merged per node (8)
 
+// Maximum of a 64-bit key over the wavefront, returned to every lane: DPP
+// exchanges within each row of 16 lanes (xor 1, xor 2, half-row mirror, row
+// mirror), then the four row maxima through readlane.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  int hi = (int)(k >> 32), lo = (int)(unsigned)(k & 0xffffffffull);
+#define FOSB_DPP_MAX(ctrl)                                                               \
+  {                                                                                      \
+    const int ohi = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xf, 0xf, false);         \
+    const int olo = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xf, 0xf, false);         \
+    const unsigned long long o = ((unsigned long long)(unsigned)ohi << 32) | (unsigned)olo; \
+    const unsigned long long c = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;   \
+    if (o > c) {                                                                         \
+      hi = ohi;                                                                          \
+      lo = olo;                                                                          \
+    }                                                                                    \
+  }
+  FOSB_DPP_MAX(0xB1)   // quad_perm [1,0,3,2]
+  FOSB_DPP_MAX(0x4E)   // quad_perm [2,3,0,1]
+  FOSB_DPP_MAX(0x141)  // row_half_mirror
+  FOSB_DPP_MAX(0x140)  // row_mirror
+#undef FOSB_DPP_MAX
+  unsigned long long m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned h = (unsigned)__builtin_amdgcn_readlane(hi, 16 * r);
+    const unsigned l = (unsigned)__builtin_amdgcn_readlane(lo, 16 * r);
+    const unsigned long long x = ((unsigned long long)h << 32) | l;
+    m = x > m ? x : m;
+  }
+  return m;
+}
+
 template <typename T>
 __device__ __forceinline__ unsigned long long pivot_key(cplx<T> v, int row) {
   const float m = (float)cabs1(v);
@@ -78,12 +110,7 @@ __device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvali
   step = -1;
   for (int j = 0; j < steps; ++j) {
     const int b = j & 1;
-    unsigned long long key = (valid && step < 0) ? pivot_key(a[0], tid) : 0ull;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(key, off, 64);
-      key = o > key ? o : key;
-    }
+    unsigned long long key = wave_max_u64((valid && step < 0) ? pivot_key(a[0], tid) : 0ull);
     if (lane == 0) skey[b][wave] = key;
     __syncthreads();
 #pragma unroll
@@ -95,29 +122,41 @@ __device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvali
     if (tid == r) {
       step = j;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        prow[b][c] = a[c];
-        const int col = c < NB - j ? j + c : c - (NB - j);
-        lu[j][col] = a[c];
-      }
+      for (int c = 0; c < NB; ++c) prow[b][c] = a[c];
     }
     __syncthreads();
     const cplx<T> piv = prow[b][0];
     if (piv.re == T(0) && piv.im == T(0) && zero_col < 0) zero_col = j;
     if (valid && step < 0) {
       const cplx<T> l = cmul(a[0], cinv(piv));
-      const int wr = w - j;  // live columns of this step
+      // slots c >= NB - j of the pivot row hold its multipliers: masked out
+      // (branch-free); the pivot row is read from LDS eight columns at a time
 #pragma unroll
-      for (int c = 1; c < NB; ++c) {
-        if (c < wr) {
-          const cplx<T> u = prow[b][c];
-          a[c].re -= l.re * u.re - l.im * u.im;
-          a[c].im -= l.re * u.im + l.im * u.re;
+      for (int c0 = 0; c0 < NB; c0 += 8) {
+        cplx<T> u[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) u[e] = prow[b][c0 + e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int c = c0 + e;
+          if (c == 0) continue;
+          const bool live = c < NB - j;
+          const T ur = live ? u[e].re : T(0), ui = live ? u[e].im : T(0);
+          a[c].re -= l.re * ur - l.im * ui;
+          a[c].im -= l.re * ui + l.im * ur;
         }
       }
 #pragma unroll
       for (int c = 0; c < NB - 1; ++c) a[c] = a[c + 1];
       a[NB - 1] = l;
+    }
+  }
+  // chosen rows stopped rotating at their step: write them as rows of L\U
+  if (step >= 0) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int col = c < NB - step ? step + c : c - (NB - step);
+      lu[step][col] = a[c];
     }
   }
   __syncthreads();
@@ -309,37 +348,41 @@ __global__ __launch_bounds__(256) void k_permute_rows(cplx<T>* __restrict__ A, i
     for (int e = g; e < cnt; e += 4) A[(int64_t)plist[2 + 2 * e] * lda + c] = buf[e][threadIdx.x & 63];
 }
 
-// Write L11\U11 into the diagonal block and form A21 U11^{-1} below it.
+// Write L11\U11 into the diagonal block and form A21 U11^{-1} below it; four
+// threads per row, each producing eight of the row's 32 columns.
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel_finish(cplx<T>* __restrict__ A, int64_t lda, int64_t n, int64_t k,
                                                       int w, const cplx<T>* __restrict__ top,
                                                       const cplx<T>* __restrict__ invU) {
-  __shared__ cplx<T> su[NB][NB];
+  __shared__ cplx<T> su[NB][NB + 1];
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) su[e / NB][e % NB] = invU[e];
-  __syncthreads();
-  const int64_t r = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  const int64_t r = k + (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2);
+  const int q = threadIdx.x & 3;
   cplx<T>* row = A + r * lda + k;
+  cplx<T> a[NB];
+  const bool live = r < n && r >= k + w;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) a[c] = (live && c < w) ? row[c] : cplx<T>{T(0), T(0)};
+  __syncthreads();  // every thread has read its row before any is overwritten
+  if (r >= n) return;
   if (r < k + w) {
     const int rr = (int)(r - k);
-    for (int c = 0; c < w; ++c) row[c] = top[rr * NB + c];
+    for (int c = q; c < w; c += 4) row[c] = top[rr * NB + c];
     return;
   }
-  cplx<T> a[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) a[c] = c < w ? row[c] : cplx<T>{T(0), T(0)};
+  for (int cc = 0; cc < NB / 4; ++cc) {
+    const int c = q + 4 * cc;
+    T xr = 0, xi = 0;
 #pragma unroll
-  for (int c = NB - 1; c >= 0; --c) {
-    if (c < w) {
-      T xr = 0, xi = 0;
-#pragma unroll
-      for (int t = 0; t <= c; ++t) {
+    for (int t = 0; t < NB; ++t) {
+      if (t <= c) {
         const cplx<T> u = su[t][c];
         xr += a[t].re * u.re - a[t].im * u.im;
         xi += a[t].re * u.im + a[t].im * u.re;
       }
-      row[c] = cplx<T>{xr, xi};
     }
+    if (c < w) row[c] = cplx<T>{xr, xi};
   }
 }
 
@@ -473,7 +516,7 @@ static void panel(LuRun<T>& R, int64_t k, int w) {
   }
   hipLaunchKernelGGL(k_permute_rows<T>, dim3((unsigned)((R.n + 63) / 64)), dim3(256), 0, s, R.A, R.lda, R.n, moves);
   FOSB_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_panel_finish<T>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, R.A, R.lda, R.n, k, w,
+  hipLaunchKernelGGL(k_panel_finish<T>, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, R.A, R.lda, R.n, k, w,
                      R.top, R.dinvU + blk * NB * NB);
   FOSB_LAUNCH_CHECK();
 }
