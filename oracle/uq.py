@@ -251,15 +251,17 @@ def adjoint_maps(l: Level, xh: np.ndarray) -> np.ndarray:
 
 
 def summed_variance_and_gradient(levels: dict[int, Level], L0: int, L: int, kind: str, sigma: float,
-                                 ell: float, xh: np.ndarray):
-    """S = sum_{c,i} V_c(x_i) and (dS/dsigma, dS/dell) through the linearity of
-    S in K:  S = sum_pairs sign*mult*Re sum_ab K_ab G_ab,  G = P1^T conj(P2)."""
+                                 ell: float, xh: np.ndarray, weights: np.ndarray | None = None):
+    """S = sum_{c,i} g_{c,i} V_c(x_i) (g = 1 unless weights (3, n_a) are given)
+    and (dS/dsigma, dS/dell) through the linearity of S in K:
+        S = sum_pairs sign*mult*Re sum_ab K_ab G_ab,  G = P1^T diag(g) conj(P2)."""
     P = {s: adjoint_maps(levels[s], xh) for s in levels}
+    g = np.ones(3 * xh.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64).reshape(-1)
     S = 0.0
     dsig = 0.0
     dell = 0.0
     for l1, l2, sgn, mult in ct_pairs(L0, L):
-        G = P[l1].T @ P[l2].conj()
+        G = P[l1].T @ (g[:, None] * P[l2].conj())
         a, b = levels[l1], levels[l2]
         K = covariance(kind, sigma, ell, a.X, a.Nq, b.X, b.Nq)
         dK = covariance_dell(kind, sigma, ell, a.X, a.Nq, b.X, b.Nq)

@@ -158,3 +158,20 @@ def test_adjoint_route_and_gradient(oracle_levels):
         Sm, _ = uq.summed_variance_and_gradient(levels, 0, 2, kind, sig, ell - h, xh)
         fd = (Sp - Sm) / (2 * h)
         assert abs(fd - g[1]) < 1e-6 * abs(g[1]), (fd, g[1])
+
+
+def test_weighted_adjoint_route(oracle_levels):
+    """With upstream weights g: sum g V (Sigma route) equals the adjoint-route S,
+    and dS/dell matches a central difference of the Sigma route."""
+    xh = workloads.angles_xz(13)
+    levels = {s: oracle_levels(s) for s in (0, 1, 2)}
+    g = np.random.default_rng(3).standard_normal((3, 13))
+    sig, ell = 0.02, 0.4
+    V, _, _, _, _ = uq.second_moment(None, 1.0, 0, 2, "gaussian", sig, ell, xh, levels=levels)
+    S, grad = uq.summed_variance_and_gradient(levels, 0, 2, "gaussian", sig, ell, xh, weights=g)
+    assert abs(S - np.sum(g * V)) < 1e-10 * np.sum(np.abs(g * V))
+    h = 1e-5
+    Vp = uq.second_moment(None, 1.0, 0, 2, "gaussian", sig, ell + h, xh, levels=levels)[0]
+    Vm = uq.second_moment(None, 1.0, 0, 2, "gaussian", sig, ell - h, xh, levels=levels)[0]
+    fd = np.sum(g * (Vp - Vm)) / (2 * h)
+    assert abs(fd - grad[1]) < 1e-6 * abs(grad[1]), (fd, grad[1])
