@@ -159,6 +159,12 @@ fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precis
  * levels refine in FP64 against the kept Z.  stats may be NULL. */
 fosb_status fosb_level_solve(fosb_context* ctx, const fosb_level* level, void* B, int64_t ldb,
                              int64_t nrhs, fosb_stats* stats);
+/* B <- Z^{-H} B (device complex128, N x nrhs, row stride ldb >= nrhs): the
+ * adjoint solve behind the gradient of the two-sided solve (P Z = L U gives
+ * Z^{-H} = P^T L^{-H} U^{-H}).  MIXED levels refine in FP64 against the kept
+ * Z (residual B - Z^H X).  stats may be NULL. */
+fosb_status fosb_level_solve_adjoint(fosb_context* ctx, const fosb_level* level, void* B, int64_t ldb,
+                                     int64_t nrhs, fosb_stats* stats);
 /* Copies the first-moment coefficients of direction dir into u (device, N complex128). */
 fosb_status fosb_level_first_moment(fosb_context* ctx, const fosb_level* level, int64_t dir, void* u);
 fosb_status fosb_level_destroy(fosb_level* level);
@@ -204,6 +210,27 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
                                    int32_t n_levels, int32_t L0, int32_t L, void* const* blocks,
                                    const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir,
                                    double* var, void* mean_F);
+
+/* Adjoint of the combination-technique variance with respect to the
+ * covariance parameters.  With upstream weights g = dvar (device, 3 n_a
+ * float64, same layout as var) and S = sum_r g_r var_r:
+ *   S = sum_{Lambda_H} sign mult sum_{q,q'} K(x_q, y_q') Re G[q][q'],
+ *   G = P_l1^T diag(g) conj(P_l2),  P_l = FF_l Z_l^{-1} Wgt_l  (3 n_a x Q_l),
+ * because var is linear in C = Wgt_l1 K Wgt_l2^H (FOA section, second-moment
+ * tensor equation; combination-technique sub-systems).  P_l is formed from the
+ * adjoint solve Z_l^{-H} FF_l^H, so one solve with 3 n_a right-hand sides per
+ * level replaces the pair solves.  out (device, 3 float64) receives
+ *   out[0] = dS/dsigma,  out[1] = dS/dell,  out[2] = S  (the adjoint-route value,
+ * equal to sum_r g_r var_r of fosb_far_field_moments up to rounding).
+ * levels and xhat (host, n_a x 3 unit vectors) as for fosb_far_field_moments;
+ * the levels must still hold their factors.  Device scratch of about
+ * 3 (Q_l1 + Q_l2) 3 n_a + min(Q_l1 Q_l2, 2^26) complex128 values per pair is
+ * allocated by the context.  E_INVALID on bad arguments; E_NOCONV as for the
+ * refined solves. */
+fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level* const* levels,
+                                            int32_t n_levels, int32_t L0, int32_t L, const fosb_cov* cov,
+                                            const double* xhat, int64_t n_a, int64_t dir,
+                                            const double* dvar, double* out, fosb_stats* stats);
 
 /* ---------------------------------------------------------------- profiling */
 /* Kernel classes timed by the profiler. */

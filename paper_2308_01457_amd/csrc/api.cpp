@@ -42,20 +42,30 @@ static fosb_opts opts_or_default(const fosb_opts* o) {
 static void bind(Context& ctx) { FOSB_HIP(hipSetDevice(ctx.device)); }
 
 // ------------------------------------------------------------------ level solve
-// B <- Z^{-1} B for a factorised level; MIXED levels refine in FP64.
-void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st) {
+// B <- Z^{-1} B (or Z^{-H} B) for a factorised level; MIXED levels refine in FP64.
+// With P Z = L U:  Z^{-1} = U^{-1} L^{-1} P  and  Z^{-H} = P^T L^{-H} U^{-H}.
+void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st,
+                         bool adjoint) {
   hipStream_t s = ctx.stream;
   const int64_t n = L.n;
   if (nrhs <= 0) return;
   const size_t bytes128 = (size_t)n * nrhs * sizeof(c128);
+  const int32_t* perm = L.d_perm.as<int32_t>();
   ctx.scratch[1].reserve(bytes128);
   c128* T = ctx.scratch[1].as<c128>();
   if (L.precision == FOSB_PREC_FP64) {
-    permute_rows_gather(s, L.d_perm.as<int32_t>(), B, ldb, T, nrhs, n, nrhs);
     const c128* A = static_cast<const c128*>(L.Z);
-    trsm_lower_unit<double>(ctx, A, L.ldz, L.dinv_L.as<c128>(), 0, n, T, nrhs, nrhs);
-    trsm_upper<double>(ctx, A, L.ldz, L.dinv_U.as<c128>(), 0, n, T, nrhs, nrhs);
-    copy_c128(s, T, nrhs, B, ldb, n, nrhs);
+    if (!adjoint) {
+      permute_rows_gather(s, perm, B, ldb, T, nrhs, n, nrhs);
+      trsm_lower_unit<double>(ctx, A, L.ldz, L.dinv_L.as<c128>(), 0, n, T, nrhs, nrhs);
+      trsm_upper<double>(ctx, A, L.ldz, L.dinv_U.as<c128>(), 0, n, T, nrhs, nrhs);
+      copy_c128(s, T, nrhs, B, ldb, n, nrhs);
+    } else {
+      copy_c128(s, B, ldb, T, nrhs, n, nrhs);
+      trsm_upper_ch<double>(ctx, A, L.ldz, L.dinv_U.as<c128>(), 0, n, T, nrhs, nrhs);
+      trsm_lower_unit_ch<double>(ctx, A, L.ldz, L.dinv_L.as<c128>(), 0, n, T, nrhs, nrhs);
+      permute_rows_scatter(s, perm, T, nrhs, B, ldb, n, nrhs);
+    }
     if (st) st->ir_sweeps = std::max(st->ir_sweeps, 0);
     return;
   }
@@ -63,10 +73,12 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   ctx.scratch[2].reserve(bytes128);
   ctx.scratch[3].reserve(bytes128);
   ctx.scratch[4].reserve((size_t)n * nrhs * sizeof(c64));
+  ctx.scratch[5].reserve(bytes128);
   ctx.norms.reserve(2 * sizeof(double));
   c128* Bo = ctx.scratch[2].as<c128>();
   c128* X = ctx.scratch[3].as<c128>();
   c64* R32 = ctx.scratch[4].as<c64>();
+  c128* Rw = ctx.scratch[5].as<c128>();
   const c64* A32 = static_cast<const c64*>(L.Zlow);
   const c128* Z64 = static_cast<const c128*>(L.Z);
   copy_c128(s, B, ldb, Bo, nrhs, n, nrhs);
@@ -74,17 +86,28 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   double prev = INFINITY, rel = INFINITY;
   int sweeps = 0;
   for (int it = 0;; ++it) {
-    permute_rows_gather(s, L.d_perm.as<int32_t>(), R, nrhs, T, nrhs, n, nrhs);
-    copy_c128_to_c64(s, T, nrhs, R32, nrhs, n, nrhs);
-    trsm_lower_unit<float>(ctx, A32, L.ldzlow, L.dinv_L.as<c64>(), 0, n, R32, nrhs, nrhs);
-    trsm_upper<float>(ctx, A32, L.ldzlow, L.dinv_U.as<c64>(), 0, n, R32, nrhs, nrhs);
-    copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
-    if (it == 0) {
-      copy_c128(s, T, nrhs, X, nrhs, n, nrhs);
+    c128* D;  // this sweep's correction
+    if (!adjoint) {
+      permute_rows_gather(s, perm, R, nrhs, T, nrhs, n, nrhs);
+      copy_c128_to_c64(s, T, nrhs, R32, nrhs, n, nrhs);
+      trsm_lower_unit<float>(ctx, A32, L.ldzlow, L.dinv_L.as<c64>(), 0, n, R32, nrhs, nrhs);
+      trsm_upper<float>(ctx, A32, L.ldzlow, L.dinv_U.as<c64>(), 0, n, R32, nrhs, nrhs);
+      copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
+      D = T;
     } else {
-      axpy_c128(s, T, nrhs, X, nrhs, n, nrhs);
+      copy_c128_to_c64(s, R, nrhs, R32, nrhs, n, nrhs);
+      trsm_upper_ch<float>(ctx, A32, L.ldzlow, L.dinv_U.as<c64>(), 0, n, R32, nrhs, nrhs);
+      trsm_lower_unit_ch<float>(ctx, A32, L.ldzlow, L.dinv_L.as<c64>(), 0, n, R32, nrhs, nrhs);
+      copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
+      permute_rows_scatter(s, perm, T, nrhs, Rw, nrhs, n, nrhs);  // R (if it was Rw) is consumed
+      D = Rw;
     }
-    norms2_c128(s, T, nrhs, X, nrhs, n, nrhs, ctx.norms.as<double>());
+    if (it == 0) {
+      copy_c128(s, D, nrhs, X, nrhs, n, nrhs);
+    } else {
+      axpy_c128(s, D, nrhs, X, nrhs, n, nrhs);
+    }
+    norms2_c128(s, D, nrhs, X, nrhs, n, nrhs, ctx.norms.as<double>());
     double nn[2];
     FOSB_HIP(hipMemcpyAsync(nn, ctx.norms.p, sizeof(nn), hipMemcpyDeviceToHost, s));
     FOSB_HIP(hipStreamSynchronize(s));
@@ -92,11 +115,12 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     if (it > 0) sweeps = it;
     if (rel <= L.opts.ir_tol || it >= L.opts.ir_max_sweeps || (it > 1 && rel >= prev)) break;
     prev = rel;
-    // residual R = Bo - Z64 X in FP64 (scratch[5]; the next gather reads it into scratch[1])
-    ctx.scratch[5].reserve(bytes128);
-    c128* Rw = ctx.scratch[5].as<c128>();
+    // residual R = Bo - op(Z64) X in FP64 (scratch[5])
     copy_c128(s, Bo, nrhs, Rw, nrhs, n, nrhs);
-    gemm<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
+    if (!adjoint)
+      gemm<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
+    else
+      gemm_ch<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
     R = Rw;
   }
   copy_c128(s, X, nrhs, B, ldb, n, nrhs);
@@ -367,6 +391,18 @@ fosb_status fosb_level_solve(fosb_context* ctx, const fosb_level* level, void* B
   API_END
 }
 
+fosb_status fosb_level_solve_adjoint(fosb_context* ctx, const fosb_level* level, void* B, int64_t ldb, int64_t nrhs,
+                                     fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && level && B, "ctx/level/B is NULL");
+  REQUIRE(level->ctx == ctx, "level belongs to another context");
+  REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+  if (ldb < nrhs) fail(FOSB_E_WORKSPACE, "ldb < nrhs");
+  bind(*ctx);
+  level_solve_inplace(*ctx, *level, static_cast<c128*>(B), ldb, nrhs, stats, true);
+  API_END
+}
+
 fosb_status fosb_level_first_moment(fosb_context* ctx, const fosb_level* level, int64_t dir, void* u) {
   API_BEGIN
   REQUIRE(ctx && level && u, "ctx/level/u is NULL");
@@ -583,3 +619,79 @@ fosb_status fosb_profile_read(fosb_context* ctx, int32_t cls, int64_t* launches,
 }
 
 }  // extern "C"
+
+fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                                            int32_t L0, int32_t L, const fosb_cov* cov, const double* xhat,
+                                            int64_t n_a, int64_t dir, const double* dvar, double* out,
+                                            fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && levels && xhat && dvar && out, "NULL argument");
+  REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  check_cov(cov);
+  for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
+  for (int64_t i = 0; i < n_a; ++i) {
+    double nn = xhat[3 * i] * xhat[3 * i] + xhat[3 * i + 1] * xhat[3 * i + 1] + xhat[3 * i + 2] * xhat[3 * i + 2];
+    REQUIRE(std::fabs(nn - 1.0) < 1e-9, "xhat[%lld] is not a unit vector", (long long)i);
+  }
+  bind(*ctx);
+  hipStream_t s = ctx->stream;
+  std::vector<double> x(xhat, xhat + 3 * n_a);
+  DevBuf dx;
+  upload(dx, x, s);
+  const int64_t R = 3 * n_a;
+  // per level: Hn = (FF Z^{-1} Wgt)^T (Q x R) and Bg = diag(g) conj(FF Z^{-1} Wgt) (R x Q)
+  std::vector<DevBuf> Hn(n_levels), Bg(n_levels);
+  {
+    DevBuf FF, Y;
+    for (int32_t i = 0; i < n_levels; ++i) {
+      const fosb_level& l = *levels[i];
+      const int64_t N = l.n, Q = 6LL * l.mesh->h.nt;
+      FF.reserve((size_t)R * N * sizeof(c128));
+      Y.reserve((size_t)N * R * sizeof(c128));
+      far_field_matrix_kernel(s, *l.mesh, l.k, dx.as<double>(), n_a, FF.as<c128>());
+      conj_transpose_c128(s, FF.as<c128>(), N, Y.as<c128>(), R, R, N);           // Y = FF^H (N x R)
+      level_solve_inplace(*ctx, l, Y.as<c128>(), R, R, stats, true);           // Y = Z^{-H} FF^H
+      Hn[i].alloc((size_t)Q * R * sizeof(c128));
+      Bg[i].alloc((size_t)R * Q * sizeof(c128));
+      adjoint_nodes(s, *l.mesh, l.W.as<c128>() + dir * l.mesh->h.nt * 18, Y.as<c128>(), R, Hn[i].as<c128>());
+      conj_transpose_c128(s, Hn[i].as<c128>(), R, Bg[i].as<c128>(), Q, Q, R, dvar);
+    }
+    FOSB_HIP(hipStreamSynchronize(s));
+  }
+  // G = Hn_l1 Bg_l2 in row chunks of at most 2^26 entries, reduced against the covariance
+  auto v = ct_pairs_vec(L0, L);
+  const int64_t budget = (int64_t)1 << 26;
+  auto chunk_rows = [&](int64_t Q1, int64_t Q2) {
+    int64_t ch = std::max<int64_t>(16, budget / Q2) / 16 * 16;
+    return std::min<int64_t>(ch, Q1);
+  };
+  int64_t n_part = 0, g_max = 0;
+  for (auto& q : v) {
+    const int64_t Q1 = 6LL * levels[q[0] - L0]->mesh->h.nt, Q2 = 6LL * levels[q[1] - L0]->mesh->h.nt;
+    const int64_t ch = chunk_rows(Q1, Q2);
+    g_max = std::max(g_max, ch * Q2);
+    for (int64_t a0 = 0; a0 < Q1; a0 += ch) n_part += ((Q2 + 255) / 256) * ((std::min(ch, Q1 - a0) + 15) / 16);
+  }
+  DevBuf Gb((size_t)g_max * sizeof(c128));
+  DevBuf part((size_t)2 * n_part * sizeof(double));
+  int64_t off = 0;
+  for (auto& q : v) {
+    const fosb_level& l1 = *levels[q[0] - L0];
+    const fosb_level& l2 = *levels[q[1] - L0];
+    const int64_t Q1 = 6LL * l1.mesh->h.nt, Q2 = 6LL * l2.mesh->h.nt;
+    const int64_t ch = chunk_rows(Q1, Q2);
+    for (int64_t a0 = 0; a0 < Q1; a0 += ch) {
+      const int64_t na = std::min(ch, Q1 - a0);
+      gemm<double>(*ctx, na, Q2, R, 1.0, Hn[q[0] - L0].as<c128>() + a0 * R, R, Bg[q[1] - L0].as<c128>(), Q2, 0.0,
+                   Gb.as<c128>(), Q2);
+      off += cov_grad_partials(s, Gb.as<c128>(), a0, na, l1, l2, *cov, (double)(q[2] * q[3]),
+                               part.as<double>() + 2 * off);
+    }
+  }
+  if (off != n_part) fail(FOSB_E_DEVICE, "backward: partial count mismatch");
+  cov_grad_finish(s, part.as<double>(), n_part, cov->sigma, out);
+  FOSB_HIP(hipStreamSynchronize(s));
+  API_END
+}

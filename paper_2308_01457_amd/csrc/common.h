@@ -203,6 +203,10 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
 template <typename T>
 void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
           const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc);
+// C = beta*C + alpha*A^H*B; A is stored K x M (row-major, leading dimension lda)
+template <typename T>
+void gemm_ch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
+             const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc);
 // lu.hip
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
@@ -213,13 +217,24 @@ void trsm_lower_unit(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>*
 template <typename T>
 void trsm_upper(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvU, int64_t k0, int64_t n,
                 cplx<T>* B, int64_t ldb, int64_t nrhs);
+// B <- U^{-H} B and B <- L^{-H} B with the same stored factors
+template <typename T>
+void trsm_upper_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvU, int64_t k0, int64_t n,
+                   cplx<T>* B, int64_t ldb, int64_t nrhs);
+template <typename T>
+void trsm_lower_unit_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0, int64_t n,
+                        cplx<T>* B, int64_t ldb, int64_t nrhs);
 void permute_rows_gather(hipStream_t s, const int32_t* perm, const c128* src, int64_t lds, c128* dst,
                          int64_t ldd, int64_t n, int64_t ncols);
+// dst[perm[i]] = src[i]
+void permute_rows_scatter(hipStream_t s, const int32_t* perm, const c128* src, int64_t lds, c128* dst,
+                          int64_t ldd, int64_t n, int64_t ncols);
 void copy_c128_to_c64(hipStream_t s, const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int64_t cols);
 void copy_c64_to_c128(hipStream_t s, const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int64_t cols);
 void copy_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int64_t cols);
+// dst = diag(row_scale) src^H (row_scale: device, one per dst row, or nullptr)
 void conj_transpose_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows,
-                         int64_t cols);
+                         int64_t cols, const double* row_scale = nullptr);
 void axpy_c128(hipStream_t s, const c128* x, int64_t ldx, c128* y, int64_t ldy, int64_t rows, int64_t cols);
 // squared Frobenius norms of x and of y (two doubles written to out, device)
 void norms2_c128(hipStream_t s, const c128* x, int64_t ldx, const c128* y, int64_t ldy, int64_t rows,
@@ -238,8 +253,17 @@ void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const doubl
 void row_dot_re_accumulate(hipStream_t s, const c128* P, const c128* FF2, int64_t rows, int64_t n, double scale,
                            double* var);
 void matvec_rows(hipStream_t s, const c128* FF, int64_t rows, int64_t n, const c128* u, c128* out);
+// adjoint of the variance: node rows Hn (Q x R) of FF Z^{-1} Wgt from B = Z^{-H} FF^H (N x R)
+void adjoint_nodes(hipStream_t s, const Mesh& m, const c128* W, const c128* B, int64_t R, c128* Hn);
+// partial sums of kappa Re G and dkappa/dell Re G over rows [a0, a0 + na) of G (Q1 x Q2 block
+// of a pair); returns the number of partial pairs written
+int64_t cov_grad_partials(hipStream_t s, const c128* G, int64_t a0, int64_t na, const Level& l1, const Level& l2,
+                          const fosb_cov& cov, double scale, double* partial);
+void cov_grad_finish(hipStream_t s, const double* partial, int64_t n, double sigma, double* out);
 
 // level-wide solves (api.cpp helpers)
-void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st);
+// B <- Z^{-1} B, or B <- Z^{-H} B (adjoint)
+void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st,
+                         bool adjoint = false);
 
 }  // namespace fosb

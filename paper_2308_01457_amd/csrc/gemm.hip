@@ -1,5 +1,5 @@
-// Complex GEMM on CDNA matrix cores:  C = beta*C + alpha*A*B  (row-major,
-// interleaved complex, real alpha/beta).  FP64 uses v_mfma_f64_16x16x4f64,
+// Complex GEMM on CDNA matrix cores:  C = beta*C + alpha*op(A)*B  (row-major,
+// interleaved complex, real alpha/beta; op(A) = A or its conjugate transpose).  FP64 uses v_mfma_f64_16x16x4f64,
 // FP32 uses v_mfma_f32_16x16x4f32.  The complex product is formed with three
 // real products (Higham's 3M form):
 //   T1 = Ar Br,  T2 = Ai Bi,  T3 = (Ar + Ai)(Br + Bi),
@@ -47,7 +47,7 @@ constexpr int PADA = 4, PADB = 4;
 template <typename T> struct Slice { static constexpr int BK = 16; };
 template <> struct Slice<double> { static constexpr int BK = 8; };
 
-template <typename T>
+template <typename T, bool CONJ_A>
 __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, const cplx<T>* __restrict__ A,
                                               int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb, T beta,
                                               cplx<T>* __restrict__ C, int64_t ldc) {
@@ -68,9 +68,10 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   const int64_t m0 = (int64_t)blockIdx.y * BM;
   const int64_t n0 = (int64_t)blockIdx.x * BN;
 
-  // global -> register staging assignment
-  const int a_row = tid / (BK / AE);
-  const int a_k = (tid % (BK / AE)) * AE;
+  // global -> register staging assignment (op(A) = A^H: threads run along the
+  // rows of op(A), which are contiguous in memory)
+  const int a_row = CONJ_A ? tid % BM : tid / (BK / AE);
+  const int a_k = CONJ_A ? (tid / BM) * AE : (tid % (BK / AE)) * AE;
   const int b_k = tid / (BN / BE);
   const int b_col = (tid % (BN / BE)) * BE;
 
@@ -80,7 +81,12 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
 #pragma unroll
     for (int e = 0; e < AE; ++e) {
       const int64_t gk = k0 + a_k + e;
-      ra[e] = (gr < M && gk < K) ? A[gr * lda + gk] : cplx<T>{T(0), T(0)};
+      if (CONJ_A) {
+        const cplx<T> v = (gr < M && gk < K) ? A[gk * lda + gr] : cplx<T>{T(0), T(0)};
+        ra[e] = cplx<T>{v.re, -v.im};
+      } else {
+        ra[e] = (gr < M && gk < K) ? A[gr * lda + gk] : cplx<T>{T(0), T(0)};
+      }
     }
     const int64_t gk = k0 + b_k;
 #pragma unroll
@@ -179,9 +185,9 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
       }
 }
 
-template <typename T>
-void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
-          const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc) {
+template <typename T, bool CONJ_A>
+static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
+                        const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc) {
   if (M <= 0 || N <= 0) return;
   if (K <= 0) {
     if (beta == 1.0) return;
@@ -191,14 +197,30 @@ void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cpl
   const double bytes = (double)sizeof(cplx<T>) * ((double)M * K + (double)K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N);
   ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
-  hipLaunchKernelGGL(k_gemm<T>, grid, dim3(256), 0, ctx.stream, M, N, std::max<int64_t>(K, 0), (T)alpha, A, lda, B,
-                     ldb, (T)beta, C, ldc);
+  hipLaunchKernelGGL((k_gemm<T, CONJ_A>), grid, dim3(256), 0, ctx.stream, M, N, std::max<int64_t>(K, 0), (T)alpha, A,
+                     lda, B, ldb, (T)beta, C, ldc);
   FOSB_LAUNCH_CHECK();
+}
+
+template <typename T>
+void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
+          const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc) {
+  gemm_launch<T, false>(ctx, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+template <typename T>
+void gemm_ch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
+             const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc) {
+  gemm_launch<T, true>(ctx, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 template void gemm<double>(Context&, int64_t, int64_t, int64_t, double, const c128*, int64_t, const c128*, int64_t,
                            double, c128*, int64_t);
 template void gemm<float>(Context&, int64_t, int64_t, int64_t, double, const c64*, int64_t, const c64*, int64_t,
                           double, c64*, int64_t);
+template void gemm_ch<double>(Context&, int64_t, int64_t, int64_t, double, const c128*, int64_t, const c128*, int64_t,
+                              double, c128*, int64_t);
+template void gemm_ch<float>(Context&, int64_t, int64_t, int64_t, double, const c64*, int64_t, const c64*, int64_t,
+                             double, c64*, int64_t);
 
 }  // namespace fosb

@@ -387,16 +387,18 @@ __global__ __launch_bounds__(256) void k_panel_finish(cplx<T>* __restrict__ A, i
 }
 
 // Triangular solve on a diagonal block of up to NL rows in one launch:
-// rows [k0, k0 + n) of B <- op(T)^{-1} B, where T is the unit lower (LOWER) or
-// upper factor stored in A and its 32x32 diagonal blocks are applied through
-// their stored inverses.  Each workgroup owns a stripe of CS right-hand sides
+// rows [k0, k0 + n) of B <- op(T)^{-1} B.  Without CONJT, T is the unit lower
+// (LOWER) or upper factor stored in A; with CONJT, op(T) is the conjugate
+// transpose of the upper (LOWER: U^H is lower) or unit lower factor (L^H).
+// The 32x32 diagonal blocks are applied through their stored inverses
+// ((T^H)^{-1} = (T^{-1})^H).  Each workgroup owns a stripe of CS right-hand sides
 // held in LDS; after each diagonal block the coupling to the remaining rows
 // of the leaf is subtracted with the off-diagonal factor entries.
 constexpr int NL = 256;
 template <typename T> struct LeafCS { static constexpr int v = 16; };
 template <> struct LeafCS<double> { static constexpr int v = 8; };
 
-template <typename T, bool LOWER, int CS>
+template <typename T, bool LOWER, int CS, bool CONJT>
 __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A, int64_t lda,
                                                    const cplx<T>* __restrict__ dinv, int64_t k0, int n,
                                                    cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs) {
@@ -415,7 +417,14 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A
     const int r0 = b * NB, rn = min(NB, n - r0);
     __syncthreads();
     const cplx<T>* inv = dinv + (k0 / NB + b) * NB * NB;
-    for (int e = tid; e < NB * NB; e += 256) si[e / NB][e % NB] = inv[e];
+    for (int e = tid; e < NB * NB; e += 256) {
+      if (CONJT) {
+        const cplx<T> v = inv[(e % NB) * NB + e / NB];
+        si[e / NB][e % NB] = cplx<T>{v.re, -v.im};
+      } else {
+        si[e / NB][e % NB] = inv[e];
+      }
+    }
     __syncthreads();
     cplx<T> xv[XPT];
 #pragma unroll
@@ -445,10 +454,19 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A
     const int u0 = LOWER ? r0 + rn : 0;
     const int u1 = LOWER ? n : r0;
     if (tid >= u0 && tid < u1) {  // one thread per remaining row: its factor segment once, all CS columns
-      const cplx<T>* arow = A + (k0 + tid) * lda + k0 + r0;
       cplx<T> l[NB];
+      if (CONJT) {  // column tid of the stored factor, rows r0 .. r0 + rn: coalesced across the wave
+        const cplx<T>* acol = A + (k0 + r0) * lda + k0 + tid;
 #pragma unroll
-      for (int t = 0; t < NB; ++t) l[t] = t < rn ? arow[t] : cplx<T>{T(0), T(0)};
+        for (int t = 0; t < NB; ++t) {
+          const cplx<T> v = t < rn ? acol[(int64_t)t * lda] : cplx<T>{T(0), T(0)};
+          l[t] = cplx<T>{v.re, -v.im};
+        }
+      } else {
+        const cplx<T>* arow = A + (k0 + tid) * lda + k0 + r0;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) l[t] = t < rn ? arow[t] : cplx<T>{T(0), T(0)};
+      }
 #pragma unroll
       for (int c = 0; c < CS; ++c) {
         T xr = 0, xi = 0;
@@ -585,21 +603,25 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   return info;  // 0, or 1-based index of the first exactly zero pivot
 }
 
+template <typename T, bool LOWER, bool CONJT>
+static void trsm_leaf_launch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinv, int64_t k0, int64_t n,
+                             cplx<T>* B, int64_t ldb, int64_t nrhs) {
+  ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 4.0 * n * n * nrhs, sizeof(cplx<T>) * (0.5 * n * n + 2.0 * n * nrhs));
+  if (nrhs <= 2)
+    hipLaunchKernelGGL((k_trsm_leaf<T, LOWER, 1, CONJT>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda, dinv,
+                       k0, (int)n, B, ldb, nrhs);
+  else
+    hipLaunchKernelGGL((k_trsm_leaf<T, LOWER, LeafCS<T>::v, CONJT>),
+                       dim3((unsigned)((nrhs + LeafCS<T>::v - 1) / LeafCS<T>::v)), dim3(256), 0, ctx.stream, A, lda,
+                       dinv, k0, (int)n, B, ldb, nrhs);
+  FOSB_LAUNCH_CHECK();
+}
+
 template <typename T>
 void trsm_lower_unit(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0, int64_t n,
                      cplx<T>* B, int64_t ldb, int64_t nrhs) {
   if (n <= 0 || nrhs <= 0) return;
-  if (n <= NL) {
-    ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 4.0 * n * n * nrhs, sizeof(cplx<T>) * (0.5 * n * n + 2.0 * n * nrhs));
-    if (nrhs <= 2)
-      hipLaunchKernelGGL((k_trsm_leaf<T, true, 1>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda, dinvL, k0,
-                         (int)n, B, ldb, nrhs);
-    else
-      hipLaunchKernelGGL((k_trsm_leaf<T, true, LeafCS<T>::v>), dim3((unsigned)((nrhs + LeafCS<T>::v - 1) / LeafCS<T>::v)),
-                         dim3(256), 0, ctx.stream, A, lda, dinvL, k0, (int)n, B, ldb, nrhs);
-    FOSB_LAUNCH_CHECK();
-    return;
-  }
+  if (n <= NL) return trsm_leaf_launch<T, true, false>(ctx, A, lda, dinvL, k0, n, B, ldb, nrhs);
   const int64_t n1 = split_half(n);
   trsm_lower_unit<T>(ctx, A, lda, dinvL, k0, n1, B, ldb, nrhs);
   gemm<T>(ctx, n - n1, nrhs, n1, -1.0, A + (k0 + n1) * lda + k0, lda, B, ldb, 1.0, B + n1 * ldb, ldb);
@@ -610,21 +632,37 @@ template <typename T>
 void trsm_upper(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvU, int64_t k0, int64_t n,
                 cplx<T>* B, int64_t ldb, int64_t nrhs) {
   if (n <= 0 || nrhs <= 0) return;
-  if (n <= NL) {
-    ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 4.0 * n * n * nrhs, sizeof(cplx<T>) * (0.5 * n * n + 2.0 * n * nrhs));
-    if (nrhs <= 2)
-      hipLaunchKernelGGL((k_trsm_leaf<T, false, 1>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda, dinvU, k0,
-                         (int)n, B, ldb, nrhs);
-    else
-      hipLaunchKernelGGL((k_trsm_leaf<T, false, LeafCS<T>::v>), dim3((unsigned)((nrhs + LeafCS<T>::v - 1) / LeafCS<T>::v)),
-                         dim3(256), 0, ctx.stream, A, lda, dinvU, k0, (int)n, B, ldb, nrhs);
-    FOSB_LAUNCH_CHECK();
-    return;
-  }
+  if (n <= NL) return trsm_leaf_launch<T, false, false>(ctx, A, lda, dinvU, k0, n, B, ldb, nrhs);
   const int64_t n1 = split_half(n);
   trsm_upper<T>(ctx, A, lda, dinvU, k0 + n1, n - n1, B + n1 * ldb, ldb, nrhs);
   gemm<T>(ctx, n1, nrhs, n - n1, -1.0, A + k0 * lda + (k0 + n1), lda, B + n1 * ldb, ldb, 1.0, B, ldb);
   trsm_upper<T>(ctx, A, lda, dinvU, k0, n1, B, ldb, nrhs);
+}
+
+// B <- U^{-H} B (U^H is lower triangular: forward substitution)
+template <typename T>
+void trsm_upper_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvU, int64_t k0, int64_t n,
+                   cplx<T>* B, int64_t ldb, int64_t nrhs) {
+  if (n <= 0 || nrhs <= 0) return;
+  if (n <= NL) return trsm_leaf_launch<T, true, true>(ctx, A, lda, dinvU, k0, n, B, ldb, nrhs);
+  const int64_t n1 = split_half(n);
+  trsm_upper_ch<T>(ctx, A, lda, dinvU, k0, n1, B, ldb, nrhs);
+  // B2 -= (U12)^H B1, U12 = rows k0 .. k0+n1, columns k0+n1 .. k0+n
+  gemm_ch<T>(ctx, n - n1, nrhs, n1, -1.0, A + k0 * lda + (k0 + n1), lda, B, ldb, 1.0, B + n1 * ldb, ldb);
+  trsm_upper_ch<T>(ctx, A, lda, dinvU, k0 + n1, n - n1, B + n1 * ldb, ldb, nrhs);
+}
+
+// B <- L^{-H} B (L^H is unit upper triangular: backward substitution)
+template <typename T>
+void trsm_lower_unit_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0, int64_t n,
+                        cplx<T>* B, int64_t ldb, int64_t nrhs) {
+  if (n <= 0 || nrhs <= 0) return;
+  if (n <= NL) return trsm_leaf_launch<T, false, true>(ctx, A, lda, dinvL, k0, n, B, ldb, nrhs);
+  const int64_t n1 = split_half(n);
+  trsm_lower_unit_ch<T>(ctx, A, lda, dinvL, k0 + n1, n - n1, B + n1 * ldb, ldb, nrhs);
+  // B1 -= (L21)^H B2, L21 = rows k0+n1 .. k0+n, columns k0 .. k0+n1
+  gemm_ch<T>(ctx, n1, nrhs, n - n1, -1.0, A + (k0 + n1) * lda + k0, lda, B + n1 * ldb, ldb, 1.0, B, ldb);
+  trsm_lower_unit_ch<T>(ctx, A, lda, dinvL, k0, n1, B, ldb, nrhs);
 }
 
 template int64_t lu_factor<double>(Context&, c128*, int64_t, int64_t, c128*, c128*, std::vector<int32_t>&);
@@ -637,6 +675,14 @@ template void trsm_upper<double>(Context&, const c128*, int64_t, const c128*, in
                                  int64_t);
 template void trsm_upper<float>(Context&, const c64*, int64_t, const c64*, int64_t, int64_t, c64*, int64_t,
                                 int64_t);
+template void trsm_upper_ch<double>(Context&, const c128*, int64_t, const c128*, int64_t, int64_t, c128*, int64_t,
+                                    int64_t);
+template void trsm_upper_ch<float>(Context&, const c64*, int64_t, const c64*, int64_t, int64_t, c64*, int64_t,
+                                   int64_t);
+template void trsm_lower_unit_ch<double>(Context&, const c128*, int64_t, const c128*, int64_t, int64_t, c128*,
+                                         int64_t, int64_t);
+template void trsm_lower_unit_ch<float>(Context&, const c64*, int64_t, const c64*, int64_t, int64_t, c64*, int64_t,
+                                        int64_t);
 
 // ------------------------------------------------------------------ element-wise helpers
 template <typename S, typename D>
@@ -687,10 +733,25 @@ void permute_rows_gather(hipStream_t s, const int32_t* perm, const c128* src, in
   FOSB_LAUNCH_CHECK();
 }
 
-// dst (cols x rows) = src^H (src rows x cols), 32x32 tiles through LDS
+__global__ void k_scatter_rows(const int32_t* __restrict__ perm, const c128* __restrict__ src, int64_t lds,
+                               c128* __restrict__ dst, int64_t ldd, int64_t n, int64_t cols) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t r = blockIdx.y; r < n; r += gridDim.y)
+    if (c < cols) dst[(int64_t)perm[r] * ldd + c] = src[r * lds + c];
+}
+
+void permute_rows_scatter(hipStream_t s, const int32_t* perm, const c128* src, int64_t lds, c128* dst, int64_t ldd,
+                          int64_t n, int64_t ncols) {
+  if (n <= 0 || ncols <= 0) return;
+  dim3 g((unsigned)((ncols + 255) / 256), (unsigned)std::min<int64_t>(n, 65535));
+  hipLaunchKernelGGL(k_scatter_rows, g, dim3(256), 0, s, perm, src, lds, dst, ldd, n, ncols);
+  FOSB_LAUNCH_CHECK();
+}
+
+// dst (cols x rows) = diag(scale) src^H (src rows x cols; scale optional), 32x32 tiles through LDS
 __global__ __launch_bounds__(256) void k_conj_transpose(const c128* __restrict__ src, int64_t lds,
                                                         c128* __restrict__ dst, int64_t ldd, int64_t rows,
-                                                        int64_t cols) {
+                                                        int64_t cols, const double* __restrict__ scale) {
   __shared__ c128 t[32][33];
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -703,16 +764,18 @@ __global__ __launch_bounds__(256) void k_conj_transpose(const c128* __restrict__
     const int64_t r = c0 + q, c = r0 + tx;  // dst row = src col
     if (r < cols && c < rows) {
       const c128 v = t[tx][q];
-      dst[r * ldd + c] = c128{v.re, -v.im};
+      const double f = scale ? scale[r] : 1.0;
+      dst[r * ldd + c] = c128{f * v.re, -f * v.im};
     }
   }
 }
 
 void conj_transpose_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows,
-                         int64_t cols) {
+                         int64_t cols, const double* row_scale) {
   if (rows <= 0 || cols <= 0) return;
+  if ((cols + 31) / 32 > INT32_MAX || (rows + 31) / 32 > 65535) fail(FOSB_E_UNSUPPORTED, "transpose of %lld rows", (long long)rows);
   dim3 g((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
-  hipLaunchKernelGGL(k_conj_transpose, g, dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+  hipLaunchKernelGGL(k_conj_transpose, g, dim3(256), 0, s, src, lds, dst, ldd, rows, cols, row_scale);
   FOSB_LAUNCH_CHECK();
 }
 

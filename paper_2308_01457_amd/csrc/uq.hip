@@ -361,4 +361,156 @@ void matvec_rows(hipStream_t s, const c128* FF, int64_t rows, int64_t n, const c
   FOSB_LAUNCH_CHECK();
 }
 
+
+// ------------------------------------------------------------------ adjoint of the variance
+// Hn[q][r] = P[r][q] = sum_a conj(B[e(t,a)][r]) W[t][a][j] for node q = 6t + j,
+// with B = Z^{-H} FF^H (N x R): the rows of FF Z^{-1} Wgt, one per node.
+__global__ __launch_bounds__(256) void k_adjoint_nodes(const int32_t* __restrict__ tri_edge, int nt,
+                                                       const c128* __restrict__ W, const c128* __restrict__ B,
+                                                       int64_t R, c128* __restrict__ Hn) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int64_t Q = 6LL * nt;
+  for (int64_t q = blockIdx.y; q < Q; q += gridDim.y) {
+    const int t = (int)(q / 6), j = (int)(q % 6);
+    double hr = 0, hi = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int e = tri_edge[a * nt + t];
+      const c128 w = W[((int64_t)t * 3 + a) * 6 + j];
+      const c128 b = B[(int64_t)e * R + r];
+      // conj(b) * w
+      hr += b.re * w.re + b.im * w.im;
+      hi += b.re * w.im - b.im * w.re;
+    }
+    Hn[q * R + r] = c128{hr, hi};
+  }
+}
+
+void adjoint_nodes(hipStream_t s, const Mesh& m, const c128* W, const c128* B, int64_t R, c128* Hn) {
+  const int64_t Q = 6LL * m.h.nt;
+  dim3 g((unsigned)((R + 255) / 256), (unsigned)std::min<int64_t>(Q, 65535));
+  hipLaunchKernelGGL(k_adjoint_nodes, g, dim3(256), 0, s, m.tri_edge.as<int32_t>(), (int)m.h.nt, W, B, R, Hn);
+  FOSB_LAUNCH_CHECK();
+}
+
+// Correlation function kappa = K / sigma^2 and d kappa / d ell at squared distance r2.
+__device__ __forceinline__ void corr_and_dell(const CovParams& cp, double ell, double r2, double ndot, double& kv,
+                                              double& dl) {
+  switch (cp.kind) {
+    case FOSB_COV_GAUSSIAN: {
+      kv = exp(-r2 * cp.inv2l2);
+      dl = kv * r2 / (ell * ell * ell);
+      return;
+    }
+    case FOSB_COV_MATERN32: {
+      const double a = sqrt(r2) * cp.s3l;
+      const double ea = exp(-a);
+      kv = (1.0 + a) * ea;
+      dl = a * a * ea / ell;
+      return;
+    }
+    case FOSB_COV_CONSTANT: kv = 1.0; dl = 0.0; return;
+    default: kv = ndot; dl = 0.0; return;
+  }
+}
+
+// For rows q1 in [a0, a0 + na) of G (row stride Q2) and all columns q2:
+// partial[2 b] = scale sum kappa Re G, partial[2 b + 1] = scale sum dkappa/dell Re G,
+// one pair of values per block b (16 rows x 256 columns), summed later in block order.
+__global__ __launch_bounds__(256) void k_cov_grad_partials(const c128* __restrict__ G, int64_t a0, int64_t na,
+                                                           int64_t Q2, const double* __restrict__ x1, int64_t Q1,
+                                                           const double* __restrict__ n1, int nt1,
+                                                           const double* __restrict__ x2,
+                                                           const double* __restrict__ n2, int nt2, CovParams cp,
+                                                           double ell, double scale, double* __restrict__ partial) {
+  __shared__ double s0[256], s1[256];
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t rb = (int64_t)blockIdx.y * 16;
+  double acc0 = 0, acc1 = 0;
+  if (c < Q2) {
+    const double y0 = x2[c], y1 = x2[Q2 + c], y2 = x2[2 * Q2 + c];
+    const int t2 = (int)(c / 6);
+    const double m0 = n2[t2], m1 = n2[nt2 + t2], m2 = n2[2 * nt2 + t2];
+    for (int i = 0; i < 16; ++i) {
+      const int64_t rr = rb + i;
+      if (rr >= na) break;
+      const int64_t q1 = a0 + rr;
+      const double d0 = x1[q1] - y0, d1 = x1[Q1 + q1] - y1, d2 = x1[2 * Q1 + q1] - y2;
+      const int t1 = (int)(q1 / 6);
+      const double nd = n1[t1] * m0 + n1[nt1 + t1] * m1 + n1[2 * nt1 + t1] * m2;
+      double kv, dl;
+      corr_and_dell(cp, ell, d0 * d0 + d1 * d1 + d2 * d2, nd, kv, dl);
+      const double g = G[rr * Q2 + c].re;
+      acc0 += kv * g;
+      acc1 += dl * g;
+    }
+  }
+  s0[threadIdx.x] = acc0;
+  s1[threadIdx.x] = acc1;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s0[threadIdx.x] += s0[threadIdx.x + o];
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    partial[2 * b] = scale * s0[0];
+    partial[2 * b + 1] = scale * s1[0];
+  }
+}
+
+int64_t cov_grad_partials(hipStream_t s, const c128* G, int64_t a0, int64_t na, const Level& l1, const Level& l2,
+                          const fosb_cov& cov, double scale, double* partial) {
+  const Mesh& m1 = *l1.mesh;
+  const Mesh& m2 = *l2.mesh;
+  const int64_t Q1 = 6LL * m1.h.nt, Q2 = 6LL * m2.h.nt;
+  CovParams cp;
+  cp.kind = cov.kind;
+  cp.s2 = 1.0;
+  cp.inv2l2 = cov.ell > 0 ? 1.0 / (2.0 * cov.ell * cov.ell) : 0.0;
+  cp.s3l = cov.ell > 0 ? std::sqrt(3.0) / cov.ell : 0.0;
+  dim3 g((unsigned)((Q2 + 255) / 256), (unsigned)((na + 15) / 16));
+  hipLaunchKernelGGL(k_cov_grad_partials, g, dim3(256), 0, s, G, a0, na, Q2, l1.qx.as<double>(), Q1,
+                     m1.nrm.as<double>(), (int)m1.h.nt, l2.qx.as<double>(), m2.nrm.as<double>(), (int)m2.h.nt, cp,
+                     cov.ell, scale, partial);
+  FOSB_LAUNCH_CHECK();
+  return (int64_t)g.x * g.y;
+}
+
+// out[0] = 2 sigma A, out[1] = sigma^2 B, out[2] = sigma^2 A with (A, B) the
+// partial pairs summed in order (one block, fixed reduction tree).
+__global__ __launch_bounds__(256) void k_cov_grad_finish(const double* __restrict__ partial, int64_t n, double sigma,
+                                                         double* __restrict__ out) {
+  __shared__ double s0[256], s1[256];
+  double a = 0, b = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    a += partial[2 * i];
+    b += partial[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s0[threadIdx.x] += s0[threadIdx.x + o];
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = 2.0 * sigma * s0[0];
+    out[1] = sigma * sigma * s1[0];
+    out[2] = sigma * sigma * s0[0];
+  }
+}
+
+void cov_grad_finish(hipStream_t s, const double* partial, int64_t n, double sigma, double* out) {
+  hipLaunchKernelGGL(k_cov_grad_finish, dim3(1), dim3(256), 0, s, partial, n, sigma, out);
+  FOSB_LAUNCH_CHECK();
+}
+
 }  // namespace fosb

@@ -65,6 +65,7 @@ _SIGS = {
                                     C.POINTER(_P)]),
     "fosb_level_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
     "fosb_level_solve": (C.c_int, [_P, _P, _P, _I64, _I64, C.POINTER(Stats)]),
+    "fosb_level_solve_adjoint": (C.c_int, [_P, _P, _P, _I64, _I64, C.POINTER(Stats)]),
     "fosb_level_first_moment": (C.c_int, [_P, _P, _I64, _P]),
     "fosb_level_destroy": (C.c_int, [_P]),
     "fosb_rhs_correlation": (C.c_int, [_P, _P, _P, C.POINTER(Cov), _I64, _P, _I64]),
@@ -76,6 +77,8 @@ _SIGS = {
     "fosb_far_field_matrix": (C.c_int, [_P, _P, _P, _I64, _P]),
     "fosb_far_field_moments": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64), _P,
                                          _I64, _I64, _P, _P]),
+    "fosb_far_field_moments_backward": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
+                                                  _I64, _P, _P, C.POINTER(Stats)]),
     "fosb_profile_enable": (C.c_int, [_P, _I32]),
     "fosb_profile_read": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
 }
@@ -266,6 +269,15 @@ class Level:
                                       C.byref(st)))
         return B
 
+    def solve_adjoint(self, B, stats: Stats | None = None):
+        """B <- Z^{-H} B in place."""
+        import torch
+        st = stats if stats is not None else Stats()
+        B2 = B if B.dim() == 2 else B.view(-1, 1)
+        _check(lib().fosb_level_solve_adjoint(self.ctx.h, self.h, _dev(B2, torch.complex128), B2.stride(0),
+                                              B2.shape[1], C.byref(st)))
+        return B
+
     def first_moment(self, dir: int = 0):
         import torch
         u = torch.empty(self.n, dtype=torch.complex128, device=self.ctx.torch_device)
@@ -349,6 +361,65 @@ def far_field_moments(ctx: Context, levels: list[Level], L0: int, L: int, blocks
                                         _dev(var, torch.float64), _dev(mean) if mean is not None else None))
     var = var.view(3, n_a)
     return (var, mean.view(3, n_a)) if with_mean else var
+
+
+def far_field_moments_backward(ctx: Context, levels: list[Level], L0: int, L: int, cov: Cov, xhat, dvar,
+                               dir: int = 0, stats: Stats | None = None):
+    """Adjoint of the CT variance in the covariance parameters: for S = sum(dvar * var)
+    returns a device float64 tensor (dS/dsigma, dS/dell, S)."""
+    import torch
+    x = _host_f64(xhat).reshape(-1, 3)
+    n_a = x.shape[0]
+    g = dvar.reshape(3 * n_a)
+    if not g.is_contiguous():
+        g = g.contiguous()
+    out = torch.empty(3, dtype=torch.float64, device=ctx.torch_device)
+    st = stats if stats is not None else Stats()
+    lv = (_P * len(levels))(*[l.h for l in levels])
+    _check(lib().fosb_far_field_moments_backward(ctx.h, lv, len(levels), L0, L, C.byref(cov), x.ctypes.data_as(_P),
+                                                 n_a, dir, _dev(g, torch.float64), _dev(out, torch.float64),
+                                                 C.byref(st)))
+    return out
+
+
+def _variance_function():
+    import torch
+
+    class RcsVariance(torch.autograd.Function):
+        """var(sigma, ell) through fosb_correlation + fosb_far_field_moments; the
+        backward pass is fosb_far_field_moments_backward."""
+
+        @staticmethod
+        def forward(fctx, sigma, ell, ctx, levels, L0, L, kind, xhat, dir):
+            cov = make_cov(kind, float(sigma), float(ell))
+            blocks = correlation(ctx, levels, L0, L, cov, dir)
+            var = far_field_moments(ctx, levels, L0, L, blocks, xhat, dir)
+            del blocks
+            fctx.args = (ctx, levels, L0, L, cov, xhat, dir)
+            fctx.devices = (sigma.device, ell.device)
+            return var
+
+        @staticmethod
+        def backward(fctx, gvar):
+            ctx, levels, L0, L, cov, xhat, dir = fctx.args
+            g = gvar.to(torch.float64).contiguous()
+            out = far_field_moments_backward(ctx, levels, L0, L, cov, xhat, g, dir)
+            return (out[0].to(fctx.devices[0]), out[1].to(fctx.devices[1]), None, None, None, None, None, None,
+                    None)
+
+    return RcsVariance
+
+
+_RCS_VARIANCE = None
+
+
+def rcs_variance(ctx: Context, levels: list[Level], L0: int, L: int, kind: str, sigma, ell, xhat, dir: int = 0):
+    """Differentiable CT far-field variance (3, n_a) as a function of the covariance
+    amplitude sigma and correlation length ell (0-d float64 tensors)."""
+    global _RCS_VARIANCE
+    if _RCS_VARIANCE is None:
+        _RCS_VARIANCE = _variance_function()
+    return _RCS_VARIANCE.apply(sigma, ell, ctx, levels, L0, L, kind, xhat, dir)
 
 
 @dataclass
