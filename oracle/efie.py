@@ -150,13 +150,14 @@ def assemble(m: meshmod.RWGMesh, k: float, n_gauss: int = 5, chunk: int | None =
                 blk[r, j] = sing[(int(i), int(j))]
         Zhat = blk.transpose(0, 2, 1, 3).reshape(3 * len(rows), 3 * nt)
         Srows = S[:, 3 * i0: 3 * (i0 + len(rows))]
-        return Srows @ (Zhat @ ST)
+        edges = np.unique(Srows.nonzero()[0])         # the only rows this chunk contributes to
+        return edges, Srows[edges] @ (Zhat @ ST)
 
     Z = np.zeros((m.ne, m.ne), dtype=np.complex128)
     starts = list(range(0, nt, chunk))
     for g0 in range(0, len(starts), workers):
-        for part in _pool_map(rows_block, starts[g0:g0 + workers], workers):
-            Z += part
+        for edges, part in _pool_map(rows_block, starts[g0:g0 + workers], workers):
+            Z[edges] += part
     return Z
 
 
