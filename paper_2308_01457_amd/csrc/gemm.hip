@@ -185,6 +185,76 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
       }
 }
 
+// Narrow right-hand sides (N <= 4, e.g. one incidence): a bandwidth-bound
+// product, one wave per row of A streaming it once with 16-byte loads; the N
+// columns of B are read through the cache.  Row sums are reduced in the wave.
+constexpr int GEMV_MAXN = 4;
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_gemv(int64_t M, int64_t K, T alpha, const cplx<T>* __restrict__ A,
+                                              int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb, T beta,
+                                              cplx<T>* __restrict__ C, int64_t ldc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= M) return;
+  const cplx<T>* a = A + row * lda;
+  T ar[NC], ai[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) ar[c] = ai[c] = T(0);
+  int64_t k = lane;
+  for (; k + 192 < K; k += 256) {
+    cplx<T> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = a[k + 64 * u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const cplx<T> b = B[(k + 64 * u) * ldb + c];
+        ar[c] += v[u].re * b.re - v[u].im * b.im;
+        ai[c] += v[u].re * b.im + v[u].im * b.re;
+      }
+  }
+  for (; k < K; k += 64) {
+    const cplx<T> v = a[k];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const cplx<T> b = B[k * ldb + c];
+      ar[c] += v.re * b.re - v.im * b.im;
+      ai[c] += v.re * b.im + v.im * b.re;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      ar[c] += __shfl_xor(ar[c], o);
+      ai[c] += __shfl_xor(ai[c], o);
+    }
+  }
+  if (lane < NC) {
+    T sr = ar[0], si = ai[0];
+#pragma unroll
+    for (int c = 1; c < NC; ++c)
+      if (lane == c) sr = ar[c], si = ai[c];
+    cplx<T>* p = C + row * ldc + lane;
+    if (beta == T(0)) {
+      *p = cplx<T>{alpha * sr, alpha * si};
+    } else {
+      const cplx<T> o = *p;
+      *p = cplx<T>{beta * o.re + alpha * sr, beta * o.im + alpha * si};
+    }
+  }
+}
+
+template <typename T, int NC>
+static void gemv_launch(Context& ctx, int64_t M, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
+                        const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc) {
+  hipLaunchKernelGGL((k_gemv<T, NC>), dim3((unsigned)((M + 3) / 4)), dim3(256), 0, ctx.stream, M, K, (T)alpha, A,
+                     lda, B, ldb, (T)beta, C, ldc);
+  FOSB_LAUNCH_CHECK();
+}
+
 template <typename T, bool CONJ_A>
 static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
                         const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc) {
@@ -196,6 +266,14 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
   const double flops = 8.0 * (double)M * (double)N * (double)std::max<int64_t>(K, 0);
   const double bytes = (double)sizeof(cplx<T>) * ((double)M * K + (double)K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N);
   ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);
+  if (!CONJ_A && N <= GEMV_MAXN && K > 0 && (M + 3) / 4 <= INT32_MAX) {
+    switch (N) {
+      case 1: return gemv_launch<T, 1>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
+      case 2: return gemv_launch<T, 2>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
+      case 3: return gemv_launch<T, 3>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
+      default: return gemv_launch<T, 4>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    }
+  }
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
   hipLaunchKernelGGL((k_gemm<T, CONJ_A>), grid, dim3(256), 0, ctx.stream, M, N, std::max<int64_t>(K, 0), (T)alpha, A,
                      lda, B, ldb, (T)beta, C, ldc);
