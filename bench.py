@@ -36,6 +36,27 @@ if ROOT not in sys.path:
 
 PEAK = {"fp64": 78.6, "mixed": 157.3}          # dense MFMA TFLOP/s (FP64, FP32)
 HBM_PEAK = 8000.0                               # GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_gemm_f32_mixed_k5.txt")
+GEMM_SRC = os.path.join(ROOT, "paper_2308_01457_amd", "csrc", "gemm.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None when it is missing or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
+        if kv.get("source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -53,6 +74,9 @@ def parse():
                     help="mixed path: stop refining when the relative correction is below this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--progress", action="store_true", help="print a line after every stage of every step")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -69,6 +93,14 @@ def gpu_setup(fosb, torch, ctx, W):
     return meshes, Z
 
 
+PROGRESS = False
+
+
+def _progress(msg):
+    if PROGRESS:
+        log(f"[bench]   {time.strftime('%H:%M:%S')} {msg}")
+
+
 def one_step(fosb, torch, ctx, W, meshes, Z, Zlow, precision, cov, opts, stage_ev=None):
     w = W.w
     k = w.k
@@ -76,20 +108,25 @@ def one_step(fosb, torch, ctx, W, meshes, Z, Zlow, precision, cov, opts, stage_e
     ev = stage_ev
     if ev:
         ev[0].record()
-    for m, z in zip(meshes, Z):
+    for s, m, z in zip(w.levels, meshes, Z):
         fosb.assemble(ctx, m, k, opts, Z=z)
+        _progress(f"assembled s={s}")
     if ev:
         ev[1].record()
-    levels = [fosb.Level(ctx, m, k, z, precision, w.dirs, w.pols, "radial", opts,
-                         Zlow=(zl if precision == fosb.MIXED else None))
-              for m, z, zl in zip(meshes, Z, Zlow)]
+    levels = []
+    for s, m, z, zl in zip(w.levels, meshes, Z, Zlow):
+        levels.append(fosb.Level(ctx, m, k, z, precision, w.dirs, w.pols, "radial", opts,
+                                 Zlow=(zl if precision == fosb.MIXED else None)))
+        _progress(f"factored s={s}")
     if ev:
         ev[2].record()
     st = fosb.Stats()
     blocks = fosb.correlation(ctx, levels, L0, L, cov, 0, stats=st)
+    _progress("pairs solved")
     if ev:
         ev[3].record()
     var = fosb.far_field_moments(ctx, levels, L0, L, blocks, W.xh)
+    _progress("far field")
     if ev:
         ev[4].record()
     return var, blocks, levels, st
@@ -222,8 +259,28 @@ def cpu_baseline(W):
             "projected_seconds_per_step": proj}
 
 
+def calibrate_copy():
+    """Plain device-to-device copy of a known size: the reference that scales
+    rocprofv3's FETCH_SIZE / WRITE_SIZE counters to HBM bytes."""
+    import torch
+    n = 1 << 28                                     # 2^28 float32 = 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "launches": 5}), flush=True)
+
+
 def main():
     args = parse()
+    global PROGRESS
+    PROGRESS = args.progress
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -263,8 +320,12 @@ def main():
         ach = fl / sec / 1e12 if sec > 0 else 0.0
         line["roofline"] = {"kernel": f"k_gemm<{'float' if head == 'mixed' else 'double'}>", "bound": "mfma",
                             "achieved": ach, "peak": PEAK[head], "unit": "TFLOP/s", "frac": ach / PEAK[head],
-                            "traffic": None, "launches": n, "avg_launch_us": sec / max(n, 1) * 1e6,
-                            "algorithmic_flop_per_launch": fl / max(n, 1)}
+                            "traffic": measured_traffic() if head == "mixed" else None,
+                            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                            "copy-calibrated)",
+                            "launches": n, "avg_launch_us": sec / max(n, 1) * 1e6,
+                            "algorithmic_flop_per_launch": fl / max(n, 1),
+                            "algorithmic_bytes_per_launch": by / max(n, 1)}
         line["kernel_profile"] = {k: {"launches": v[0], "seconds": v[1], "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
                                       "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof.items()}
     if not args.no_cpu_baseline:

@@ -41,6 +41,8 @@ struct Mfma<float> {
 };
 
 constexpr int BM = 128, BN = 64;
+constexpr int NXCD = 8;  // accelerator complex dies; workgroups are dealt to them round-robin
+constexpr int GM = 8;    // tile rows per group of the tile order
 constexpr int PADA = 4, PADB = 4;
 // K slice staged per LDS buffer: 16 (FP32) / 8 (FP64), two buffers, so one
 // barrier per slice and the next slice's global loads overlap the MFMAs.
@@ -65,8 +67,26 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   const int wave = tid >> 6;
   const int wr = wave >> 1;  // wave row (0..1): rows wr*64 .. +64
   const int wc = wave & 1;   // wave col (0..1): cols wc*32 .. +32
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  // XCD-aware tile order: workgroup L runs on XCD L % 8, so XCD x is given the
+  // contiguous tile range [start(x), start(x) + count(x)), walked in groups of
+  // GM tile rows, column by column: the ~64 workgroups resident on one XCD then
+  // cover an 8 x 8 block of tiles and share their A rows and B columns in that
+  // XCD's L2.
+  int64_t tm, tn;
+  {
+    const int64_t nN = gridDim.x, nM = gridDim.y, ntile = nN * nM;
+    const int64_t L = (int64_t)blockIdx.y * nN + blockIdx.x;
+    const int64_t x = L % NXCD, slot = L / NXCD;
+    const int64_t t = x * (ntile / NXCD) + min(x, ntile % NXCD) + slot;
+    const int64_t group = t / (GM * nN);
+    const int64_t fm = group * GM;
+    const int64_t gs = min<int64_t>(nM - fm, GM);
+    const int64_t in = t - group * GM * nN;
+    tm = fm + in % gs;
+    tn = in / gs;
+  }
+  const int64_t m0 = tm * BM;
+  const int64_t n0 = tn * BN;
 
   // global -> register staging assignment (op(A) = A^H: threads run along the
   // rows of op(A), which are contiguous in memory)
@@ -265,8 +285,8 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
   // algorithmic work: 8 flop per complex multiply-add; A, B read and C read+written once
   const double flops = 8.0 * (double)M * (double)N * (double)std::max<int64_t>(K, 0);
   const double bytes = (double)sizeof(cplx<T>) * ((double)M * K + (double)K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N);
-  ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);
   if (!CONJ_A && N <= GEMV_MAXN && K > 0 && (M + 3) / 4 <= INT32_MAX) {
+    ProfScope prof(ctx, FOSB_K_GEMV, flops, bytes);
     switch (N) {
       case 1: return gemv_launch<T, 1>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
       case 2: return gemv_launch<T, 2>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
@@ -274,6 +294,7 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
       default: return gemv_launch<T, 4>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
     }
   }
+  ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
   hipLaunchKernelGGL((k_gemm<T, CONJ_A>), grid, dim3(256), 0, ctx.stream, M, N, std::max<int64_t>(K, 0), (T)alpha, A,
                      lda, B, ldb, (T)beta, C, ldc);
