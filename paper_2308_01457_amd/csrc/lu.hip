@@ -97,67 +97,81 @@ __device__ __forceinline__ unsigned long long pivot_key(cplx<T> v, int row) {
   return ((unsigned long long)__float_as_uint(m) << 32) | (unsigned long long)(~(unsigned)row);
 }
 
+// 1/a for the panel's multipliers: FP32 through the hardware reciprocal with
+// one Newton step (within an ulp or two of the exact quotient: partial
+// pivoting needs no correctly rounded multipliers), FP64 by exact division.
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return r * (2.0f - x * r);
+}
+__device__ __forceinline__ cplx<float> cinv_panel(cplx<float> a) {
+  const float s = fabsf(a.re) + fabsf(a.im);
+  if (s == 0.0f) return cplx<float>{0.0f, 0.0f};
+  const float rs = rcp_nr(s);
+  const float ar = a.re * rs, ai = a.im * rs;
+  const float t = rcp_nr(ar * ar + ai * ai) * rs;
+  return cplx<float>{ar * t, -ai * t};
+}
+__device__ __forceinline__ cplx<double> cinv_panel(cplx<double> a) { return cinv(a); }
+
+// Partial-pivoting elimination of the node's rows (one row per thread, the
+// row's NB columns in registers).  The step loop is unrolled, so column j is
+// addressed statically and every row stays in place: a row chosen at step j
+// then holds L[j][0..j) (its multipliers) followed by U[j][j..].  Per step,
+// each wave's best candidate publishes its key and its row; one barrier, then
+// every thread picks the largest key and reads that row.  Slots alternate
+// between two buffers, so a wave entering step j+1 never overwrites a slot
+// that another wave still reads at step j.
 template <typename T>
 __device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvalid, int w, int tid, int& step,
-                                         cplx<T> (*prow)[NB], cplx<T> (*lu)[NB + 1],
+                                         cplx<T> (*prow)[NWAVE][NB], cplx<T> (*lu)[NB + 1],
                                          unsigned long long (*skey)[NWAVE]) {
-  // a[0] is always the current column j: after each step a row rotates left
-  // by one and its multiplier enters the last slot, so the row chosen at step
-  // j holds U[j][j..] in its leading slots and L[j][0..j-1] in its trailing ones.
   int zero_col = -1;
   const int steps = min(nvalid, w);
   const int lane = tid & 63, wave = tid >> 6;
   step = -1;
-  for (int j = 0; j < steps; ++j) {
-    const int b = j & 1;
-    unsigned long long key = wave_max_u64((valid && step < 0) ? pivot_key(a[0], tid) : 0ull);
-    if (lane == 0) skey[b][wave] = key;
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NWAVE; ++q) {
-      const unsigned long long o = skey[b][q];
-      key = o > key ? o : key;
-    }
-    const int r = (int)(~(unsigned)(key & 0xffffffffull));
-    if (tid == r) {
-      step = j;
+  for (int j = 0; j < NB; ++j) {
+    if (j < steps) {  // uniform over the workgroup
+      const int b = j & 1;
+      const unsigned long long mine = (valid && step < 0) ? pivot_key(a[j], tid) : 0ull;
+      const unsigned long long wmax = wave_max_u64(mine);
+      if (mine != 0ull && mine == wmax) {  // keys are unique: one publisher per wave
+        skey[b][wave] = wmax;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) prow[b][c] = a[c];
-    }
-    __syncthreads();
-    const cplx<T> piv = prow[b][0];
-    if (piv.re == T(0) && piv.im == T(0) && zero_col < 0) zero_col = j;
-    if (valid && step < 0) {
-      const cplx<T> l = cmul(a[0], cinv(piv));
-      // slots c >= NB - j of the pivot row hold its multipliers: masked out
-      // (branch-free); the pivot row is read from LDS eight columns at a time
+        for (int c = j; c < NB; ++c) prow[b][wave][c] = a[c];
+      } else if (wmax == 0ull && lane == 0) {
+        skey[b][wave] = 0ull;
+      }
+      __syncthreads();
+      unsigned long long key = 0ull;
+      int q = 0;
 #pragma unroll
-      for (int c0 = 0; c0 < NB; c0 += 8) {
-        cplx<T> u[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) u[e] = prow[b][c0 + e];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int c = c0 + e;
-          if (c == 0) continue;
-          const bool live = c < NB - j;
-          const T ur = live ? u[e].re : T(0), ui = live ? u[e].im : T(0);
-          a[c].re -= l.re * ur - l.im * ui;
-          a[c].im -= l.re * ui + l.im * ur;
+      for (int v = 0; v < NWAVE; ++v) {
+        const unsigned long long o = skey[b][v];
+        if (o > key) {
+          key = o;
+          q = v;
         }
       }
+      if (mine != 0ull && mine == key) step = j;
+      const cplx<T> piv = prow[b][q][j];
+      if (piv.re == T(0) && piv.im == T(0) && zero_col < 0) zero_col = j;
+      if (valid && step < 0) {
+        const cplx<T> l = cmul(a[j], cinv_panel(piv));
 #pragma unroll
-      for (int c = 0; c < NB - 1; ++c) a[c] = a[c + 1];
-      a[NB - 1] = l;
+        for (int c = j + 1; c < NB; ++c) {
+          const cplx<T> u = prow[b][q][c];
+          a[c].re -= l.re * u.re - l.im * u.im;
+          a[c].im -= l.re * u.im + l.im * u.re;
+        }
+        a[j] = l;
+      }
     }
   }
-  // chosen rows stopped rotating at their step: write them as rows of L\U
   if (step >= 0) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const int col = c < NB - step ? step + c : c - (NB - step);
-      lu[step][col] = a[c];
-    }
+    for (int c = 0; c < NB; ++c) lu[step][c] = a[c];
   }
   __syncthreads();
   return zero_col;
@@ -281,7 +295,7 @@ __global__ __launch_bounds__(NODE) void k_tslu_node(const cplx<T>* __restrict__ 
                                                     int32_t* __restrict__ moves, int32_t* __restrict__ info,
                                                     cplx<T>* __restrict__ top, cplx<T>* __restrict__ invL,
                                                     cplx<T>* __restrict__ invU) {
-  __shared__ cplx<T> prow[2][NB];
+  __shared__ cplx<T> prow[2][NWAVE][NB];
   __shared__ cplx<T> lu[NB][NB + 1];
   __shared__ int sidx[NODE];
   __shared__ int win[NB];
