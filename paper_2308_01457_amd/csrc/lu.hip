@@ -617,18 +617,31 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   return info;  // 0, or 1-based index of the first exactly zero pivot
 }
 
+template <typename T, bool LOWER, int CS, bool CONJT>
+static void trsm_leaf_go(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinv, int64_t k0, int64_t n,
+                         cplx<T>* B, int64_t ldb, int64_t nrhs) {
+  hipLaunchKernelGGL((k_trsm_leaf<T, LOWER, CS, CONJT>), dim3((unsigned)((nrhs + CS - 1) / CS)), dim3(256), 0,
+                     ctx.stream, A, lda, dinv, k0, (int)n, B, ldb, nrhs);
+  FOSB_LAUNCH_CHECK();
+}
+
+// The stripe of right-hand sides per workgroup is the widest that still gives
+// about two workgroups per compute unit: a leaf is a chain of eight dependent
+// block steps, so narrow right-hand sides are spread over more of the chip.
 template <typename T, bool LOWER, bool CONJT>
 static void trsm_leaf_launch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinv, int64_t k0, int64_t n,
                              cplx<T>* B, int64_t ldb, int64_t nrhs) {
   ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 4.0 * n * n * nrhs, sizeof(cplx<T>) * (0.5 * n * n + 2.0 * n * nrhs));
-  if (nrhs <= 2)
-    hipLaunchKernelGGL((k_trsm_leaf<T, LOWER, 1, CONJT>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda, dinv,
-                       k0, (int)n, B, ldb, nrhs);
-  else
-    hipLaunchKernelGGL((k_trsm_leaf<T, LOWER, LeafCS<T>::v, CONJT>),
-                       dim3((unsigned)((nrhs + LeafCS<T>::v - 1) / LeafCS<T>::v)), dim3(256), 0, ctx.stream, A, lda,
-                       dinv, k0, (int)n, B, ldb, nrhs);
-  FOSB_LAUNCH_CHECK();
+  const int64_t target = 2LL * ctx.n_cu;
+  int cs = LeafCS<T>::v;
+  while (cs > 1 && (nrhs + cs - 1) / cs < target) cs >>= 1;
+  switch (cs) {
+    case 16: return trsm_leaf_go<T, LOWER, (LeafCS<T>::v >= 16 ? 16 : 8), CONJT>(ctx, A, lda, dinv, k0, n, B, ldb, nrhs);
+    case 8: return trsm_leaf_go<T, LOWER, 8, CONJT>(ctx, A, lda, dinv, k0, n, B, ldb, nrhs);
+    case 4: return trsm_leaf_go<T, LOWER, 4, CONJT>(ctx, A, lda, dinv, k0, n, B, ldb, nrhs);
+    case 2: return trsm_leaf_go<T, LOWER, 2, CONJT>(ctx, A, lda, dinv, k0, n, B, ldb, nrhs);
+    default: return trsm_leaf_go<T, LOWER, 1, CONJT>(ctx, A, lda, dinv, k0, n, B, ldb, nrhs);
+  }
 }
 
 template <typename T>
