@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--progress", action="store_true", help="print a line after every stage of every step")
+    ap.add_argument("--schedule", default="concurrent", choices=["concurrent", "sequential"],
+                    help="concurrent: the library's two-stream pipeline (fosb_second_moment); sequential: the "
+                         "step-by-step calls, timed per stage")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -132,6 +135,18 @@ def one_step(fosb, torch, ctx, W, meshes, Z, Zlow, precision, cov, opts, stage_e
     return var, blocks, levels, st
 
 
+def one_step_concurrent(fosb, ctx, W, meshes, Z, Zlow, precision, cov, opts, blocks):
+    """The same pass through fosb_second_moment: finest level on the main
+    stream, coarser levels and their pairs concurrently on the auxiliary one."""
+    w = W.w
+    st = fosb.Stats()
+    var, _, _ = fosb.second_moment(ctx, meshes, w.L0, w.L, w.k, precision, cov, W.xh, w.dirs, w.pols, "radial", 0,
+                                   Z=Z, Zlow=(Zlow if precision == fosb.MIXED else None), blocks=blocks,
+                                   opts=opts, stats=st)
+    _progress("pipeline done")
+    return var, st
+
+
 def algorithmic_flops(W):
     """8 flop per complex multiply-add: LU (8/3) N^3 per level, two-sided solve
     8 N1 N2 (N1 + N2) per pair, far-field contraction 24 n_a N1 N2 per pair."""
@@ -158,41 +173,52 @@ def run_gpu(args, W):
         Zlow = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex64, device=ctx.torch_device) for m in meshes]
     lu_f, solve_f, ff_f, npairs = algorithmic_flops(W)
     out = {}
+    blocks = [torch.empty((meshes[a - W.w.L0].n_edges, meshes[b - W.w.L0].n_edges), dtype=torch.complex128,
+                          device=ctx.torch_device) for a, b, _, _ in fosb.ct_pairs(W.w.L0, W.w.L)]
+
+    def step(prec, ev=None):
+        if args.schedule == "concurrent":
+            return one_step_concurrent(fosb, ctx, W, meshes, Z, Zlow, prec, cov, opts, blocks)
+        var, blk, levels, st = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts, ev)
+        del blk, levels
+        return var, st
+
     for pname in precs:
         prec = fosb.MIXED if pname == "mixed" else fosb.FP64
         log(f"[bench] {pname}: warmup {args.warmup}")
         for _ in range(args.warmup):
-            res = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts)
-            del res
+            step(prec)
         torch.cuda.synchronize()
         stage = np.zeros(4)
         times = []
-        var = None
+        keep_var = None
+        st = None
         for i in range(args.steps):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if args.schedule == "sequential" else None
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            var, blocks, levels, st = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts, ev)
+            var, st = step(prec, ev)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             times.append(dt)
-            stage += [ev[j].elapsed_time(ev[j + 1]) * 1e-3 for j in range(4)]
+            if ev:
+                stage += [ev[j].elapsed_time(ev[j + 1]) * 1e-3 for j in range(4)]
             log(f"[bench] {pname} step {i}: {dt:.3f} s  (ir sweeps {st.ir_sweeps})")
             keep_var = var.cpu().numpy()
-            del blocks, levels
-        stage /= max(1, args.steps)
         t_step = float(np.mean(times))
-        rec = {"seconds_per_step": t_step, "pair_solves_per_s": npairs / t_step,
-               "stage_s": {"assemble": stage[0], "lu_first_moment": stage[1], "pairs": stage[2],
-                           "far_field": stage[3]},
-               "lu_tflops": lu_f / stage[1] / 1e12, "ir_sweeps": int(st.ir_sweeps), "var": keep_var}
+        rec = {"seconds_per_step": t_step, "pair_solves_per_s": npairs / t_step, "ir_sweeps": int(st.ir_sweeps),
+               "var": keep_var}
+        if args.schedule == "sequential":
+            stage /= max(1, args.steps)
+            rec["stage_s"] = {"assemble": stage[0], "lu_first_moment": stage[1], "pairs": stage[2],
+                              "far_field": stage[3]}
+            rec["lu_tflops"] = lu_f / stage[1] / 1e12
         if not args.no_profile:
             log(f"[bench] {pname}: profiled step")
             fosb.profile_enable(ctx, True)
-            res = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts)
+            step(prec)
             prof = fosb.profile_read(ctx)
             fosb.profile_enable(ctx, False)
-            del res
             rec["profile"] = prof
         out[pname] = rec
     return out, (lu_f, solve_f, ff_f, npairs)
@@ -304,7 +330,7 @@ def main():
         "config": {"workload": f"mixed_k5: unit icosphere s={W.w.levels[0]}..{W.w.levels[-1]} "
                                f"(N up to {30 * 4 ** W.w.levels[-1]}), k=5, Gaussian radial cov (0.01, 0.5), "
                                f"L0={W.w.L0} L={W.w.L} ({npairs} pairs), {W.w.n_angles} angles",
-                   "precision": head},
+                   "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol},
         "algorithmic_flop_per_step": {"lu": lu_f, "pair_solves": solve_f, "far_field": ff_f},
     }
     for pname, rec in gpu.items():

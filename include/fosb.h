@@ -232,6 +232,29 @@ fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level*
                                             const double* xhat, int64_t n_a, int64_t dir,
                                             const double* dvar, double* out, fosb_stats* stats);
 
+/* ---------------------------------------------------------------- whole pipeline */
+/* One pass of the hot path over a level ladder L0..L (levels[i] = level L0 + i,
+ * coarse to fine): EFIE assembly into Z[i] (device, N_i x N_i complex128, row
+ * stride ldz[i]; MIXED also needs Zlow[i], complex64, stride ldzlow[i]),
+ * factorisation, first moments and RHS weights of every level, the RHS
+ * correlation and two-sided solve of every pair of fosb_ct_pairs(L0, L) into
+ * blocks[p] (as fosb_correlation), and the far-field variance var (device,
+ * 3 n_a float64, as fosb_far_field_moments) for incidence dir.  The same
+ * results as the step-by-step calls; the work is scheduled over two streams:
+ * the finest level on the context's stream, the coarser levels and the pairs
+ * among them concurrently on an auxiliary stream the context owns (a second
+ * host thread drives it).  levels_out (may be NULL, else n_levels entries)
+ * receives the level handles, owned by the caller; otherwise they are
+ * destroyed.  Z buffers are overwritten (FP64: with the LU factors).  Errors
+ * as for the step-by-step calls; outputs are unspecified on error. */
+fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes, int32_t n_levels,
+                               int32_t L0, int32_t L, double k, int32_t precision, void* const* Z,
+                               const int64_t* ldz, void* const* Zlow, const int64_t* ldzlow,
+                               const double* dirs, const double* pols, int64_t n_dirs, int32_t field,
+                               const fosb_cov* cov, int64_t dir, const double* xhat, int64_t n_a,
+                               void* const* blocks, const int64_t* ldb, double* var,
+                               const fosb_opts* opts, fosb_level** levels_out, fosb_stats* stats);
+
 /* ---------------------------------------------------------------- profiling */
 /* Kernel classes timed by the profiler. */
 typedef enum fosb_kernel_class {

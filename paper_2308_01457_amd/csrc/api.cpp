@@ -3,8 +3,11 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <exception>
 #include <map>
+#include <thread>
 
 #include "common.h"
 
@@ -153,9 +156,6 @@ static void two_sided(Context& ctx, const Level& l1, const Level& l2, c128* C, i
 
 using namespace fosb;
 
-struct fosb_context : fosb::Context {};
-struct fosb_mesh : fosb::Mesh {};
-struct fosb_level : fosb::Level {};
 
 #define API_BEGIN try {
 #define API_END                                                   \
@@ -183,6 +183,173 @@ struct fosb_level : fosb::Level {};
   do {                     \
     if (!(cond)) fail(FOSB_E_INVALID, __VA_ARGS__); \
   } while (0)
+
+
+struct fosb_context : fosb::Context {};
+struct fosb_mesh : fosb::Mesh {};
+struct fosb_level : fosb::Level {};
+
+namespace fosb {
+
+static void check_level_args(const fosb_mesh* mesh, double k, int32_t precision, void* Z, int64_t ldz, void* Zlow,
+                             int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs, int32_t field) {
+  REQUIRE(std::isfinite(k) && k > 0, "wavenumber must be positive and finite");
+  REQUIRE(precision == FOSB_PREC_FP64 || precision == FOSB_PREC_MIXED, "unknown precision %d", precision);
+  REQUIRE(field == FOSB_FIELD_RADIAL || field == FOSB_FIELD_NORMAL, "unknown field %d", field);
+  REQUIRE(Z, "Z is NULL");
+  REQUIRE(dirs && pols && n_dirs >= 1 && n_dirs <= 4096, "need 1..4096 incidence directions");
+  const int64_t n = mesh->h.ne;
+  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz < N");
+  if (precision == FOSB_PREC_MIXED) {
+    REQUIRE(Zlow, "MIXED precision needs the complex64 buffer Zlow");
+    if (ldzlow < n) fail(FOSB_E_WORKSPACE, "ldzlow < N");
+  } else {
+    REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
+  }
+  for (int64_t d = 0; d < n_dirs; ++d) {
+    double nd = 0, np = 0;
+    for (int c = 0; c < 3; ++c) {
+      REQUIRE(std::isfinite(dirs[3 * d + c]) && std::isfinite(pols[3 * d + c]), "non-finite direction/polarisation");
+      nd += dirs[3 * d + c] * dirs[3 * d + c];
+      np += pols[3 * d + c] * pols[3 * d + c];
+    }
+    REQUIRE(std::fabs(nd - 1.0) < 1e-9, "direction %lld is not a unit vector", (long long)d);
+    REQUIRE(np > 0, "polarisation %lld is zero", (long long)d);
+  }
+}
+
+// Factorisation, first moments and RHS weights of one level, on c's stream.
+static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh, double k, int32_t precision,
+                                               void* Z, int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs,
+                                               const double* pols, int64_t n_dirs, int32_t field,
+                                               const fosb_opts& o) {
+  hipStream_t s = c.stream;
+  const int64_t n = mesh->h.ne;
+  std::unique_ptr<fosb_level> L(new fosb_level());
+  L->ctx = &c;
+  L->mesh = mesh;
+  L->k = k;
+  L->precision = precision;
+  L->n = n;
+  L->Z = Z;
+  L->ldz = ldz;
+  L->Zlow = Zlow;
+  L->ldzlow = ldzlow;
+  L->n_dirs = n_dirs;
+  L->field = field;
+  L->opts = o;
+  const int64_t nblk = (n + kPanel - 1) / kPanel;
+  int64_t info = 0;
+  if (precision == FOSB_PREC_FP64) {
+    L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
+    L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
+    info = lu_factor<double>(c, static_cast<c128*>(Z), n, ldz, L->dinv_L.as<c128>(), L->dinv_U.as<c128>(), L->perm);
+  } else {
+    L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
+    L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
+    copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
+    info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(), L->perm);
+  }
+  if (info != 0) fail(FOSB_E_SINGULAR, "exactly zero pivot at index %lld", (long long)(info - 1));
+  upload(L->d_perm, L->perm, s);
+  // quadrature nodes, first moments and RHS weights
+  L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));
+  quad_nodes(s, *mesh, L->qx.as<double>());
+  std::vector<double> dp(dirs, dirs + 3 * n_dirs), pp(pols, pols + 3 * n_dirs);
+  DevBuf ddir, dpol;
+  upload(ddir, dp, s);
+  upload(dpol, pp, s);
+  L->u.alloc((size_t)n * n_dirs * sizeof(c128));
+  incident_rhs(s, *mesh, k, ddir.as<double>(), dpol.as<double>(), (int)n_dirs, L->u.as<c128>());
+  level_solve_inplace(c, *L, L->u.as<c128>(), n_dirs, n_dirs, nullptr);
+  L->W.alloc((size_t)n_dirs * mesh->h.nt * 18 * sizeof(c128));
+  for (int64_t d = 0; d < n_dirs; ++d)
+    rhs_weights(s, *mesh, k, field, L->u.as<c128>() + d, n_dirs, L->W.as<c128>() + d * mesh->h.nt * 18);
+  FOSB_HIP(hipStreamSynchronize(s));
+  return L;
+}
+
+
+static void check_pair(const fosb_context* ctx, const fosb_level* a, const fosb_level* b) {
+  REQUIRE(a && b, "level is NULL");
+  REQUIRE(a->ctx == ctx && b->ctx == ctx, "level belongs to another context");
+  REQUIRE(a->k == b->k, "levels have different wavenumbers");
+  REQUIRE(a->n_dirs == b->n_dirs, "levels have different incidence sets");
+  REQUIRE(a->field == b->field, "levels use different perturbation fields");
+}
+
+static void check_cov(const fosb_cov* cov) {
+  REQUIRE(cov, "cov is NULL");
+  REQUIRE(cov->kind >= FOSB_COV_GAUSSIAN && cov->kind <= FOSB_COV_NORMAL_DOT, "unknown covariance kind %d", cov->kind);
+  REQUIRE(std::isfinite(cov->sigma) && cov->sigma >= 0, "sigma must be >= 0");
+  if (cov->kind == FOSB_COV_GAUSSIAN || cov->kind == FOSB_COV_MATERN32)
+    REQUIRE(std::isfinite(cov->ell) && cov->ell > 0, "ell must be > 0");
+}
+
+static std::vector<std::array<int32_t, 4>> ct_pairs_vec(int32_t L0, int32_t L) {
+  std::vector<std::array<int32_t, 4>> out;
+  const int32_t tots[2] = {L + L0, L + L0 - 1};
+  const int32_t sg[2] = {1, -1};
+  for (int q = 0; q < 2; ++q)
+    for (int32_t l1 = L; l1 >= L0; --l1) {
+      const int32_t l2 = tots[q] - l1;
+      if (l2 >= L0 && l2 <= l1) out.push_back({l1, l2, sg[q], l1 == l2 ? 1 : 2});
+    }
+  return out;
+}
+
+static void check_far_field_args(const double* xhat, int64_t n_a, int32_t L0, int32_t L,
+                                 const fosb_level* const* levels, void* const* blocks, const int64_t* ldb) {
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  for (int64_t i = 0; i < n_a; ++i) {
+    double nn = xhat[3 * i] * xhat[3 * i] + xhat[3 * i + 1] * xhat[3 * i + 1] + xhat[3 * i + 2] * xhat[3 * i + 2];
+    REQUIRE(std::fabs(nn - 1.0) < 1e-9, "xhat[%lld] is not a unit vector", (long long)i);
+  }
+  auto v = ct_pairs_vec(L0, L);
+  for (size_t p = 0; p < v.size(); ++p) {
+    REQUIRE(blocks[p], "block %zu is NULL", p);
+    if (ldb[p] < levels[v[p][1] - L0]->n) fail(FOSB_E_WORKSPACE, "ldb[%zu] < N_l2", p);
+  }
+}
+
+// var = sum over Lambda_H of sign mult Re diag(FF_l1 Sigma FF_l2^H); mean_F (optional)
+// = FF_L u_L of direction dir.  Synchronises c's stream.
+static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t L0, int32_t L, void* const* blocks,
+                           const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir, double* var,
+                           void* mean_F) {
+  const int32_t n_levels = L - L0 + 1;
+  hipStream_t s = c.stream;
+  std::vector<double> x(xhat, xhat + 3 * n_a);
+  DevBuf dx;
+  upload(dx, x, s);
+  const int64_t rows = 3 * n_a;
+  auto v = ct_pairs_vec(L0, L);
+  std::vector<DevBuf> FF(n_levels);
+  for (int32_t i = 0; i < n_levels; ++i) {
+    FF[i].alloc((size_t)rows * levels[i]->n * sizeof(c128));
+    far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
+  }
+  FOSB_HIP(hipMemsetAsync(var, 0, rows * sizeof(double), s));
+  int64_t maxn2 = 0;
+  for (auto& q : v) maxn2 = std::max(maxn2, levels[q[1] - L0]->n);
+  DevBuf P((size_t)rows * maxn2 * sizeof(c128));
+  for (size_t p = 0; p < v.size(); ++p) {
+    const int i1 = v[p][0] - L0, i2 = v[p][1] - L0;
+    const int64_t n1 = levels[i1]->n, n2 = levels[i2]->n;
+    gemm<double>(c, rows, n2, n1, 1.0, FF[i1].as<c128>(), n1, static_cast<const c128*>(blocks[p]), ldb[p], 0.0,
+                 P.as<c128>(), n2);
+    row_dot_re_accumulate(s, P.as<c128>(), FF[i2].as<c128>(), rows, n2, (double)(v[p][2] * v[p][3]), var);
+  }
+  if (mean_F) {
+    const int iL = n_levels - 1;
+    c.scratch[1].reserve((size_t)levels[iL]->n * sizeof(c128));
+    copy_c128(s, levels[iL]->u.as<c128>() + dir, levels[iL]->n_dirs, c.scratch[1].as<c128>(), 1, levels[iL]->n, 1);
+    matvec_rows(s, FF[iL].as<c128>(), rows, levels[iL]->n, c.scratch[1].as<c128>(), static_cast<c128*>(mean_F));
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace fosb
 
 extern "C" {
 
@@ -296,77 +463,10 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
   REQUIRE(ctx && mesh && out, "ctx/mesh/out is NULL");
   *out = nullptr;
   REQUIRE(mesh->ctx == ctx, "mesh belongs to another context");
-  REQUIRE(std::isfinite(k) && k > 0, "wavenumber must be positive and finite");
-  REQUIRE(precision == FOSB_PREC_FP64 || precision == FOSB_PREC_MIXED, "unknown precision %d", precision);
-  REQUIRE(field == FOSB_FIELD_RADIAL || field == FOSB_FIELD_NORMAL, "unknown field %d", field);
-  REQUIRE(Z, "Z is NULL");
-  REQUIRE(dirs && pols && n_dirs >= 1 && n_dirs <= 4096, "need 1..4096 incidence directions");
-  const int64_t n = mesh->h.ne;
-  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz < N");
-  if (precision == FOSB_PREC_MIXED) {
-    REQUIRE(Zlow, "MIXED precision needs the complex64 buffer Zlow");
-    if (ldzlow < n) fail(FOSB_E_WORKSPACE, "ldzlow < N");
-  } else {
-    REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
-  }
-  for (int64_t d = 0; d < n_dirs; ++d) {
-    double nd = 0, np = 0, dp = 0;
-    for (int c = 0; c < 3; ++c) {
-      REQUIRE(std::isfinite(dirs[3 * d + c]) && std::isfinite(pols[3 * d + c]), "non-finite direction/polarisation");
-      nd += dirs[3 * d + c] * dirs[3 * d + c];
-      np += pols[3 * d + c] * pols[3 * d + c];
-      dp += dirs[3 * d + c] * pols[3 * d + c];
-    }
-    REQUIRE(std::fabs(nd - 1.0) < 1e-9, "direction %lld is not a unit vector", (long long)d);
-    REQUIRE(np > 0, "polarisation %lld is zero", (long long)d);
-    (void)dp;
-  }
+  check_level_args(mesh, k, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, field);
   fosb_opts o = opts_or_default(opts);
   bind(*ctx);
-  hipStream_t s = ctx->stream;
-  std::unique_ptr<fosb_level> L(new fosb_level());
-  L->ctx = ctx;
-  L->mesh = mesh;
-  L->k = k;
-  L->precision = precision;
-  L->n = n;
-  L->Z = Z;
-  L->ldz = ldz;
-  L->Zlow = Zlow;
-  L->ldzlow = ldzlow;
-  L->n_dirs = n_dirs;
-  L->field = field;
-  L->opts = o;
-  const int64_t nblk = (n + kPanel - 1) / kPanel;
-  int64_t info = 0;
-  if (precision == FOSB_PREC_FP64) {
-    L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
-    L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
-    info = lu_factor<double>(*ctx, static_cast<c128*>(Z), n, ldz, L->dinv_L.as<c128>(), L->dinv_U.as<c128>(), L->perm);
-  } else {
-    L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
-    L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
-    copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
-    info = lu_factor<float>(*ctx, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
-                            L->perm);
-  }
-  if (info != 0) fail(FOSB_E_SINGULAR, "exactly zero pivot at index %lld", (long long)(info - 1));
-  upload(L->d_perm, L->perm, s);
-  // quadrature nodes, first moments and RHS weights
-  L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));
-  quad_nodes(s, *mesh, L->qx.as<double>());
-  std::vector<double> dp(dirs, dirs + 3 * n_dirs), pp(pols, pols + 3 * n_dirs);
-  DevBuf ddir, dpol;
-  upload(ddir, dp, s);
-  upload(dpol, pp, s);
-  L->u.alloc((size_t)n * n_dirs * sizeof(c128));
-  incident_rhs(s, *mesh, k, ddir.as<double>(), dpol.as<double>(), (int)n_dirs, L->u.as<c128>());
-  level_solve_inplace(*ctx, *L, L->u.as<c128>(), n_dirs, n_dirs, nullptr);
-  L->W.alloc((size_t)n_dirs * mesh->h.nt * 18 * sizeof(c128));
-  for (int64_t d = 0; d < n_dirs; ++d)
-    rhs_weights(s, *mesh, k, field, L->u.as<c128>() + d, n_dirs, L->W.as<c128>() + d * mesh->h.nt * 18);
-  FOSB_HIP(hipStreamSynchronize(s));
-  *out = L.release();
+  *out = level_build(*ctx, mesh, k, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, field, o).release();
   API_END
 }
 
@@ -421,22 +521,6 @@ fosb_status fosb_level_destroy(fosb_level* level) {
   API_END
 }
 
-static void check_pair(const fosb_context* ctx, const fosb_level* a, const fosb_level* b) {
-  REQUIRE(a && b, "level is NULL");
-  REQUIRE(a->ctx == ctx && b->ctx == ctx, "level belongs to another context");
-  REQUIRE(a->k == b->k, "levels have different wavenumbers");
-  REQUIRE(a->n_dirs == b->n_dirs, "levels have different incidence sets");
-  REQUIRE(a->field == b->field, "levels use different perturbation fields");
-}
-
-static void check_cov(const fosb_cov* cov) {
-  REQUIRE(cov, "cov is NULL");
-  REQUIRE(cov->kind >= FOSB_COV_GAUSSIAN && cov->kind <= FOSB_COV_NORMAL_DOT, "unknown covariance kind %d", cov->kind);
-  REQUIRE(std::isfinite(cov->sigma) && cov->sigma >= 0, "sigma must be >= 0");
-  if (cov->kind == FOSB_COV_GAUSSIAN || cov->kind == FOSB_COV_MATERN32)
-    REQUIRE(std::isfinite(cov->ell) && cov->ell > 0, "ell must be > 0");
-}
-
 fosb_status fosb_rhs_correlation(fosb_context* ctx, const fosb_level* l1, const fosb_level* l2, const fosb_cov* cov,
                                  int64_t dir, void* C, int64_t ldc) {
   API_BEGIN
@@ -459,18 +543,6 @@ fosb_status fosb_two_sided_solve(fosb_context* ctx, const fosb_level* l1, const 
   bind(*ctx);
   two_sided(*ctx, *l1, *l2, static_cast<c128*>(C), ldc, stats);
   API_END
-}
-
-static std::vector<std::array<int32_t, 4>> ct_pairs_vec(int32_t L0, int32_t L) {
-  std::vector<std::array<int32_t, 4>> out;
-  const int32_t tots[2] = {L + L0, L + L0 - 1};
-  const int32_t sg[2] = {1, -1};
-  for (int q = 0; q < 2; ++q)
-    for (int32_t l1 = L; l1 >= L0; --l1) {
-      const int32_t l2 = tots[q] - l1;
-      if (l2 >= L0 && l2 <= l1) out.push_back({l1, l2, sg[q], l1 == l2 ? 1 : 2});
-    }
-  return out;
 }
 
 fosb_status fosb_ct_pairs(int32_t L0, int32_t L, int32_t* l1, int32_t* l2, int32_t* sign, int32_t* mult,
@@ -537,88 +609,13 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
   API_BEGIN
   REQUIRE(ctx && levels && blocks && ldb && xhat && var, "NULL argument");
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
-  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
   REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
-  for (int64_t i = 0; i < n_a; ++i) {
-    double nn = xhat[3 * i] * xhat[3 * i] + xhat[3 * i + 1] * xhat[3 * i + 1] + xhat[3 * i + 2] * xhat[3 * i + 2];
-    REQUIRE(std::fabs(nn - 1.0) < 1e-9, "xhat[%lld] is not a unit vector", (long long)i);
-  }
-  auto v = ct_pairs_vec(L0, L);
-  for (size_t p = 0; p < v.size(); ++p) {
-    REQUIRE(blocks[p], "block %zu is NULL", p);
-    if (ldb[p] < levels[v[p][1] - L0]->n) fail(FOSB_E_WORKSPACE, "ldb[%zu] < N_l2", p);
-  }
+  check_far_field_args(xhat, n_a, L0, L, levels, blocks, ldb);
   bind(*ctx);
-  hipStream_t s = ctx->stream;
-  std::vector<double> x(xhat, xhat + 3 * n_a);
-  DevBuf dx;
-  upload(dx, x, s);
-  const int64_t rows = 3 * n_a;
-  std::vector<DevBuf> FF(n_levels);
-  for (int32_t i = 0; i < n_levels; ++i) {
-    FF[i].alloc((size_t)rows * levels[i]->n * sizeof(c128));
-    far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
-  }
-  FOSB_HIP(hipMemsetAsync(var, 0, rows * sizeof(double), s));
-  int64_t maxn2 = 0;
-  for (auto& q : v) maxn2 = std::max(maxn2, levels[q[1] - L0]->n);
-  DevBuf P((size_t)rows * maxn2 * sizeof(c128));
-  for (size_t p = 0; p < v.size(); ++p) {
-    const int i1 = v[p][0] - L0, i2 = v[p][1] - L0;
-    const int64_t n1 = levels[i1]->n, n2 = levels[i2]->n;
-    gemm<double>(*ctx, rows, n2, n1, 1.0, FF[i1].as<c128>(), n1, static_cast<const c128*>(blocks[p]), ldb[p], 0.0,
-                 P.as<c128>(), n2);
-    row_dot_re_accumulate(s, P.as<c128>(), FF[i2].as<c128>(), rows, n2, (double)(v[p][2] * v[p][3]), var);
-  }
-  if (mean_F) {
-    const int iL = n_levels - 1;
-    ctx->scratch[1].reserve((size_t)levels[iL]->n * sizeof(c128));
-    copy_c128(s, levels[iL]->u.as<c128>() + dir, levels[iL]->n_dirs, ctx->scratch[1].as<c128>(), 1, levels[iL]->n, 1);
-    matvec_rows(s, FF[iL].as<c128>(), rows, levels[iL]->n, ctx->scratch[1].as<c128>(), static_cast<c128*>(mean_F));
-  }
-  FOSB_HIP(hipStreamSynchronize(s));
+  far_field_impl(*ctx, levels, L0, L, blocks, ldb, xhat, n_a, dir, var, mean_F);
   API_END
 }
-
-fosb_status fosb_profile_enable(fosb_context* ctx, int32_t on) {
-  API_BEGIN
-  REQUIRE(ctx, "ctx is NULL");
-  bind(*ctx);
-  if (on) {
-    FOSB_HIP(hipStreamSynchronize(ctx->stream));
-    ctx->recs.clear();
-  }
-  ctx->prof_on = on != 0;
-  API_END
-}
-
-fosb_status fosb_profile_read(fosb_context* ctx, int32_t cls, int64_t* launches, double* seconds, double* flops,
-                              double* bytes) {
-  API_BEGIN
-  REQUIRE(ctx, "ctx is NULL");
-  REQUIRE(cls >= 0 && cls < FOSB_K_COUNT, "unknown kernel class %d", cls);
-  bind(*ctx);
-  FOSB_HIP(hipStreamSynchronize(ctx->stream));
-  int64_t cnt = 0;
-  double sec = 0, fl = 0, by = 0;
-  for (const ProfRec& r : ctx->recs) {
-    if (r.cls != cls) continue;
-    float ms = 0.f;
-    FOSB_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[r.ev], ctx->ev_pool[r.ev + 1]));
-    ++cnt;
-    sec += 1e-3 * ms;
-    fl += r.flops;
-    by += r.bytes;
-  }
-  if (launches) *launches = cnt;
-  if (seconds) *seconds = sec;
-  if (flops) *flops = fl;
-  if (bytes) *bytes = by;
-  API_END
-}
-
-}  // extern "C"
 
 fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
                                             int32_t L0, int32_t L, const fosb_cov* cov, const double* xhat,
@@ -695,3 +692,162 @@ fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level*
   FOSB_HIP(hipStreamSynchronize(s));
   API_END
 }
+
+fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes, int32_t n_levels, int32_t L0,
+                               int32_t L, double k, int32_t precision, void* const* Z, const int64_t* ldz,
+                               void* const* Zlow, const int64_t* ldzlow, const double* dirs, const double* pols,
+                               int64_t n_dirs, int32_t field, const fosb_cov* cov, int64_t dir, const double* xhat,
+                               int64_t n_a, void* const* blocks, const int64_t* ldb, double* var,
+                               const fosb_opts* opts, fosb_level** levels_out, fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && meshes && Z && ldz && blocks && ldb && xhat && var, "NULL argument");
+  REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  REQUIRE(precision == FOSB_PREC_FP64 || (Zlow && ldzlow), "MIXED precision needs Zlow and ldzlow");
+  for (int32_t i = 0; i < n_levels; ++i) {
+    REQUIRE(meshes[i] && meshes[i]->ctx == ctx, "mesh %d is NULL or belongs to another context", i);
+    if (i > 0) REQUIRE(meshes[i]->h.ne > meshes[i - 1]->h.ne, "levels must be ordered coarse to fine");
+    check_level_args(meshes[i], k, precision, Z[i], ldz[i], precision == FOSB_PREC_MIXED ? Zlow[i] : nullptr,
+                     precision == FOSB_PREC_MIXED ? ldzlow[i] : 0, dirs, pols, n_dirs, field);
+  }
+  check_cov(cov);
+  REQUIRE(dir >= 0 && dir < n_dirs, "dir out of range");
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  auto v = ct_pairs_vec(L0, L);
+  for (size_t p = 0; p < v.size(); ++p) {
+    REQUIRE(blocks[p], "block %zu is NULL", p);
+    if (ldb[p] < meshes[v[p][1] - L0]->h.ne) fail(FOSB_E_WORKSPACE, "ldb[%zu] < N_l2", p);
+  }
+  const fosb_opts o = opts_or_default(opts);
+  bind(*ctx);
+  Context& aux = ctx->aux_context();
+  const int top = n_levels - 1;
+  std::vector<std::unique_ptr<fosb_level>> lv(n_levels);
+  fosb_stats st_main{}, st_aux{};
+
+  auto build = [&](Context& c, int i) {
+    {
+      const double ne = (double)meshes[i]->h.ne;
+      ProfScope prof(c, FOSB_K_ASSEMBLE, 0.0, 16.0 * ne * ne);
+      assemble_efie(c, *meshes[i], k, o.n_gauss_singular, static_cast<c128*>(Z[i]), ldz[i]);
+    }
+    lv[i] = level_build(c, meshes[i], k, precision, Z[i], ldz[i],
+                        precision == FOSB_PREC_MIXED ? Zlow[i] : nullptr,
+                        precision == FOSB_PREC_MIXED ? ldzlow[i] : 0, dirs, pols, n_dirs, field, o);
+  };
+  auto pair = [&](Context& c, size_t p, fosb_stats* st) {
+    const fosb_level& a = *lv[v[p][0] - L0];
+    const fosb_level& b = *lv[v[p][1] - L0];
+    c128* C = static_cast<c128*>(blocks[p]);
+    {
+      ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)a.n * (double)b.n);
+      rhs_correlation_kernel(c.stream, a, b, *cov, dir, C, ldb[p]);
+    }
+    two_sided(c, a, b, C, ldb[p], st);
+  };
+
+  // The finest level (the bulk of the work) is built on the context's stream
+  // while a worker thread builds the coarser levels and solves the pairs that
+  // do not involve the finest level on the auxiliary stream; the pairs with
+  // the finest level follow on the main stream once the coarse levels exist.
+  std::mutex mu;
+  std::condition_variable cv;
+  bool coarse_ready = false;
+  std::exception_ptr aux_err;
+  std::thread worker([&] {
+    try {
+      FOSB_HIP(hipSetDevice(ctx->device));
+      for (int i = top - 1; i >= 0; --i) build(aux, i);
+    } catch (...) {
+      aux_err = std::current_exception();
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      coarse_ready = true;
+    }
+    cv.notify_all();
+    if (aux_err) return;
+    try {
+      for (size_t p = 0; p < v.size(); ++p)
+        if (v[p][0] != L) pair(aux, p, &st_aux);
+      FOSB_HIP(hipStreamSynchronize(aux.stream));
+    } catch (...) {
+      aux_err = std::current_exception();
+    }
+  });
+  struct Joiner {
+    std::thread& t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } joiner{worker};
+  build(*ctx, top);
+  {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return coarse_ready; });
+  }
+  if (!aux_err)
+    for (size_t p = 0; p < v.size(); ++p)
+      if (v[p][0] == L) pair(*ctx, p, &st_main);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  worker.join();
+  if (aux_err) std::rethrow_exception(aux_err);
+
+  std::vector<const fosb_level*> lp(n_levels);
+  for (int i = 0; i < n_levels; ++i) {
+    lv[i]->ctx = ctx;  // handles belong to the caller's context from here on
+    lp[i] = lv[i].get();
+  }
+  far_field_impl(*ctx, lp.data(), L0, L, blocks, ldb, xhat, n_a, dir, var, nullptr);
+  if (stats) {
+    stats->ir_sweeps = std::max(stats->ir_sweeps, std::max(st_main.ir_sweeps, st_aux.ir_sweeps));
+    stats->n_solves += st_main.n_solves + st_aux.n_solves;
+    stats->ir_rel_correction =
+        std::max(stats->ir_rel_correction, std::max(st_main.ir_rel_correction, st_aux.ir_rel_correction));
+  }
+  if (levels_out)
+    for (int i = 0; i < n_levels; ++i) levels_out[i] = lv[i].release();
+  API_END
+}
+
+fosb_status fosb_profile_enable(fosb_context* ctx, int32_t on) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  bind(*ctx);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->aux) FOSB_HIP(hipStreamSynchronize(ctx->aux->stream));
+  {
+    std::lock_guard<std::mutex> lock(ctx->prof_mu);
+    if (on) ctx->recs.clear();
+    ctx->prof_on = on != 0;
+  }
+  API_END
+}
+
+fosb_status fosb_profile_read(fosb_context* ctx, int32_t cls, int64_t* launches, double* seconds, double* flops,
+                              double* bytes) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  REQUIRE(cls >= 0 && cls < FOSB_K_COUNT, "unknown kernel class %d", cls);
+  bind(*ctx);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->aux) FOSB_HIP(hipStreamSynchronize(ctx->aux->stream));
+  std::lock_guard<std::mutex> lock(ctx->prof_mu);
+  int64_t cnt = 0;
+  double sec = 0, fl = 0, by = 0;
+  for (const ProfRec& r : ctx->recs) {
+    if (r.cls != cls) continue;
+    float ms = 0.f;
+    FOSB_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[r.ev], ctx->ev_pool[r.ev + 1]));
+    ++cnt;
+    sec += 1e-3 * ms;
+    fl += r.flops;
+    by += r.bytes;
+  }
+  if (launches) *launches = cnt;
+  if (seconds) *seconds = sec;
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
+  API_END
+}
+
+}  // extern "C"

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -101,17 +102,27 @@ struct Context {
   DevBuf ss[13];
   int ss_off[13][3] = {};
   int ss_cnt[13][3] = {};
-  // profiler (fosb_profile_*): event pool and records of the current session
+  // profiler (fosb_profile_*): event pool and records of the current session,
+  // kept by the root context for itself and its auxiliary context
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<ProfRec> recs;
+  std::mutex prof_mu;
+  // auxiliary context: own stream (created by the library, default priority)
+  // and own scratch, used by the concurrent pipeline; its profiler root is the
+  // owning context
+  Context* prof_root = nullptr;
+  bool owns_stream = false;
+  std::unique_ptr<Context> aux;
+  Context& aux_context();
   ~Context();
 };
 
 // Brackets the launches issued during its lifetime with a pair of events when
 // the context's profiler is on.
 struct ProfScope {
-  Context& ctx;
+  Context& ctx;      // records go to the root context ...
+  hipStream_t stream;  // ... events are recorded on the launching context's stream
   int idx = -1;
   ProfScope(Context& c, int cls, double flops, double bytes);
   ~ProfScope();

@@ -79,6 +79,10 @@ _SIGS = {
                                          _I64, _I64, _P, _P]),
     "fosb_far_field_moments_backward": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
                                                   _I64, _P, _P, C.POINTER(Stats)]),
+    "fosb_second_moment": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, _D, _I32, C.POINTER(_P), C.POINTER(_I64),
+                                     C.POINTER(_P), C.POINTER(_I64), _P, _P, _I64, _I32, C.POINTER(Cov), _I64, _P,
+                                     _I64, C.POINTER(_P), C.POINTER(_I64), _P, C.POINTER(Opts), C.POINTER(_P),
+                                     C.POINTER(Stats)]),
     "fosb_profile_enable": (C.c_int, [_P, _I32]),
     "fosb_profile_read": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
 }
@@ -269,6 +273,14 @@ class Level:
                                       C.byref(st)))
         return B
 
+    @classmethod
+    def _adopt(cls, ctx: "Context", mesh: "Mesh", k: float, h, precision: int, Z, Zlow, n_dirs: int):
+        """Wrap a handle created by the library (fosb_second_moment)."""
+        self = cls.__new__(cls)
+        self.ctx, self.mesh, self.k, self.Z, self.Zlow = ctx, mesh, float(k), Z, Zlow
+        self.precision, self.h, self.n, self.n_dirs = precision, h, mesh.n_edges, n_dirs
+        return self
+
     def solve_adjoint(self, B, stats: Stats | None = None):
         """B <- Z^{-H} B in place."""
         import torch
@@ -420,6 +432,52 @@ def rcs_variance(ctx: Context, levels: list[Level], L0: int, L: int, kind: str, 
     if _RCS_VARIANCE is None:
         _RCS_VARIANCE = _variance_function()
     return _RCS_VARIANCE.apply(sigma, ell, ctx, levels, L0, L, kind, xhat, dir)
+
+
+def second_moment(ctx: Context, meshes: list[Mesh], L0: int, L: int, k: float, precision: int, cov: Cov, xhat,
+                  dirs=((0.0, 0.0, 1.0),), pols=((1.0, 0.0, 0.0),), field: str | int = "radial", dir: int = 0,
+                  Z=None, Zlow=None, blocks=None, opts: Opts | None = None, keep_levels: bool = False,
+                  stats: Stats | None = None):
+    """fosb_second_moment: the whole hot path over the ladder meshes (levels
+    L0..L, coarse to fine) with the library's two-stream schedule.  Returns
+    (var (3, n_a), blocks, levels or None)."""
+    import torch
+    n = len(meshes)
+    dev = ctx.torch_device
+    if Z is None:
+        Z = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex128, device=dev) for m in meshes]
+    if precision == MIXED and Zlow is None:
+        Zlow = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex64, device=dev) for m in meshes]
+    pairs = ct_pairs(L0, L)
+    if blocks is None:
+        blocks = [torch.empty((meshes[a - L0].n_edges, meshes[b - L0].n_edges), dtype=torch.complex128, device=dev)
+                  for a, b, _, _ in pairs]
+    x = _host_f64(xhat).reshape(-1, 3)
+    d = _host_f64(dirs).reshape(-1, 3)
+    p = _host_f64(pols).reshape(-1, 3)
+    var = torch.empty(3 * x.shape[0], dtype=torch.float64, device=dev)
+    st = stats if stats is not None else Stats()
+    ms = (_P * n)(*[m.h for m in meshes])
+    zp = (_P * n)(*[_dev(z, torch.complex128) for z in Z])
+    zl = (_I64 * n)(*[z.stride(0) for z in Z])
+    if precision == MIXED:
+        lp = (_P * n)(*[_dev(z, torch.complex64) for z in Zlow])
+        ll = (_I64 * n)(*[z.stride(0) for z in Zlow])
+    else:
+        lp, ll = None, None
+    bp = (_P * len(blocks))(*[_dev(b, torch.complex128) for b in blocks])
+    bl = (_I64 * len(blocks))(*[b.stride(0) for b in blocks])
+    out = (_P * n)() if keep_levels else None
+    fld = FIELDS[field] if isinstance(field, str) else int(field)
+    _check(lib().fosb_second_moment(ctx.h, ms, n, L0, L, float(k), precision, zp, zl, lp, ll, d.ctypes.data_as(_P),
+                                    p.ctypes.data_as(_P), d.shape[0], fld, C.byref(cov), dir, x.ctypes.data_as(_P),
+                                    x.shape[0], bp, bl, _dev(var, torch.float64), C.byref(opts) if opts else None,
+                                    out, C.byref(st)))
+    levels = None
+    if keep_levels:
+        levels = [Level._adopt(ctx, meshes[i], k, _P(out[i]), precision, Z[i],
+                               Zlow[i] if precision == MIXED else None, d.shape[0]) for i in range(n)]
+    return var.view(3, -1), blocks, levels
 
 
 @dataclass

@@ -1,0 +1,97 @@
+"""fosb_second_moment (two-stream schedule of the whole hot path) against the
+step-by-step calls and the oracle, on the plain FP64 workload (unit icosphere
+s=1..3, k=1, L0=1, L=3, 181 angles, radial Gaussian covariance 0.01 / 0.5).
+
+The kernels are deterministic and the schedule only changes which stream
+runs them, so blocks and variance must equal the step-by-step results
+exactly."""
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+K1 = 1.0
+SIG, ELL = 0.01, 0.5
+
+
+@pytest.fixture(scope="module")
+def fz():
+    import torch
+    from paper_2308_01457_amd import fosb
+    assert torch.cuda.is_available()
+    return fosb, fosb.Context(0), torch
+
+
+def _step_by_step(fosb, ctx, meshes, L0, L, prec, cov, xh, opts=None):
+    levels = []
+    for m in meshes:
+        Z = fosb.assemble(ctx, m, K1, opts)
+        levels.append(fosb.Level(ctx, m, K1, Z, prec, opts=opts))
+    blocks = fosb.correlation(ctx, levels, L0, L, cov)
+    var = fosb.far_field_moments(ctx, levels, L0, L, blocks, xh)
+    return var.cpu().numpy(), [b.cpu().numpy() for b in blocks], levels
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pipeline_equals_step_by_step(fz, oracle_levels, precision):
+    fosb, ctx, torch = fz
+    from oracle import uq
+    prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
+    xh = workloads.angles_xz(181)
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    meshes = [fosb.Mesh(ctx, *workloads.icosphere(s)) for s in (1, 2, 3)]
+    print(f"[gpu] pipeline {precision} s=1..3", flush=True)
+    st = fosb.Stats()
+    var, blocks, _ = fosb.second_moment(ctx, meshes, 1, 3, K1, prec, cov, xh, stats=st)
+    v_ref, b_ref, _ = _step_by_step(fosb, ctx, meshes, 1, 3, prec, cov, xh)
+    assert np.array_equal(var.cpu().numpy(), v_ref)
+    for b, r in zip(blocks, b_ref):
+        assert np.array_equal(b.cpu().numpy(), r)
+    olv = {s: oracle_levels(s) for s in (1, 2, 3)}
+    Vo = uq.second_moment(None, K1, 1, 3, "gaussian", SIG, ELL, xh, levels=olv)[0]
+    e = float(np.linalg.norm(var.cpu().numpy() - Vo) / np.linalg.norm(Vo))
+    print(f"[gpu]   variance vs oracle {e:.2e}, sweeps {st.ir_sweeps}, solves {st.n_solves}", flush=True)
+    assert e < (1e-10 if precision == "fp64" else 1e-5)
+    assert st.n_solves == 3
+
+
+def test_pipeline_single_level_and_handles(fz):
+    """L0 = L (no auxiliary work), and the returned handles serve the adjoint."""
+    fosb, ctx, torch = fz
+    xh = workloads.angles_xz(37)
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    meshes = [fosb.Mesh(ctx, *workloads.icosphere(2))]
+    print("[gpu] pipeline single level s=2", flush=True)
+    var, blocks, levels = fosb.second_moment(ctx, meshes, 2, 2, K1, fosb.FP64, cov, xh, keep_levels=True)
+    v_ref, b_ref, lv_ref = _step_by_step(fosb, ctx, meshes, 2, 2, fosb.FP64, cov, xh)
+    assert np.array_equal(var.cpu().numpy(), v_ref)
+    ones = torch.ones((3, 37), dtype=torch.float64, device=ctx.torch_device)
+    g1 = fosb.far_field_moments_backward(ctx, levels, 2, 2, cov, xh, ones).cpu().numpy()
+    g2 = fosb.far_field_moments_backward(ctx, lv_ref, 2, 2, cov, xh, ones).cpu().numpy()
+    assert np.array_equal(g1, g2)
+    print("[gpu] pipeline with handles kept, s=1..3 mixed", flush=True)
+    meshes = [fosb.Mesh(ctx, *workloads.icosphere(s)) for s in (1, 2, 3)]
+    var, blocks, levels = fosb.second_moment(ctx, meshes, 1, 3, K1, fosb.MIXED, cov, xh, keep_levels=True)
+    g3 = fosb.far_field_moments_backward(ctx, levels, 1, 3, cov, xh, ones).cpu().numpy()
+    assert abs(g3[2] - float(var.sum().item())) < 1e-10 * abs(g3[2])
+
+
+def test_pipeline_rejects_bad_ladders(fz):
+    fosb, ctx, torch = fz
+    xh = workloads.angles_xz(5)
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    m1, m2 = (fosb.Mesh(ctx, *workloads.icosphere(s)) for s in (1, 2))
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.second_moment(ctx, [m2, m1], 1, 2, K1, fosb.FP64, cov, xh)     # fine to coarse
+    assert e.value.name == "E_INVALID"
+    Z = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex128, device=ctx.torch_device) for m in (m1, m2)]
+    blocks = [torch.empty((1, 1), dtype=torch.complex128, device=ctx.torch_device) for _ in range(3)]
+    with pytest.raises(fosb.FosbError) as e:                                # n_levels != L - L0 + 1
+        fosb.second_moment(ctx, [m1, m2], 1, 3, K1, fosb.FP64, cov, xh, Z=Z, blocks=blocks)
+    assert e.value.name == "E_INVALID"
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.second_moment(ctx, [m1, m2], 1, 2, -1.0, fosb.FP64, cov, xh)   # wavenumber
+    assert e.value.name == "E_INVALID"
