@@ -75,6 +75,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--progress", action="store_true", help="print a line after every stage of every step")
+    ap.add_argument("--workload", default="mixed_k5", choices=["mixed_k5", "ellipsoids"],
+                    help="mixed_k5: the k=5 icosphere ladder (default); ellipsoids: 64 seeded ellipsoids x 16 "
+                         "incidences, 3 levels each, Matern-3/2 covariance, all incidences solved together")
+    ap.add_argument("--shapes", type=int, default=64, help="ellipsoids: number of shapes")
     ap.add_argument("--schedule", default="concurrent", choices=["concurrent", "sequential"],
                     help="concurrent: the library's two-stream pipeline (fosb_second_moment); sequential: the "
                          "step-by-step calls, timed per stage")
@@ -224,6 +228,81 @@ def run_gpu(args, W):
     return out, (lu_f, solve_f, ff_f, npairs)
 
 
+def run_batched(args):
+    """64 seeded ellipsoids (semi-axes U[0.7, 1.3], geodesic levels nu/4, nu/2,
+    nu with nu ~ U{8..16}: 1280..5120 top triangles), k ~ U[1, 4], 16
+    incidences each, Matern-3/2 radial covariance (0.01, ell ~ U[0.3, 0.8]),
+    CT L0 = 0, L = 2 (3 pairs), 181 angles: 3 x 16 x 64 = 3072 level-pair
+    solves per step, every shape through fosb_second_moment with its 16
+    incidences stacked as right-hand sides."""
+    import torch
+
+    import workloads
+    from paper_2308_01457_amd import fosb
+    shapes = workloads.batched_ellipsoids(args.shapes, 16, 0)
+    ctx = fosb.Context(0)
+    dev = ctx.torch_device
+    xh = workloads.angles_xz(181)
+    meshes = [[fosb.Mesh(ctx, V, F) for V, F in w.meshes] for w in shapes]
+    N = [[m.n_edges for m in ms] for ms in meshes]
+    nmax = [max(n[i] for n in N) for i in range(3)]
+    Zb = [torch.empty(nmax[i] ** 2, dtype=torch.complex128, device=dev) for i in range(3)]
+    Zl = [torch.empty(nmax[i] ** 2, dtype=torch.complex64, device=dev) for i in range(3)]
+    pairs = fosb.ct_pairs(0, 2)
+    Bb = [torch.empty(nmax[a] * 16 * nmax[b], dtype=torch.complex128, device=dev) for a, b, _, _ in pairs]
+    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
+    npairs = len(pairs) * 16 * len(shapes)
+    precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    out = {}
+
+    def step(prec):
+        res = []
+        st = fosb.Stats()
+        for w, ms, n in zip(shapes, meshes, N):
+            Z = [Zb[i][: n[i] ** 2].view(n[i], n[i]) for i in range(3)]
+            Zlo = [Zl[i][: n[i] ** 2].view(n[i], n[i]) for i in range(3)] if prec == fosb.MIXED else None
+            blocks = [Bb[p][: n[a] * 16 * n[b]].view(n[a], 16 * n[b]) for p, (a, b, _, _) in enumerate(pairs)]
+            cov = fosb.make_cov("matern32", w.sigma, w.ell)
+            var, _, _ = fosb.second_moment(ctx, ms, 0, 2, w.k, prec, cov, xh, w.dirs, w.pols, "radial", -1, Z=Z,
+                                           Zlow=Zlo, blocks=blocks, opts=opts, stats=st)
+            res.append(var)
+        return res, st
+
+    for pname in precs:
+        prec = fosb.MIXED if pname == "mixed" else fosb.FP64
+        log(f"[bench] ellipsoids {pname}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            step(prec)
+        times = []
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, st = step(prec)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            log(f"[bench] ellipsoids {pname} step {i}: {times[-1]:.3f} s  (ir sweeps {st.ir_sweeps})")
+        t = float(np.mean(times))
+        out[pname] = {"seconds_per_step": t, "pair_solves_per_s": npairs / t, "ir_sweeps": int(st.ir_sweeps),
+                      "var": torch.stack([r.reshape(-1) for r in [x.reshape(-1) for x in res]]).cpu().numpy()}
+    head = "mixed" if "mixed" in out else "fp64"
+    line = {"metric": "Cor[u'] level-pair solves/sec + MFMA TFLOP/s, mixed vs FP64 at 1e-6 rel err",
+            "value": out[head]["pair_solves_per_s"], "unit": "level-pair solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[head]["seconds_per_step"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "c64+f64" if head == "mixed" else "c128", "data": "synthetic",
+            "config": {"workload": f"batched ellipsoids: {len(shapes)} shapes x 16 incidences, geodesic levels "
+                                   f"nu/4, nu/2, nu (top 1280..5120 triangles), k ~ U[1,4], Matern-3/2 (0.01, "
+                                   f"U[0.3,0.8]), L0=0 L=2 (3 pairs), 181 angles, incidences stacked",
+                       "precision": head, "ir_tol": args.ir_tol, "level_pair_solves": npairs}}
+    for pname, rec in out.items():
+        line[pname] = {k: v for k, v in rec.items() if k != "var"}
+    if "mixed" in out and "fp64" in out:
+        a, b = out["mixed"]["var"], out["fp64"]["var"]
+        line["mixed_speedup_vs_fp64"] = out["fp64"]["seconds_per_step"] / out["mixed"]["seconds_per_step"]
+        line["mixed_vs_fp64_var_rel_err"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(W):
     """The oracle on a bounded sample of the same workload: levels s = 2, 3 of
     the ladder (480 and 1920 RWG) timed stage by stage on the host, then
@@ -310,6 +389,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "ellipsoids":
+        run_batched(args)
+        return
     W = Workload(args.max_level)
     gpu, (lu_f, solve_f, ff_f, npairs) = run_gpu(args, W)
     head = "mixed" if "mixed" in gpu else "fp64"

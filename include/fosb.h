@@ -239,7 +239,11 @@ fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level*
  * factorisation, first moments and RHS weights of every level, the RHS
  * correlation and two-sided solve of every pair of fosb_ct_pairs(L0, L) into
  * blocks[p] (as fosb_correlation), and the far-field variance var (device,
- * 3 n_a float64, as fosb_far_field_moments) for incidence dir.  The same
+ * 3 n_a float64, as fosb_far_field_moments) for incidence dir.  dir = -1
+ * solves all n_dirs incidences together, their right-hand sides stacked:
+ * blocks[p] is then N_l1 x (n_dirs N_l2) with incidence d in columns
+ * d N_l2 .. (d+1) N_l2 (ldb[p] >= n_dirs N_l2), and var holds n_dirs
+ * consecutive 3 n_a vectors.  The same
  * results as the step-by-step calls; the work is scheduled over two streams:
  * the finest level on the context's stream, the coarser levels and the pairs
  * among them concurrently on an auxiliary stream the context owns (a second

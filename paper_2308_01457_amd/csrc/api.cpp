@@ -138,18 +138,21 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   }
 }
 
-static void two_sided(Context& ctx, const Level& l1, const Level& l2, c128* C, int64_t ldc, fosb_stats* st) {
+// In place: C <- Sigma with Z1 Sigma Z2^H = C for nd incidences stacked side by
+// side (C is N1 x nd*N2, direction d in columns d*N2 .. (d+1)*N2): one solve
+// with nd*N2 right-hand sides, per-direction conjugate transposes into an
+// N2 x nd*N1 slab, one solve with nd*N1 right-hand sides, and back.
+static void two_sided(Context& ctx, const Level& l1, const Level& l2, c128* C, int64_t ldc, fosb_stats* st,
+                      int64_t nd = 1) {
   const int64_t n1 = l1.n, n2 = l2.n;
-  // stage 1: Y = Z1^{-1} C   (n1 x n2)
-  level_solve_inplace(ctx, l1, C, ldc, n2, st);
-  // stage 2: Sigma^H = Z2^{-1} Y^H  (n2 x n1)
+  level_solve_inplace(ctx, l1, C, ldc, nd * n2, st);
   DevBuf& tb = ctx.scratch[0];
-  tb.reserve((size_t)n1 * n2 * sizeof(c128));
+  tb.reserve((size_t)n1 * n2 * nd * sizeof(c128));
   c128* Tt = tb.as<c128>();
-  conj_transpose_c128(ctx.stream, C, ldc, Tt, n1, n1, n2);
-  level_solve_inplace(ctx, l2, Tt, n1, n1, st);
-  conj_transpose_c128(ctx.stream, Tt, n1, C, ldc, n2, n1);
-  if (st) st->n_solves += 1;
+  for (int64_t d = 0; d < nd; ++d) conj_transpose_c128(ctx.stream, C + d * n2, ldc, Tt + d * n1, nd * n1, n1, n2);
+  level_solve_inplace(ctx, l2, Tt, nd * n1, nd * n1, st);
+  for (int64_t d = 0; d < nd; ++d) conj_transpose_c128(ctx.stream, Tt + d * n1, nd * n1, C + d * n2, ldc, n2, n1);
+  if (st) st->n_solves += (int32_t)nd;
 }
 
 }  // namespace fosb
@@ -312,10 +315,12 @@ static void check_far_field_args(const double* xhat, int64_t n_a, int32_t L0, in
   }
 }
 
-// var = sum over Lambda_H of sign mult Re diag(FF_l1 Sigma FF_l2^H); mean_F (optional)
-// = FF_L u_L of direction dir.  Synchronises c's stream.
+// var = sum over Lambda_H of sign mult Re diag(FF_l1 Sigma FF_l2^H) for nd
+// incidences dir0 .. dir0+nd-1 (blocks stacked side by side as in two_sided,
+// var[d*3 n_a ..]); mean_F (optional) = FF_L u_L per direction.  The far-field
+// maps are formed once.  Synchronises c's stream.
 static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t L0, int32_t L, void* const* blocks,
-                           const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir, double* var,
+                           const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir0, int64_t nd, double* var,
                            void* mean_F) {
   const int32_t n_levels = L - L0 + 1;
   hipStream_t s = c.stream;
@@ -329,22 +334,29 @@ static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t 
     FF[i].alloc((size_t)rows * levels[i]->n * sizeof(c128));
     far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
   }
-  FOSB_HIP(hipMemsetAsync(var, 0, rows * sizeof(double), s));
+  FOSB_HIP(hipMemsetAsync(var, 0, nd * rows * sizeof(double), s));
+  // one product FF_l1 [Sigma_0 | Sigma_1 | ...] per pair covers every incidence
   int64_t maxn2 = 0;
   for (auto& q : v) maxn2 = std::max(maxn2, levels[q[1] - L0]->n);
-  DevBuf P((size_t)rows * maxn2 * sizeof(c128));
+  DevBuf P((size_t)rows * nd * maxn2 * sizeof(c128));
   for (size_t p = 0; p < v.size(); ++p) {
     const int i1 = v[p][0] - L0, i2 = v[p][1] - L0;
     const int64_t n1 = levels[i1]->n, n2 = levels[i2]->n;
-    gemm<double>(c, rows, n2, n1, 1.0, FF[i1].as<c128>(), n1, static_cast<const c128*>(blocks[p]), ldb[p], 0.0,
-                 P.as<c128>(), n2);
-    row_dot_re_accumulate(s, P.as<c128>(), FF[i2].as<c128>(), rows, n2, (double)(v[p][2] * v[p][3]), var);
+    gemm<double>(c, rows, nd * n2, n1, 1.0, FF[i1].as<c128>(), n1, static_cast<const c128*>(blocks[p]), ldb[p], 0.0,
+                 P.as<c128>(), nd * n2);
+    for (int64_t d = 0; d < nd; ++d)
+      row_dot_re_accumulate(s, P.as<c128>() + d * n2, nd * n2, FF[i2].as<c128>(), rows, n2,
+                            (double)(v[p][2] * v[p][3]), var + d * rows);
   }
   if (mean_F) {
     const int iL = n_levels - 1;
     c.scratch[1].reserve((size_t)levels[iL]->n * sizeof(c128));
-    copy_c128(s, levels[iL]->u.as<c128>() + dir, levels[iL]->n_dirs, c.scratch[1].as<c128>(), 1, levels[iL]->n, 1);
-    matvec_rows(s, FF[iL].as<c128>(), rows, levels[iL]->n, c.scratch[1].as<c128>(), static_cast<c128*>(mean_F));
+    for (int64_t d = 0; d < nd; ++d) {
+      copy_c128(s, levels[iL]->u.as<c128>() + dir0 + d, levels[iL]->n_dirs, c.scratch[1].as<c128>(), 1,
+                levels[iL]->n, 1);
+      matvec_rows(s, FF[iL].as<c128>(), rows, levels[iL]->n, c.scratch[1].as<c128>(),
+                  static_cast<c128*>(mean_F) + d * rows);
+    }
   }
   FOSB_HIP(hipStreamSynchronize(s));
 }
@@ -613,7 +625,7 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
   REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
   check_far_field_args(xhat, n_a, L0, L, levels, blocks, ldb);
   bind(*ctx);
-  far_field_impl(*ctx, levels, L0, L, blocks, ldb, xhat, n_a, dir, var, mean_F);
+  far_field_impl(*ctx, levels, L0, L, blocks, ldb, xhat, n_a, dir, 1, var, mean_F);
   API_END
 }
 
@@ -710,12 +722,14 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
                      precision == FOSB_PREC_MIXED ? ldzlow[i] : 0, dirs, pols, n_dirs, field);
   }
   check_cov(cov);
-  REQUIRE(dir >= 0 && dir < n_dirs, "dir out of range");
+  REQUIRE(dir >= -1 && dir < n_dirs, "dir out of range");
+  const int64_t nd = dir < 0 ? n_dirs : 1;   // incidences solved together
+  const int64_t d0 = dir < 0 ? 0 : dir;
   REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
   auto v = ct_pairs_vec(L0, L);
   for (size_t p = 0; p < v.size(); ++p) {
     REQUIRE(blocks[p], "block %zu is NULL", p);
-    if (ldb[p] < meshes[v[p][1] - L0]->h.ne) fail(FOSB_E_WORKSPACE, "ldb[%zu] < N_l2", p);
+    if (ldb[p] < nd * meshes[v[p][1] - L0]->h.ne) fail(FOSB_E_WORKSPACE, "ldb[%zu] < n_dirs N_l2", p);
   }
   const fosb_opts o = opts_or_default(opts);
   bind(*ctx);
@@ -739,10 +753,13 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
     const fosb_level& b = *lv[v[p][1] - L0];
     c128* C = static_cast<c128*>(blocks[p]);
     {
-      ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)a.n * (double)b.n);
-      rhs_correlation_kernel(c.stream, a, b, *cov, dir, C, ldb[p]);
+      ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)nd * (double)a.n * (double)b.n);
+      if (nd == 1)
+        rhs_correlation_kernel(c.stream, a, b, *cov, d0, C, ldb[p]);
+      else
+        rhs_correlation_multi(c.stream, a, b, *cov, d0, nd, C, ldb[p], b.n);
     }
-    two_sided(c, a, b, C, ldb[p], st);
+    two_sided(c, a, b, C, ldb[p], st, nd);
   };
 
   // The finest level (the bulk of the work) is built on the context's stream
@@ -797,7 +814,7 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
     lv[i]->ctx = ctx;  // handles belong to the caller's context from here on
     lp[i] = lv[i].get();
   }
-  far_field_impl(*ctx, lp.data(), L0, L, blocks, ldb, xhat, n_a, dir, var, nullptr);
+  far_field_impl(*ctx, lp.data(), L0, L, blocks, ldb, xhat, n_a, d0, nd, var, nullptr);
   if (stats) {
     stats->ir_sweeps = std::max(stats->ir_sweeps, std::max(st_main.ir_sweeps, st_aux.ir_sweeps));
     stats->n_solves += st_main.n_solves + st_aux.n_solves;

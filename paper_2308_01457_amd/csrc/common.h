@@ -259,10 +259,13 @@ void quad_nodes(hipStream_t s, const Mesh& m, double* qx);
 void rhs_weights(hipStream_t s, const Mesh& m, double k, int field, const c128* u, int64_t ustride, c128* W);
 void rhs_correlation_kernel(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t dir,
                             c128* C, int64_t ldc);
+// C_d = Wgt_l1(dir0 + d) K Wgt_l2(dir0 + d)^H for d < nd at C + d * dstride (row stride ldc)
+void rhs_correlation_multi(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t dir0,
+                           int64_t nd, c128* C, int64_t ldc, int64_t dstride);
 void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a,
                              c128* FF);
-void row_dot_re_accumulate(hipStream_t s, const c128* P, const c128* FF2, int64_t rows, int64_t n, double scale,
-                           double* var);
+void row_dot_re_accumulate(hipStream_t s, const c128* P, int64_t ldp, const c128* FF2, int64_t rows, int64_t n,
+                           double scale, double* var);
 void matvec_rows(hipStream_t s, const c128* FF, int64_t rows, int64_t n, const c128* u, c128* out);
 // adjoint of the variance: node rows Hn (Q x R) of FF Z^{-1} Wgt from B = Z^{-H} FF^H (N x R)
 void adjoint_nodes(hipStream_t s, const Mesh& m, const c128* W, const c128* B, int64_t R, c128* Hn);

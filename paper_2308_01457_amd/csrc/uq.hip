@@ -206,6 +206,23 @@ __device__ void stage_edge(const EdgeSide& L, int e, double (*x)[3], c128* w, do
   }
 }
 
+// node coordinates and triangle normals of RWG e (no weights)
+__device__ void stage_nodes(const EdgeSide& L, int e, double (*x)[3], double (*nn)[3]) {
+  const int64_t Q = 6LL * L.nt;
+  for (int side = 0; side < 2; ++side) {
+    const int t = L.edge_tri[side * L.ne + e];
+    for (int q = 0; q < 6; ++q) {
+      const int64_t id = 6LL * t + q;
+      x[side * 6 + q][0] = L.qx[id];
+      x[side * 6 + q][1] = L.qx[Q + id];
+      x[side * 6 + q][2] = L.qx[2 * Q + id];
+    }
+    nn[side][0] = L.nrm[t];
+    nn[side][1] = L.nrm[L.nt + t];
+    nn[side][2] = L.nrm[2 * L.nt + t];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rhs_correlation(EdgeSide A, EdgeSide B, CovParams cp, c128* __restrict__ C,
                                                          int64_t ldc) {
   __shared__ double xa[16][12][3], xb[16][12][3];
@@ -243,6 +260,103 @@ __global__ __launch_bounds__(256) void k_rhs_correlation(EdgeSide A, EdgeSide B,
     ci += w.re * ai + w.im * ar;
   }
   C[(int64_t)m * ldc + n] = c128{cr, ci};
+}
+
+// Several incidences at once: the covariance between the 12 nodes of RWG m
+// and those of RWG n does not depend on the incidence, so each block of
+// kernel values is evaluated once per chunk of up to RC_DC incidences and
+// applied to all of them.  C_d (incidence dir0 + d) is written at
+// C + d * dstride with row stride ldc.
+constexpr int RC_DC = 8;
+
+__global__ __launch_bounds__(256) void k_rhs_correlation_multi(EdgeSide A, EdgeSide B, CovParams cp, int dc,
+                                                               c128* __restrict__ C, int64_t ldc, int64_t dstride) {
+  __shared__ double xa[16][12][3], xb[16][12][3];
+  __shared__ c128 wa[16][12][RC_DC], wb[16][12][RC_DC];
+  __shared__ double na[16][2][3], nb[16][2][3];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
+  if (threadIdx.x < 16) {
+    const int e = m0 + threadIdx.x;
+    if (e < A.ne) stage_nodes(A, e, xa[threadIdx.x], na[threadIdx.x]);
+  } else if (threadIdx.x < 32) {
+    const int r = threadIdx.x - 16;
+    const int e = n0 + r;
+    if (e < B.ne) stage_nodes(B, e, xb[r], nb[r]);
+  }
+  // weights of every incidence of the chunk: wa[r][q][d], wb[r][q][d] (zero past dc)
+  for (int e = threadIdx.x; e < 2 * 16 * 12 * RC_DC; e += 256) {
+    const int side = e / (16 * 12 * RC_DC);
+    const int rem = e % (16 * 12 * RC_DC);
+    const int r = rem / (12 * RC_DC), q = (rem / RC_DC) % 12, d = rem % RC_DC;
+    const EdgeSide& S = side ? B : A;
+    const int eidx = (side ? n0 : m0) + r;
+    c128 w = c128{0.0, 0.0};
+    if (eidx < S.ne && d < dc) {
+      const int t = S.edge_tri[(q / 6) * S.ne + eidx];
+      const int a = S.edge_loc[(q / 6) * S.ne + eidx];
+      w = S.W[(int64_t)d * S.nt * 18 + ((int64_t)t * 3 + a) * 6 + q % 6];  // incidences of a level: nt*18 apart
+    }
+    if (side)
+      wb[r][q][d] = w;
+    else
+      wa[r][q][d] = w;
+  }
+  __syncthreads();
+  const int m = m0 + ty, n = n0 + tx;
+  if (m >= A.ne || n >= B.ne) return;
+  double cr[RC_DC], ci[RC_DC];
+#pragma unroll
+  for (int d = 0; d < RC_DC; ++d) cr[d] = ci[d] = 0.0;
+  for (int q = 0; q < 12; ++q) {
+    const double x0 = xa[ty][q][0], x1 = xa[ty][q][1], x2 = xa[ty][q][2];
+    const double* nx = na[ty][q / 6];
+    double ar[RC_DC], ai[RC_DC];  // sum_p K(q, p) conj(W2_d[p])
+#pragma unroll
+    for (int d = 0; d < RC_DC; ++d) ar[d] = ai[d] = 0.0;
+#pragma unroll 1
+    for (int p = 0; p < 12; ++p) {
+      const double d0 = x0 - xb[tx][p][0], d1 = x1 - xb[tx][p][1], d2 = x2 - xb[tx][p][2];
+      const double* ny = nb[tx][p / 6];
+      const double kv = cov_eval(cp, d0 * d0 + d1 * d1 + d2 * d2, nx[0] * ny[0] + nx[1] * ny[1] + nx[2] * ny[2]);
+#pragma unroll
+      for (int d = 0; d < RC_DC; ++d) {
+        const c128 w = wb[tx][p][d];
+        ar[d] += kv * w.re;
+        ai[d] -= kv * w.im;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < RC_DC; ++d) {
+      const c128 w = wa[ty][q][d];
+      cr[d] += w.re * ar[d] - w.im * ai[d];
+      ci[d] += w.re * ai[d] + w.im * ar[d];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < RC_DC; ++d)
+    if (d < dc) C[d * dstride + (int64_t)m * ldc + n] = c128{cr[d], ci[d]};
+}
+
+void rhs_correlation_multi(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t dir0,
+                           int64_t nd, c128* C, int64_t ldc, int64_t dstride) {
+  const Mesh& m1 = *l1.mesh;
+  const Mesh& m2 = *l2.mesh;
+  CovParams cp;
+  cp.kind = cov.kind;
+  cp.s2 = cov.sigma * cov.sigma;
+  cp.inv2l2 = cov.ell > 0 ? 1.0 / (2.0 * cov.ell * cov.ell) : 0.0;
+  cp.s3l = cov.ell > 0 ? std::sqrt(3.0) / cov.ell : 0.0;
+  dim3 g((unsigned)((m2.h.ne + 15) / 16), (unsigned)((m1.h.ne + 15) / 16));
+  for (int64_t c0 = 0; c0 < nd; c0 += RC_DC) {
+    EdgeSide A{m1.edge_tri.as<int32_t>(), m1.edge_loc.as<int32_t>(), m1.nrm.as<double>(), l1.qx.as<double>(),
+               l1.W.as<c128>() + (dir0 + c0) * m1.h.nt * 18, (int)m1.h.ne, (int)m1.h.nt};
+    EdgeSide B{m2.edge_tri.as<int32_t>(), m2.edge_loc.as<int32_t>(), m2.nrm.as<double>(), l2.qx.as<double>(),
+               l2.W.as<c128>() + (dir0 + c0) * m2.h.nt * 18, (int)m2.h.ne, (int)m2.h.nt};
+    const int dc = (int)std::min<int64_t>(RC_DC, nd - c0);
+    hipLaunchKernelGGL(k_rhs_correlation_multi, g, dim3(256), 0, s, A, B, cp, dc, C + c0 * dstride, ldc, dstride);
+    FOSB_LAUNCH_CHECK();
+  }
 }
 
 void rhs_correlation_kernel(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t dir,
@@ -308,14 +422,16 @@ void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const doubl
   FOSB_LAUNCH_CHECK();
 }
 
-// var[r] += scale * Re sum_n P[r][n] conj(F2[r][n]); one block per row, fixed order.
-__global__ __launch_bounds__(256) void k_row_dot_re(const c128* __restrict__ P, const c128* __restrict__ F2, int64_t n,
-                                                    double scale, double* __restrict__ var) {
+// var[r] += scale * Re sum_n P[r][n] conj(F2[r][n]) (P row stride ldp); one
+// block per row, fixed order.
+__global__ __launch_bounds__(256) void k_row_dot_re(const c128* __restrict__ P, int64_t ldp,
+                                                    const c128* __restrict__ F2, int64_t n, double scale,
+                                                    double* __restrict__ var) {
   __shared__ double sm[256];
   const int64_t r = blockIdx.x;
   double acc = 0;
   for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
-    const c128 a = P[r * n + c], b = F2[r * n + c];
+    const c128 a = P[r * ldp + c], b = F2[r * n + c];
     acc += a.re * b.re + a.im * b.im;
   }
   sm[threadIdx.x] = acc;
@@ -327,9 +443,9 @@ __global__ __launch_bounds__(256) void k_row_dot_re(const c128* __restrict__ P, 
   if (threadIdx.x == 0) var[r] += scale * sm[0];
 }
 
-void row_dot_re_accumulate(hipStream_t s, const c128* P, const c128* FF2, int64_t rows, int64_t n, double scale,
-                           double* var) {
-  hipLaunchKernelGGL(k_row_dot_re, dim3((unsigned)rows), dim3(256), 0, s, P, FF2, n, scale, var);
+void row_dot_re_accumulate(hipStream_t s, const c128* P, int64_t ldp, const c128* FF2, int64_t rows, int64_t n,
+                           double scale, double* var) {
+  hipLaunchKernelGGL(k_row_dot_re, dim3((unsigned)rows), dim3(256), 0, s, P, ldp, FF2, n, scale, var);
   FOSB_LAUNCH_CHECK();
 }
 

@@ -440,7 +440,8 @@ def second_moment(ctx: Context, meshes: list[Mesh], L0: int, L: int, k: float, p
                   stats: Stats | None = None):
     """fosb_second_moment: the whole hot path over the ladder meshes (levels
     L0..L, coarse to fine) with the library's two-stream schedule.  Returns
-    (var (3, n_a), blocks, levels or None)."""
+    (var (3, n_a), blocks, levels or None); dir = -1 solves every incidence
+    together (blocks N1 x n_dirs*N2, var (n_dirs, 3, n_a))."""
     import torch
     n = len(meshes)
     dev = ctx.torch_device
@@ -449,13 +450,14 @@ def second_moment(ctx: Context, meshes: list[Mesh], L0: int, L: int, k: float, p
     if precision == MIXED and Zlow is None:
         Zlow = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex64, device=dev) for m in meshes]
     pairs = ct_pairs(L0, L)
-    if blocks is None:
-        blocks = [torch.empty((meshes[a - L0].n_edges, meshes[b - L0].n_edges), dtype=torch.complex128, device=dev)
-                  for a, b, _, _ in pairs]
     x = _host_f64(xhat).reshape(-1, 3)
     d = _host_f64(dirs).reshape(-1, 3)
     p = _host_f64(pols).reshape(-1, 3)
-    var = torch.empty(3 * x.shape[0], dtype=torch.float64, device=dev)
+    nd = d.shape[0] if dir < 0 else 1
+    if blocks is None:
+        blocks = [torch.empty((meshes[a - L0].n_edges, nd * meshes[b - L0].n_edges), dtype=torch.complex128,
+                              device=dev) for a, b, _, _ in pairs]
+    var = torch.empty(nd * 3 * x.shape[0], dtype=torch.float64, device=dev)
     st = stats if stats is not None else Stats()
     ms = (_P * n)(*[m.h for m in meshes])
     zp = (_P * n)(*[_dev(z, torch.complex128) for z in Z])
@@ -477,7 +479,7 @@ def second_moment(ctx: Context, meshes: list[Mesh], L0: int, L: int, k: float, p
     if keep_levels:
         levels = [Level._adopt(ctx, meshes[i], k, _P(out[i]), precision, Z[i],
                                Zlow[i] if precision == MIXED else None, d.shape[0]) for i in range(n)]
-    return var.view(3, -1), blocks, levels
+    return (var.view(3, -1) if dir >= 0 else var.view(nd, 3, -1)), blocks, levels
 
 
 @dataclass
