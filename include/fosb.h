@@ -269,7 +269,8 @@ typedef enum fosb_kernel_class {
   FOSB_K_TRSM_LEAF = 4,     /* diagonal-block inverse applications                      */
   FOSB_K_RHS = 5,           /* RHS correlation, weights, far-field kernels              */
   FOSB_K_GEMV = 6,          /* matrix times at most four columns (bandwidth-bound)      */
-  FOSB_K_COUNT = 7
+  FOSB_K_SPLITK_SUM = 7,    /* sum of the partial products of a split-K GEMM            */
+  FOSB_K_COUNT = 8
 } fosb_kernel_class;
 
 /* on != 0: from now on every launch of an instrumented kernel on this context

@@ -99,6 +99,7 @@ struct Context {
   // Sauter-Schwab point tables per Gauss order n (1..12): 5 doubles per point,
   // kinds 0/1/2 concatenated; offsets and counts in points.
   DevBuf norms;       // 2 doubles for refinement norms
+  DevBuf splitk;      // partial products of split-K GEMMs
   DevBuf ss[13];
   int ss_off[13][3] = {};
   int ss_cnt[13][3] = {};

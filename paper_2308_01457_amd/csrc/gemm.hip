@@ -49,10 +49,14 @@ constexpr int PADA = 4, PADB = 4;
 template <typename T> struct Slice { static constexpr int BK = 16; };
 template <> struct Slice<double> { static constexpr int BK = 8; };
 
+// Split K: workgroup z of gridDim.z covers K range [z*kc, min(K, (z+1)*kc)); with
+// gridDim.z > 1 it writes its raw partial product to P + z*M*N (row stride N)
+// and k_gemm_splitk_sum forms C = beta*C + alpha*sum_z P_z in fixed z order.
 template <typename T, bool CONJ_A>
 __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, const cplx<T>* __restrict__ A,
                                               int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb, T beta,
-                                              cplx<T>* __restrict__ C, int64_t ldc) {
+                                              cplx<T>* __restrict__ C, int64_t ldc, int64_t kc,
+                                              cplx<T>* __restrict__ P) {
   using V4 = typename Mfma<T>::v4;
   constexpr int BK = Slice<T>::BK;
   constexpr int AE = BM * BK / 256;  // A elements staged per thread
@@ -95,6 +99,8 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   const int b_k = tid / (BN / BE);
   const int b_col = (tid % (BN / BE)) * BE;
 
+  const int64_t kb = (int64_t)blockIdx.z * kc;
+  const int64_t ke = min(K, kb + kc);
   cplx<T> ra[AE], rb[BE];
   auto load_tiles = [&](int64_t k0) {
     const int64_t gr = m0 + a_row;
@@ -102,17 +108,17 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
     for (int e = 0; e < AE; ++e) {
       const int64_t gk = k0 + a_k + e;
       if (CONJ_A) {
-        const cplx<T> v = (gr < M && gk < K) ? A[gk * lda + gr] : cplx<T>{T(0), T(0)};
+        const cplx<T> v = (gr < M && gk < ke) ? A[gk * lda + gr] : cplx<T>{T(0), T(0)};
         ra[e] = cplx<T>{v.re, -v.im};
       } else {
-        ra[e] = (gr < M && gk < K) ? A[gr * lda + gk] : cplx<T>{T(0), T(0)};
+        ra[e] = (gr < M && gk < ke) ? A[gr * lda + gk] : cplx<T>{T(0), T(0)};
       }
     }
     const int64_t gk = k0 + b_k;
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
       const int64_t gc = n0 + b_col + e;
-      rb[e] = (gk < K && gc < N) ? B[gk * ldb + gc] : cplx<T>{T(0), T(0)};
+      rb[e] = (gk < ke && gc < N) ? B[gk * ldb + gc] : cplx<T>{T(0), T(0)};
     }
   };
   auto store_tiles = [&](int buf) {
@@ -167,13 +173,13 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
     }
   };
 
-  if (K > 0) {
-    load_tiles(0);
+  if (ke > kb) {
+    load_tiles(kb);
     store_tiles(0);
     __syncthreads();
     int buf = 0;
-    for (int64_t k0 = 0; k0 < K; k0 += BK) {
-      const bool more = k0 + BK < K;
+    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+      const bool more = k0 + BK < ke;
       if (more) load_tiles(k0 + BK);  // next slice in flight during the MFMAs
       compute(buf);
       if (more) store_tiles(buf ^ 1);  // the other buffer was last read before the previous barrier
@@ -194,6 +200,10 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
         if (row < M && col < N) {
           const T cr = t1[i][j][v] - t2[i][j][v];
           const T ci = t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
+          if (gridDim.z > 1) {
+            P[(int64_t)blockIdx.z * M * N + row * N + col] = cplx<T>{cr, ci};
+            continue;
+          }
           cplx<T>* p = C + row * ldc + col;
           if (beta == T(0)) {
             *p = cplx<T>{alpha * cr, alpha * ci};
@@ -203,6 +213,28 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
           }
         }
       }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_splitk_sum(int64_t M, int64_t N, int nz, T alpha,
+                                                         const cplx<T>* __restrict__ P, T beta,
+                                                         cplx<T>* __restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t row = idx / N, col = idx % N;
+  T sr = 0, si = 0;
+  for (int z = 0; z < nz; ++z) {
+    const cplx<T> v = P[(int64_t)z * M * N + idx];
+    sr += v.re;
+    si += v.im;
+  }
+  cplx<T>* p = C + row * ldc + col;
+  if (beta == T(0)) {
+    *p = cplx<T>{alpha * sr, alpha * si};
+  } else {
+    const cplx<T> o = *p;
+    *p = cplx<T>{beta * o.re + alpha * sr, beta * o.im + alpha * si};
+  }
 }
 
 // Narrow right-hand sides (N <= 4, e.g. one incidence): a bandwidth-bound
@@ -294,11 +326,35 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
       default: return gemv_launch<T, 4>(ctx, M, K, alpha, A, lda, B, ldb, beta, C, ldc);
     }
   }
-  ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);
-  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
-  hipLaunchKernelGGL((k_gemm<T, CONJ_A>), grid, dim3(256), 0, ctx.stream, M, N, std::max<int64_t>(K, 0), (T)alpha, A,
-                     lda, B, ldb, (T)beta, C, ldc);
-  FOSB_LAUNCH_CHECK();
+  const int64_t Kp = std::max<int64_t>(K, 0);
+  const int64_t tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+  // split K when the output has too few tiles to fill the chip and K is long:
+  // about two workgroups per CU, each still streaming at least 256 of K
+  int64_t nz = 1;
+  const int64_t want = 2LL * ctx.n_cu;
+  if (tiles < want && Kp >= 512) nz = std::min<int64_t>({(want + tiles - 1) / tiles, Kp / 256, 64});
+  int64_t kc = Kp;
+  cplx<T>* P = nullptr;
+  if (nz > 1) {
+    kc = ((Kp + nz - 1) / nz + Slice<T>::BK - 1) / Slice<T>::BK * Slice<T>::BK;
+    nz = (Kp + kc - 1) / kc;
+    ctx.splitk.reserve((size_t)nz * M * N * sizeof(cplx<T>));
+    P = static_cast<cplx<T>*>(ctx.splitk.p);
+  }
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)nz);
+  {
+    ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);
+    hipLaunchKernelGGL((k_gemm<T, CONJ_A>), grid, dim3(256), 0, ctx.stream, M, N, Kp, (T)alpha, A, lda, B, ldb,
+                       (T)beta, C, ldc, kc, P);
+    FOSB_LAUNCH_CHECK();
+  }
+  if (nz > 1) {
+    ProfScope prof(ctx, FOSB_K_SPLITK_SUM, 2.0 * (double)nz * M * N,
+                   (double)sizeof(cplx<T>) * ((double)nz + 2.0) * M * N);
+    hipLaunchKernelGGL((k_gemm_splitk_sum<T>), dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, ctx.stream, M, N,
+                       (int)nz, (T)alpha, P, (T)beta, C, ldc);
+    FOSB_LAUNCH_CHECK();
+  }
 }
 
 template <typename T>

@@ -87,7 +87,7 @@ _SIGS = {
     "fosb_profile_read": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
 }
 
-KERNEL_CLASSES = {"gemm_f64": 0, "gemm_f32": 1, "assemble": 2, "panel": 3, "trsm_leaf": 4, "rhs": 5, "gemv": 6}
+KERNEL_CLASSES = {"gemm_f64": 0, "gemm_f32": 1, "assemble": 2, "panel": 3, "trsm_leaf": 4, "rhs": 5, "gemv": 6, "splitk_sum": 7}
 
 _lib = None
 
