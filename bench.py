@@ -79,6 +79,8 @@ def parse():
                     help="mixed_k5: the k=5 icosphere ladder (default); ellipsoids: 64 seeded ellipsoids x 16 "
                          "incidences, 3 levels each, Matern-3/2 covariance, all incidences solved together")
     ap.add_argument("--shapes", type=int, default=64, help="ellipsoids: number of shapes")
+    ap.add_argument("--workers", type=int, default=4,
+                    help="ellipsoids: shapes in flight at once (fosb_second_moment_batch); 0 = one call per shape")
     ap.add_argument("--schedule", default="concurrent", choices=["concurrent", "sequential"],
                     help="concurrent: the library's two-stream pipeline (fosb_second_moment); sequential: the "
                          "step-by-step calls, timed per stage")
@@ -245,26 +247,31 @@ def run_batched(args):
     xh = workloads.angles_xz(181)
     meshes = [[fosb.Mesh(ctx, V, F) for V, F in w.meshes] for w in shapes]
     N = [[m.n_edges for m in ms] for ms in meshes]
-    nmax = [max(n[i] for n in N) for i in range(3)]
-    Zb = [torch.empty(nmax[i] ** 2, dtype=torch.complex128, device=dev) for i in range(3)]
-    Zl = [torch.empty(nmax[i] ** 2, dtype=torch.complex64, device=dev) for i in range(3)]
     pairs = fosb.ct_pairs(0, 2)
-    Bb = [torch.empty(nmax[a] * 16 * nmax[b], dtype=torch.complex128, device=dev) for a, b, _, _ in pairs]
     opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
     npairs = len(pairs) * 16 * len(shapes)
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     out = {}
+    items = [{"meshes": ms, "L0": 0, "L": 2, "k": w.k, "dirs": w.dirs, "pols": w.pols,
+              "cov": fosb.make_cov("matern32", w.sigma, w.ell)} for w, ms in zip(shapes, meshes)]
+    if args.workers == 0:
+        nmax = [max(n[i] for n in N) for i in range(3)]
+        Zb = [torch.empty(nmax[i] ** 2, dtype=torch.complex128, device=dev) for i in range(3)]
+        Zl = [torch.empty(nmax[i] ** 2, dtype=torch.complex64, device=dev) for i in range(3)]
+        Bb = [torch.empty(nmax[a] * 16 * nmax[b], dtype=torch.complex128, device=dev) for a, b, _, _ in pairs]
 
     def step(prec):
-        res = []
         st = fosb.Stats()
-        for w, ms, n in zip(shapes, meshes, N):
+        if args.workers > 0:
+            return fosb.second_moment_batch(ctx, items, prec, xh, opts, args.workers, st), st
+        res = []
+        for it, n in zip(items, N):
             Z = [Zb[i][: n[i] ** 2].view(n[i], n[i]) for i in range(3)]
             Zlo = [Zl[i][: n[i] ** 2].view(n[i], n[i]) for i in range(3)] if prec == fosb.MIXED else None
             blocks = [Bb[p][: n[a] * 16 * n[b]].view(n[a], 16 * n[b]) for p, (a, b, _, _) in enumerate(pairs)]
-            cov = fosb.make_cov("matern32", w.sigma, w.ell)
-            var, _, _ = fosb.second_moment(ctx, ms, 0, 2, w.k, prec, cov, xh, w.dirs, w.pols, "radial", -1, Z=Z,
-                                           Zlow=Zlo, blocks=blocks, opts=opts, stats=st)
+            var, _, _ = fosb.second_moment(ctx, it["meshes"], 0, 2, it["k"], prec, it["cov"], xh, it["dirs"],
+                                           it["pols"], "radial", -1, Z=Z, Zlow=Zlo, blocks=blocks, opts=opts,
+                                           stats=st)
             res.append(var)
         return res, st
 
@@ -293,7 +300,8 @@ def run_batched(args):
             "config": {"workload": f"batched ellipsoids: {len(shapes)} shapes x 16 incidences, geodesic levels "
                                    f"nu/4, nu/2, nu (top 1280..5120 triangles), k ~ U[1,4], Matern-3/2 (0.01, "
                                    f"U[0.3,0.8]), L0=0 L=2 (3 pairs), 181 angles, incidences stacked",
-                       "precision": head, "ir_tol": args.ir_tol, "level_pair_solves": npairs}}
+                       "precision": head, "ir_tol": args.ir_tol, "level_pair_solves": npairs,
+                       "shapes_in_flight": args.workers}}
     for pname, rec in out.items():
         line[pname] = {k: v for k, v in rec.items() if k != "var"}
     if "mixed" in out and "fp64" in out:

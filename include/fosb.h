@@ -259,6 +259,34 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
                                void* const* blocks, const int64_t* ldb, double* var,
                                const fosb_opts* opts, fosb_level** levels_out, fosb_stats* stats);
 
+/* One shape of a batch: its level ladder (meshes[i] = level L0 + i, coarse to
+ * fine, created on the batch's context), wavenumber, incidences (host, n_dirs
+ * x 3 each), perturbation field, covariance and output: var (device, n_dirs
+ * consecutive 3 n_a float64 vectors, as fosb_far_field_moments). */
+typedef struct fosb_batch_shape {
+  const fosb_mesh* const* meshes;
+  int32_t n_levels, L0, L, field;
+  double k;
+  const double* dirs;
+  const double* pols;
+  int64_t n_dirs;
+  fosb_cov cov;
+  double* var;
+} fosb_batch_shape;
+
+/* The whole pass (as fosb_second_moment with every incidence stacked) for
+ * many shapes of uneven sizes: n_workers host threads (1..16), each with its
+ * own stream (created by the library, default priority), scratch and
+ * grow-only Z / Zlow / block workspaces held by the context, take shapes in
+ * order from a shared queue, so several shapes are in flight on the GPU at
+ * once.  Per shape the results equal fosb_second_moment(dir = -1).  The
+ * workspaces persist in the context (each worker holds its largest shape's
+ * matrices).  Errors as for fosb_second_moment; on error the remaining shapes
+ * are skipped and their var is unspecified. */
+fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* shapes, int64_t n_shapes,
+                                     int32_t precision, const double* xhat, int64_t n_a,
+                                     const fosb_opts* opts, int32_t n_workers, fosb_stats* stats);
+
 /* ---------------------------------------------------------------- profiling */
 /* Kernel classes timed by the profiler. */
 typedef enum fosb_kernel_class {

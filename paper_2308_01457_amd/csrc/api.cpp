@@ -5,6 +5,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
+#include <atomic>
 #include <exception>
 #include <map>
 #include <thread>
@@ -194,21 +195,12 @@ struct fosb_level : fosb::Level {};
 
 namespace fosb {
 
-static void check_level_args(const fosb_mesh* mesh, double k, int32_t precision, void* Z, int64_t ldz, void* Zlow,
-                             int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs, int32_t field) {
+static void check_physics(double k, int32_t precision, const double* dirs, const double* pols, int64_t n_dirs,
+                          int32_t field) {
   REQUIRE(std::isfinite(k) && k > 0, "wavenumber must be positive and finite");
   REQUIRE(precision == FOSB_PREC_FP64 || precision == FOSB_PREC_MIXED, "unknown precision %d", precision);
   REQUIRE(field == FOSB_FIELD_RADIAL || field == FOSB_FIELD_NORMAL, "unknown field %d", field);
-  REQUIRE(Z, "Z is NULL");
   REQUIRE(dirs && pols && n_dirs >= 1 && n_dirs <= 4096, "need 1..4096 incidence directions");
-  const int64_t n = mesh->h.ne;
-  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz < N");
-  if (precision == FOSB_PREC_MIXED) {
-    REQUIRE(Zlow, "MIXED precision needs the complex64 buffer Zlow");
-    if (ldzlow < n) fail(FOSB_E_WORKSPACE, "ldzlow < N");
-  } else {
-    REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
-  }
   for (int64_t d = 0; d < n_dirs; ++d) {
     double nd = 0, np = 0;
     for (int c = 0; c < 3; ++c) {
@@ -218,6 +210,20 @@ static void check_level_args(const fosb_mesh* mesh, double k, int32_t precision,
     }
     REQUIRE(std::fabs(nd - 1.0) < 1e-9, "direction %lld is not a unit vector", (long long)d);
     REQUIRE(np > 0, "polarisation %lld is zero", (long long)d);
+  }
+}
+
+static void check_level_args(const fosb_mesh* mesh, double k, int32_t precision, void* Z, int64_t ldz, void* Zlow,
+                             int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs, int32_t field) {
+  check_physics(k, precision, dirs, pols, n_dirs, field);
+  REQUIRE(Z, "Z is NULL");
+  const int64_t n = mesh->h.ne;
+  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz < N");
+  if (precision == FOSB_PREC_MIXED) {
+    REQUIRE(Zlow, "MIXED precision needs the complex64 buffer Zlow");
+    if (ldzlow < n) fail(FOSB_E_WORKSPACE, "ldzlow < N");
+  } else {
+    REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
   }
 }
 
@@ -359,6 +365,54 @@ static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t 
     }
   }
   FOSB_HIP(hipStreamSynchronize(s));
+}
+
+
+// The whole pass for one ladder on c's stream alone, every incidence stacked,
+// Z / Zlow / blocks from c's grow-only workspaces; var receives n_dirs
+// consecutive 3 n_a vectors.  Used by the batch workers.
+static void shape_pipeline(Context& c, const fosb_mesh* const* meshes, int32_t n_levels, int32_t L0, int32_t L,
+                           double k, int32_t precision, const double* dirs, const double* pols, int64_t n_dirs,
+                           int32_t field, const fosb_cov& cov, const double* xhat, int64_t n_a, double* var,
+                           const fosb_opts& o, fosb_stats* st) {
+  const bool mixed = precision == FOSB_PREC_MIXED;
+  auto v = ct_pairs_vec(L0, L);
+  if (c.ws_Z.size() < (size_t)n_levels) c.ws_Z.resize(n_levels);
+  if (c.ws_Zlow.size() < (size_t)n_levels) c.ws_Zlow.resize(n_levels);
+  if (c.ws_blocks.size() < v.size()) c.ws_blocks.resize(v.size());
+  std::vector<std::unique_ptr<fosb_level>> lv(n_levels);
+  for (int32_t i = 0; i < n_levels; ++i) {
+    const int64_t n = meshes[i]->h.ne;
+    c.ws_Z[i].reserve((size_t)n * n * sizeof(c128));
+    if (mixed) c.ws_Zlow[i].reserve((size_t)n * n * sizeof(c64));
+    {
+      ProfScope prof(c, FOSB_K_ASSEMBLE, 0.0, 16.0 * (double)n * (double)n);
+      assemble_efie(c, *meshes[i], k, o.n_gauss_singular, c.ws_Z[i].as<c128>(), n);
+    }
+    lv[i] = level_build(c, meshes[i], k, precision, c.ws_Z[i].p, n, mixed ? c.ws_Zlow[i].p : nullptr,
+                        mixed ? n : 0, dirs, pols, n_dirs, field, o);
+  }
+  std::vector<void*> bp(v.size());
+  std::vector<int64_t> ldb(v.size());
+  for (size_t p = 0; p < v.size(); ++p) {
+    const fosb_level& a = *lv[v[p][0] - L0];
+    const fosb_level& b = *lv[v[p][1] - L0];
+    ldb[p] = n_dirs * b.n;
+    c.ws_blocks[p].reserve((size_t)a.n * ldb[p] * sizeof(c128));
+    bp[p] = c.ws_blocks[p].p;
+    c128* C = c.ws_blocks[p].as<c128>();
+    {
+      ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)n_dirs * (double)a.n * (double)b.n);
+      if (n_dirs == 1)
+        rhs_correlation_kernel(c.stream, a, b, cov, 0, C, ldb[p]);
+      else
+        rhs_correlation_multi(c.stream, a, b, cov, 0, n_dirs, C, ldb[p], b.n);
+    }
+    two_sided(c, a, b, C, ldb[p], st, n_dirs);
+  }
+  std::vector<const fosb_level*> lp(n_levels);
+  for (int32_t i = 0; i < n_levels; ++i) lp[i] = lv[i].get();
+  far_field_impl(c, lp.data(), L0, L, bp.data(), ldb.data(), xhat, n_a, 0, n_dirs, var, nullptr);
 }
 
 }  // namespace fosb
@@ -826,12 +880,79 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   API_END
 }
 
+fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* shapes, int64_t n_shapes,
+                                     int32_t precision, const double* xhat, int64_t n_a, const fosb_opts* opts,
+                                     int32_t n_workers, fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && shapes && xhat, "NULL argument");
+  REQUIRE(n_shapes >= 1, "n_shapes must be >= 1");
+  REQUIRE(n_workers >= 1 && n_workers <= 16, "n_workers must be 1..16");
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  for (int64_t i = 0; i < n_a; ++i) {
+    double nn = xhat[3 * i] * xhat[3 * i] + xhat[3 * i + 1] * xhat[3 * i + 1] + xhat[3 * i + 2] * xhat[3 * i + 2];
+    REQUIRE(std::fabs(nn - 1.0) < 1e-9, "xhat[%lld] is not a unit vector", (long long)i);
+  }
+  for (int64_t s = 0; s < n_shapes; ++s) {
+    const fosb_batch_shape& b = shapes[s];
+    REQUIRE(b.meshes && b.var, "shape %lld: meshes/var is NULL", (long long)s);
+    REQUIRE(b.L0 >= 0 && b.L >= b.L0 && b.n_levels == b.L - b.L0 + 1, "shape %lld: n_levels must be L - L0 + 1",
+            (long long)s);
+    for (int32_t i = 0; i < b.n_levels; ++i) {
+      REQUIRE(b.meshes[i] && b.meshes[i]->ctx == ctx, "shape %lld: mesh %d is NULL or foreign", (long long)s, i);
+      if (i > 0) REQUIRE(b.meshes[i]->h.ne > b.meshes[i - 1]->h.ne, "shape %lld: levels must go coarse to fine",
+                         (long long)s);
+    }
+    check_physics(b.k, precision, b.dirs, b.pols, b.n_dirs, b.field);
+    check_cov(&b.cov);
+  }
+  const fosb_opts o = opts_or_default(opts);
+  bind(*ctx);
+  const int nw = (int)std::min<int64_t>(n_workers, n_shapes);
+  for (int w = 0; w < nw; ++w) ctx->worker_context(w);
+  std::atomic<int64_t> next(0);
+  std::atomic<bool> stop(false);
+  std::vector<std::exception_ptr> err(nw);
+  std::vector<fosb_stats> st(nw);
+  for (auto& x : st) x = fosb_stats{};
+  std::vector<std::thread> pool;
+  for (int w = 0; w < nw; ++w)
+    pool.emplace_back([&, w] {
+      Context& c = *ctx->workers[w];
+      try {
+        FOSB_HIP(hipSetDevice(ctx->device));
+        for (;;) {
+          if (stop.load()) break;
+          const int64_t s = next.fetch_add(1);
+          if (s >= n_shapes) break;
+          const fosb_batch_shape& b = shapes[s];
+          shape_pipeline(c, b.meshes, b.n_levels, b.L0, b.L, b.k, precision, b.dirs, b.pols, b.n_dirs, b.field,
+                         b.cov, xhat, n_a, b.var, o, &st[w]);
+        }
+        FOSB_HIP(hipStreamSynchronize(c.stream));
+      } catch (...) {
+        err[w] = std::current_exception();
+        stop.store(true);
+      }
+    });
+  for (auto& t : pool) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  if (stats)
+    for (const fosb_stats& x : st) {
+      stats->ir_sweeps = std::max(stats->ir_sweeps, x.ir_sweeps);
+      stats->n_solves += x.n_solves;
+      stats->ir_rel_correction = std::max(stats->ir_rel_correction, x.ir_rel_correction);
+    }
+  API_END
+}
+
 fosb_status fosb_profile_enable(fosb_context* ctx, int32_t on) {
   API_BEGIN
   REQUIRE(ctx, "ctx is NULL");
   bind(*ctx);
   FOSB_HIP(hipStreamSynchronize(ctx->stream));
   if (ctx->aux) FOSB_HIP(hipStreamSynchronize(ctx->aux->stream));
+  for (auto& w : ctx->workers) FOSB_HIP(hipStreamSynchronize(w->stream));
   {
     std::lock_guard<std::mutex> lock(ctx->prof_mu);
     if (on) ctx->recs.clear();
@@ -848,6 +969,7 @@ fosb_status fosb_profile_read(fosb_context* ctx, int32_t cls, int64_t* launches,
   bind(*ctx);
   FOSB_HIP(hipStreamSynchronize(ctx->stream));
   if (ctx->aux) FOSB_HIP(hipStreamSynchronize(ctx->aux->stream));
+  for (auto& w : ctx->workers) FOSB_HIP(hipStreamSynchronize(w->stream));
   std::lock_guard<std::mutex> lock(ctx->prof_mu);
   int64_t cnt = 0;
   double sec = 0, fl = 0, by = 0;

@@ -116,6 +116,10 @@ struct Context {
   bool owns_stream = false;
   std::unique_ptr<Context> aux;
   Context& aux_context();
+  // batch workers: own streams, scratch and per-shape workspaces (Z, Zlow, blocks)
+  std::vector<std::unique_ptr<Context>> workers;
+  std::vector<DevBuf> ws_Z, ws_Zlow, ws_blocks;
+  Context& worker_context(size_t i);
   ~Context();
 };
 

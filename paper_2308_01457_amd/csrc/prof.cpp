@@ -25,22 +25,30 @@ ProfScope::~ProfScope() {
   (void)hipEventRecord(ctx.ev_pool[idx + 1], stream);
 }
 
+static std::unique_ptr<Context> child_context(Context& parent) {
+  std::unique_ptr<Context> a(new Context());
+  a->device = parent.device;
+  a->n_cu = parent.n_cu;
+  a->max_lds = parent.max_lds;
+  a->prof_root = &parent;
+  FOSB_HIP(hipSetDevice(parent.device));
+  FOSB_HIP(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));  // default priority
+  a->owns_stream = true;
+  return a;
+}
+
 Context& Context::aux_context() {
-  if (!aux) {
-    std::unique_ptr<Context> a(new Context());
-    a->device = device;
-    a->n_cu = n_cu;
-    a->max_lds = max_lds;
-    a->prof_root = this;
-    FOSB_HIP(hipSetDevice(device));
-    FOSB_HIP(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));
-    a->owns_stream = true;
-    aux = std::move(a);
-  }
+  if (!aux) aux = child_context(*this);
   return *aux;
 }
 
+Context& Context::worker_context(size_t i) {
+  while (workers.size() <= i) workers.push_back(child_context(*this));
+  return *workers[i];
+}
+
 Context::~Context() {
+  workers.clear();
   if (aux) aux.reset();
   if (owns_stream && stream) {
     (void)hipStreamSynchronize(stream);

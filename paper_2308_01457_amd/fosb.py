@@ -46,6 +46,12 @@ class Stats(C.Structure):
     _fields_ = [("ir_sweeps", C.c_int32), ("n_solves", C.c_int32), ("ir_rel_correction", C.c_double)]
 
 
+class BatchShape(C.Structure):
+    _fields_ = [("meshes", C.POINTER(C.c_void_p)), ("n_levels", C.c_int32), ("L0", C.c_int32), ("L", C.c_int32),
+                ("field", C.c_int32), ("k", C.c_double), ("dirs", C.c_void_p), ("pols", C.c_void_p),
+                ("n_dirs", C.c_int64), ("cov", Cov), ("var", C.c_void_p)]
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _I32 = C.c_int32
@@ -83,6 +89,8 @@ _SIGS = {
                                      C.POINTER(_P), C.POINTER(_I64), _P, _P, _I64, _I32, C.POINTER(Cov), _I64, _P,
                                      _I64, C.POINTER(_P), C.POINTER(_I64), _P, C.POINTER(Opts), C.POINTER(_P),
                                      C.POINTER(Stats)]),
+    "fosb_second_moment_batch": (C.c_int, [_P, C.POINTER(BatchShape), _I64, _I32, _P, _I64, C.POINTER(Opts), _I32,
+                                           C.POINTER(Stats)]),
     "fosb_profile_enable": (C.c_int, [_P, _I32]),
     "fosb_profile_read": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
 }
@@ -480,6 +488,39 @@ def second_moment(ctx: Context, meshes: list[Mesh], L0: int, L: int, k: float, p
         levels = [Level._adopt(ctx, meshes[i], k, _P(out[i]), precision, Z[i],
                                Zlow[i] if precision == MIXED else None, d.shape[0]) for i in range(n)]
     return (var.view(3, -1) if dir >= 0 else var.view(nd, 3, -1)), blocks, levels
+
+
+def second_moment_batch(ctx: Context, shapes, precision: int, xhat, opts: Opts | None = None, n_workers: int = 4,
+                        stats: Stats | None = None):
+    """fosb_second_moment_batch.  shapes: list of dicts with keys meshes (list of
+    Mesh, coarse to fine), L0, L, k, dirs, pols, cov (Cov) and optionally field.
+    Returns one device tensor (n_dirs, 3, n_a) per shape."""
+    import torch
+    x = _host_f64(xhat).reshape(-1, 3)
+    arr = (BatchShape * len(shapes))()
+    keep = []
+    outs = []
+    for i, sh in enumerate(shapes):
+        d = _host_f64(sh["dirs"]).reshape(-1, 3)
+        p = _host_f64(sh["pols"]).reshape(-1, 3)
+        ms = (_P * len(sh["meshes"]))(*[m.h for m in sh["meshes"]])
+        var = torch.empty((d.shape[0], 3, x.shape[0]), dtype=torch.float64, device=ctx.torch_device)
+        fld = sh.get("field", "radial")
+        b = arr[i]
+        b.meshes = C.cast(ms, C.POINTER(C.c_void_p))
+        b.n_levels, b.L0, b.L = len(sh["meshes"]), sh["L0"], sh["L"]
+        b.field = FIELDS[fld] if isinstance(fld, str) else int(fld)
+        b.k = float(sh["k"])
+        b.dirs, b.pols, b.n_dirs = d.ctypes.data_as(_P), p.ctypes.data_as(_P), d.shape[0]
+        b.cov = sh["cov"]
+        b.var = _dev(var, torch.float64)
+        keep += [d, p, ms]
+        outs.append(var)
+    st = stats if stats is not None else Stats()
+    _check(lib().fosb_second_moment_batch(ctx.h, arr, len(shapes), precision, x.ctypes.data_as(_P), x.shape[0],
+                                          C.byref(opts) if opts else None, n_workers, C.byref(st)))
+    del keep
+    return outs
 
 
 @dataclass

@@ -130,3 +130,26 @@ def test_stacked_incidences_ellipsoid_vs_oracle(fz):
         e = float(np.linalg.norm(vm[d].cpu().numpy() - v1.cpu().numpy()) / np.linalg.norm(v1.cpu().numpy()))
         print(f"[gpu]   mixed stacked vs single incidence {d}: {e:.2e}", flush=True)
         assert e < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_equals_per_shape(fz, precision):
+    """fosb_second_moment_batch over three ellipsoid ladders of uneven sizes
+    (two workers) equals fosb_second_moment(dir = -1) shape by shape."""
+    fosb, ctx, torch = fz
+    prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
+    xh = workloads.angles_xz(31)
+    shapes = workloads.batched_ellipsoids(n_shapes=3, n_dirs=2, seed=11)
+    items = []
+    for w, nus in zip(shapes, ((1, 2, 4), (2, 4, 6), (1, 3, 5))):
+        ms = [fosb.Mesh(ctx, *workloads.ellipsoid(nu, tuple(w.extra["axes"]))) for nu in nus]
+        items.append({"meshes": ms, "L0": 0, "L": 2, "k": w.k, "dirs": w.dirs, "pols": w.pols,
+                      "cov": fosb.make_cov("matern32", w.sigma, w.ell)})
+    print(f"[gpu] batch of 3 shapes, 2 workers, {precision}", flush=True)
+    st = fosb.Stats()
+    out = fosb.second_moment_batch(ctx, items, prec, xh, n_workers=2, stats=st)
+    assert st.n_solves == 3 * 3 * 2
+    for it, v in zip(items, out):
+        ref, _, _ = fosb.second_moment(ctx, it["meshes"], 0, 2, it["k"], prec, it["cov"], xh, it["dirs"],
+                                       it["pols"], dir=-1)
+        assert np.array_equal(v.cpu().numpy(), ref.cpu().numpy())
