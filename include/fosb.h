@@ -287,6 +287,18 @@ fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* 
                                      int32_t precision, const double* xhat, int64_t n_a,
                                      const fosb_opts* opts, int32_t n_workers, fosb_stats* stats);
 
+/* ---------------------------------------------------------------- GEMM tile autotuner */
+/* The complex GEMMs run one of several tile shapes (64x64, 64x32, 64x128,
+ * 128x64 for complex64; 64x32, 64x64, 128x64 for complex128).  With tuning on
+ * (the default) the first product of each size bucket (precision, operand
+ * form, floor(log2) of M, N, K) times every shape on its real operands into
+ * scratch output and keeps the fastest for the bucket; the table belongs to
+ * the context and its auxiliary and worker streams.  All shapes give
+ * identical results, so tuning never changes outputs.  mode: 0 off (built-in
+ * shape: the first listed), 1 on, 2 on and forget the table, -1 query only.
+ * n_entries (may be NULL) receives the number of tuned buckets. */
+fosb_status fosb_autotune(fosb_context* ctx, int32_t mode, int32_t* n_entries);
+
 /* ---------------------------------------------------------------- profiling */
 /* Kernel classes timed by the profiler. */
 typedef enum fosb_kernel_class {

@@ -946,6 +946,18 @@ fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* 
   API_END
 }
 
+fosb_status fosb_autotune(fosb_context* ctx, int32_t mode, int32_t* n_entries) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  REQUIRE(mode >= -1 && mode <= 2, "mode must be -1, 0, 1 or 2");
+  std::lock_guard<std::mutex> lock(ctx->tune_mu);
+  if (mode == 2) ctx->tune.clear();
+  if (mode == 0) ctx->autotune = 0;
+  if (mode >= 1) ctx->autotune = 1;
+  if (n_entries) *n_entries = (int32_t)ctx->tune.size();
+  API_END
+}
+
 fosb_status fosb_profile_enable(fosb_context* ctx, int32_t on) {
   API_BEGIN
   REQUIRE(ctx, "ctx is NULL");

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -100,6 +101,12 @@ struct Context {
   // kinds 0/1/2 concatenated; offsets and counts in points.
   DevBuf norms;       // 2 doubles for refinement norms
   DevBuf splitk;      // partial products of split-K GEMMs
+  DevBuf tune_out;    // scratch output of autotuning runs
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
+  // GEMM tile autotuner (kept by the root context): size bucket -> variant
+  int autotune = 1;
+  std::map<int64_t, int> tune;
+  std::mutex tune_mu;
   DevBuf ss[13];
   int ss_off[13][3] = {};
   int ss_cnt[13][3] = {};

@@ -14,6 +14,7 @@
 // lane l is D[row][l%16] with row = 4*(l/16) + v for the FP32 instruction and
 // row = l/16 + 4*v for the FP64 one.
 #include <algorithm>
+#include <map>
 
 #include "common.h"
 
@@ -40,7 +41,6 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
 };
 
-constexpr int BM = 128, BN = 64;
 constexpr int NXCD = 8;  // accelerator complex dies; workgroups are dealt to them round-robin
 constexpr int GM = 8;    // tile rows per group of the tile order
 constexpr int PADA = 4, PADB = 4;
@@ -52,13 +52,18 @@ template <> struct Slice<double> { static constexpr int BK = 8; };
 // Split K: workgroup z of gridDim.z covers K range [z*kc, min(K, (z+1)*kc)); with
 // gridDim.z > 1 it writes its raw partial product to P + z*M*N (row stride N)
 // and k_gemm_splitk_sum forms C = beta*C + alpha*sum_z P_z in fixed z order.
-template <typename T, bool CONJ_A>
+// Tile: 2 x 2 waves, each owning WM x WN blocks of 16 x 16, so the workgroup
+// covers BM = 32 WM rows and BN = 32 WN columns.  Every variant accumulates an
+// output element over K in the same order (same slices, same MFMA steps), so
+// the tile choice does not change results.
+template <typename T, bool CONJ_A, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, const cplx<T>* __restrict__ A,
                                               int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb, T beta,
                                               cplx<T>* __restrict__ C, int64_t ldc, int64_t kc,
                                               cplx<T>* __restrict__ P) {
   using V4 = typename Mfma<T>::v4;
   constexpr int BK = Slice<T>::BK;
+  constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int AE = BM * BK / 256;  // A elements staged per thread
   constexpr int BE = BN * BK / 256;  // B elements staged per thread
   __shared__ T AsR[2][BK][BM + PADA];
@@ -69,8 +74,8 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1;  // wave row (0..1): rows wr*64 .. +64
-  const int wc = wave & 1;   // wave col (0..1): cols wc*32 .. +32
+  const int wr = wave >> 1;  // wave row (0..1): rows wr*16*WM ..
+  const int wc = wave & 1;   // wave col (0..1): cols wc*16*WN ..
   // XCD-aware tile order: workgroup L runs on XCD L % 8, so XCD x is given the
   // contiguous tile range [start(x), start(x) + count(x)), walked in groups of
   // GM tile rows, column by column: the ~64 workgroups resident on one XCD then
@@ -134,11 +139,11 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
     }
   };
 
-  V4 t1[4][2], t2[4][2], t3[4][2];
+  V4 t1[WM][WN], t2[WM][WN], t3[WM][WN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < WN; ++j) {
       t1[i][j] = V4{0, 0, 0, 0};
       t2[i][j] = V4{0, 0, 0, 0};
       t3[i][j] = V4{0, 0, 0, 0};
@@ -149,23 +154,23 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T ar[4], ai[4], as[4], br[2], bi[2], bs[2];
+      T ar[WM], ai[WM], as[WM], br[WN], bi[WN], bs[WN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ar[i] = AsR[buf][kk + kq][wr * 64 + i * 16 + r16];
-        ai[i] = AsI[buf][kk + kq][wr * 64 + i * 16 + r16];
+      for (int i = 0; i < WM; ++i) {
+        ar[i] = AsR[buf][kk + kq][wr * 16 * WM + i * 16 + r16];
+        ai[i] = AsI[buf][kk + kq][wr * 16 * WM + i * 16 + r16];
         as[i] = ar[i] + ai[i];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        br[j] = BsR[buf][kk + kq][wc * 32 + j * 16 + r16];
-        bi[j] = BsI[buf][kk + kq][wc * 32 + j * 16 + r16];
+      for (int j = 0; j < WN; ++j) {
+        br[j] = BsR[buf][kk + kq][wc * 16 * WN + j * 16 + r16];
+        bi[j] = BsI[buf][kk + kq][wc * 16 * WN + j * 16 + r16];
         bs[j] = br[j] + bi[j];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < WN; ++j) {
           t1[i][j] = Mfma<T>::op(ar[i], br[j], t1[i][j]);
           t2[i][j] = Mfma<T>::op(ai[i], bi[j], t2[i][j]);
           t3[i][j] = Mfma<T>::op(as[i], bs[j], t3[i][j]);
@@ -190,13 +195,13 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
 
   // epilogue
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wr * 64 + i * 16 + Mfma<T>::row(kq, v);
-        const int64_t col = n0 + wc * 32 + j * 16 + r16;
+        const int64_t row = m0 + wr * 16 * WM + i * 16 + Mfma<T>::row(kq, v);
+        const int64_t col = n0 + wc * 16 * WN + j * 16 + r16;
         if (row < M && col < N) {
           const T cr = t1[i][j][v] - t2[i][j][v];
           const T ci = t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
@@ -307,6 +312,104 @@ static void gemv_launch(Context& ctx, int64_t M, int64_t K, double alpha, const 
   FOSB_LAUNCH_CHECK();
 }
 
+// Tile variants (WM, WN) offered to the autotuner, fastest-first by measurement
+// on gfx950 (the first entry is the built-in choice when tuning is off).
+template <typename T> struct Tiles;
+template <> struct Tiles<float> {
+  static constexpr int n = 4;
+  static constexpr int wm[4] = {2, 2, 2, 4}, wn[4] = {2, 1, 4, 2};
+};
+template <> struct Tiles<double> {
+  static constexpr int n = 3;
+  static constexpr int wm[3] = {2, 2, 4}, wn[3] = {1, 2, 2};
+};
+
+template <typename T, bool CONJ_A, int WM, int WN>
+static void launch_tile(hipStream_t s, int64_t M, int64_t N, int64_t K, T alpha, const cplx<T>* A, int64_t lda,
+                        const cplx<T>* B, int64_t ldb, T beta, cplx<T>* C, int64_t ldc, int64_t kc, cplx<T>* P,
+                        int64_t nz) {
+  dim3 grid((unsigned)((N + 32 * WN - 1) / (32 * WN)), (unsigned)((M + 32 * WM - 1) / (32 * WM)), (unsigned)nz);
+  hipLaunchKernelGGL((k_gemm<T, CONJ_A, WM, WN>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                     kc, P);
+  FOSB_LAUNCH_CHECK();
+}
+
+template <typename T, bool CONJ_A>
+static void launch_variant(int var, hipStream_t s, int64_t M, int64_t N, int64_t K, T alpha, const cplx<T>* A,
+                           int64_t lda, const cplx<T>* B, int64_t ldb, T beta, cplx<T>* C, int64_t ldc, int64_t kc,
+                           cplx<T>* P, int64_t nz) {
+  if constexpr (sizeof(T) == 4) {
+    switch (var) {
+      case 1: return launch_tile<T, CONJ_A, 2, 1>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, P, nz);
+      case 2: return launch_tile<T, CONJ_A, 2, 4>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, P, nz);
+      case 3: return launch_tile<T, CONJ_A, 4, 2>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, P, nz);
+      default: return launch_tile<T, CONJ_A, 2, 2>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, P, nz);
+    }
+  } else {
+    switch (var) {
+      case 1: return launch_tile<T, CONJ_A, 2, 2>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, P, nz);
+      case 2: return launch_tile<T, CONJ_A, 4, 2>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, P, nz);
+      default: return launch_tile<T, CONJ_A, 2, 1>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kc, P, nz);
+    }
+  }
+}
+
+static inline int log2_bucket(int64_t x) {
+  int b = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+// Tile variant for this product: the tuned choice of its size bucket (precision,
+// A operand form, floor(log2) of M, N and K).  A bucket met for the first time
+// with tuning on is settled by timing every variant on the real operands into
+// scratch output (twice each, the faster run counts); the choice is kept by the
+// root context.  The variants give identical results, so tuning only affects
+// speed.
+template <typename T, bool CONJ_A>
+static int pick_variant(Context& ctx, int64_t M, int64_t N, int64_t K, const cplx<T>* A, int64_t lda,
+                        const cplx<T>* B, int64_t ldb) {
+  Context& root = ctx.prof_root ? *ctx.prof_root : ctx;
+  if (!root.autotune) return 0;
+  const int64_t key = ((int64_t)(sizeof(T) == 8) << 40) | ((int64_t)CONJ_A << 39) | ((int64_t)log2_bucket(M) << 26) |
+                      ((int64_t)log2_bucket(N) << 13) | (int64_t)log2_bucket(K);
+  {
+    std::lock_guard<std::mutex> lock(root.tune_mu);
+    auto it = root.tune.find(key);
+    if (it != root.tune.end()) return it->second;
+  }
+  ctx.tune_out.reserve((size_t)M * N * sizeof(cplx<T>));
+  if (!ctx.tune_ev[0]) {
+    FOSB_HIP(hipEventCreate(&ctx.tune_ev[0]));
+    FOSB_HIP(hipEventCreate(&ctx.tune_ev[1]));
+  }
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int v = 0; v < Tiles<T>::n; ++v) {
+    float t = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      FOSB_HIP(hipEventRecord(ctx.tune_ev[0], ctx.stream));
+      launch_variant<T, CONJ_A>(v, ctx.stream, M, N, K, T(1), A, lda, B, ldb, T(0),
+                                static_cast<cplx<T>*>(ctx.tune_out.p), N, K, nullptr, 1);
+      FOSB_HIP(hipEventRecord(ctx.tune_ev[1], ctx.stream));
+      FOSB_HIP(hipEventSynchronize(ctx.tune_ev[1]));
+      float ms = 0.f;
+      FOSB_HIP(hipEventElapsedTime(&ms, ctx.tune_ev[0], ctx.tune_ev[1]));
+      t = std::min(t, ms);
+    }
+    if (t < best_ms) {
+      best_ms = t;
+      best = v;
+    }
+  }
+  std::lock_guard<std::mutex> lock(root.tune_mu);
+  root.tune[key] = best;
+  return best;
+}
+
 template <typename T, bool CONJ_A>
 static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
                         const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc) {
@@ -327,9 +430,11 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
     }
   }
   const int64_t Kp = std::max<int64_t>(K, 0);
-  const int64_t tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
   // split K when the output has too few tiles to fill the chip and K is long:
-  // about two workgroups per CU, each still streaming at least 256 of K
+  // about two workgroups per CU, each still streaming at least 256 of K.  The
+  // decision uses a fixed 64 x 64 reference tile, so it (and the summation
+  // order) does not depend on the tile variant chosen below.
+  const int64_t tiles = ((N + 63) / 64) * ((M + 63) / 64);
   int64_t nz = 1;
   const int64_t want = 2LL * ctx.n_cu;
   if (tiles < want && Kp >= 512) nz = std::min<int64_t>({(want + tiles - 1) / tiles, Kp / 256, 64});
@@ -341,12 +446,10 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
     ctx.splitk.reserve((size_t)nz * M * N * sizeof(cplx<T>));
     P = static_cast<cplx<T>*>(ctx.splitk.p);
   }
-  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)nz);
+  const int var = (nz == 1 && Kp > 0) ? pick_variant<T, CONJ_A>(ctx, M, N, Kp, A, lda, B, ldb) : 0;
   {
     ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);
-    hipLaunchKernelGGL((k_gemm<T, CONJ_A>), grid, dim3(256), 0, ctx.stream, M, N, Kp, (T)alpha, A, lda, B, ldb,
-                       (T)beta, C, ldc, kc, P);
-    FOSB_LAUNCH_CHECK();
+    launch_variant<T, CONJ_A>(var, ctx.stream, M, N, Kp, (T)alpha, A, lda, B, ldb, (T)beta, C, ldc, kc, P, nz);
   }
   if (nz > 1) {
     ProfScope prof(ctx, FOSB_K_SPLITK_SUM, 2.0 * (double)nz * M * N,

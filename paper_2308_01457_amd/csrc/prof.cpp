@@ -55,6 +55,8 @@ Context::~Context() {
     (void)hipStreamDestroy(stream);
   }
   for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : tune_ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 }  // namespace fosb

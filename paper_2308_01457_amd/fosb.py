@@ -91,6 +91,7 @@ _SIGS = {
                                      C.POINTER(Stats)]),
     "fosb_second_moment_batch": (C.c_int, [_P, C.POINTER(BatchShape), _I64, _I32, _P, _I64, C.POINTER(Opts), _I32,
                                            C.POINTER(Stats)]),
+    "fosb_autotune": (C.c_int, [_P, _I32, C.POINTER(_I32)]),
     "fosb_profile_enable": (C.c_int, [_P, _I32]),
     "fosb_profile_read": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
 }
@@ -193,6 +194,14 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def autotune(ctx: "Context", mode: int = -1) -> int:
+    """fosb_autotune: 0 off, 1 on, 2 on with a fresh table, -1 query.  Returns the
+    number of tuned GEMM size buckets."""
+    n = _I32()
+    _check(lib().fosb_autotune(ctx.h, mode, C.byref(n)))
+    return n.value
 
 
 def profile_enable(ctx: "Context", on: bool = True) -> None:

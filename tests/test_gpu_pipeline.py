@@ -153,3 +153,28 @@ def test_batch_equals_per_shape(fz, precision):
         ref, _, _ = fosb.second_moment(ctx, it["meshes"], 0, 2, it["k"], prec, it["cov"], xh, it["dirs"],
                                        it["pols"], dir=-1)
         assert np.array_equal(v.cpu().numpy(), ref.cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_does_not_change_results(fz, precision):
+    """GEMM tile shapes differ only in how work is spread: with the autotuner
+    off (built-in shape) and on (fresh table, every size bucket timed) the
+    whole pass gives identical bits."""
+    fosb, ctx, torch = fz
+    prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
+    xh = workloads.angles_xz(31)
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    meshes = [fosb.Mesh(ctx, *workloads.icosphere(s)) for s in (1, 2, 3)]
+    try:
+        fosb.autotune(ctx, 0)
+        v0, b0, _ = fosb.second_moment(ctx, meshes, 1, 3, K1, prec, cov, xh)
+        fosb.autotune(ctx, 2)
+        v1, b1, _ = fosb.second_moment(ctx, meshes, 1, 3, K1, prec, cov, xh)
+        n = fosb.autotune(ctx, -1)
+    finally:
+        fosb.autotune(ctx, 1)
+    print(f"[gpu] autotune {precision}: {n} tuned buckets", flush=True)
+    assert n > 0
+    assert np.array_equal(v0.cpu().numpy(), v1.cpu().numpy())
+    for x, y in zip(b0, b1):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
