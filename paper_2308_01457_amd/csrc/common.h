@@ -123,6 +123,10 @@ struct Context {
   bool owns_stream = false;
   std::unique_ptr<Context> aux;
   Context& aux_context();
+  // LU update stream (blocked LU with lookahead) and its two events
+  std::unique_ptr<Context> la;
+  Context& la_context();
+  hipEvent_t lu_ev[2] = {nullptr, nullptr};
   // batch workers: own streams, scratch and per-shape workspaces (Z, Zlow, blocks)
   std::vector<std::unique_ptr<Context>> workers;
   std::vector<DevBuf> ws_Z, ws_Zlow, ws_blocks;

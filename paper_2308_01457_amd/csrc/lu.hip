@@ -55,9 +55,11 @@ __device__ __forceinline__ T cabs1(cplx<T> a) {
 // buffered, so a step needs two barriers.  The step loop is unrolled, which
 // keeps every register index constant; the row chosen at step j then holds
 // row j of the node's L\U factors and writes it to lu[j][*] (LDS).
-constexpr int NODE = 256;         // rows per tree node = threads per workgroup
-constexpr int NWAVE = NODE / 64;
-constexpr int FANIN = NODE / NB;  // children merged per node (8)
+// Rows per tree node = threads per workgroup (one row per thread); a node
+// merges NODE / NB children.  Wider nodes (512, 1024 rows: fewer tree levels)
+// measured slower: the per-column barrier and key reduction grow with the
+// number of waves.
+template <typename T> struct Node { static constexpr int size = 256; };
 
 // Maximum of a 64-bit key over the wavefront, returned to every lane: DPP
 // exchanges within each row of 16 lanes (xor 1, xor 2, half-row mirror, row
@@ -122,10 +124,10 @@ __device__ __forceinline__ cplx<double> cinv_panel(cplx<double> a) { return cinv
 // every thread picks the largest key and reads that row.  Slots alternate
 // between two buffers, so a wave entering step j+1 never overwrites a slot
 // that another wave still reads at step j.
-template <typename T>
+template <typename T, int NW>
 __device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvalid, int w, int tid, int& step,
-                                         cplx<T> (*prow)[NWAVE][NB], cplx<T> (*lu)[NB + 1],
-                                         unsigned long long (*skey)[NWAVE]) {
+                                         cplx<T> (*prow)[NW][NB], cplx<T> (*lu)[NB + 1],
+                                         unsigned long long (*skey)[NW]) {
   int zero_col = -1;
   const int steps = min(nvalid, w);
   const int lane = tid & 63, wave = tid >> 6;
@@ -147,7 +149,7 @@ __device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvali
       unsigned long long key = 0ull;
       int q = 0;
 #pragma unroll
-      for (int v = 0; v < NWAVE; ++v) {
+      for (int v = 0; v < NW; ++v) {
         const unsigned long long o = skey[b][v];
         if (o > key) {
           key = o;
@@ -202,6 +204,7 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
                                            int tid, int32_t* __restrict__ moves, int32_t* __restrict__ info,
                                            cplx<T>* __restrict__ top, cplx<T>* __restrict__ invL,
                                            cplx<T>* __restrict__ invU) {
+  constexpr int NODE = Node<T>::size;
   __shared__ int inblk[NB];   // 1 if row k + r is itself a pivot
   __shared__ int s_cnt[2];
   for (int e = tid; e < NB * NB; e += NODE) {
@@ -289,12 +292,13 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
 // the candidates of up to FANIN children of the previous level.  Candidates
 // of node p are written to cand_out[p*NB .. p*NB + NB) (-1 = none).
 template <typename T>
-__global__ __launch_bounds__(NODE) void k_tslu_node(const cplx<T>* __restrict__ A, int64_t lda, int64_t n, int64_t k,
+__global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __restrict__ A, int64_t lda, int64_t n, int64_t k,
                                                     int w, const int32_t* __restrict__ cand_in, int n_in,
                                                     int32_t* __restrict__ cand_out, int is_root,
                                                     int32_t* __restrict__ moves, int32_t* __restrict__ info,
                                                     cplx<T>* __restrict__ top, cplx<T>* __restrict__ invL,
                                                     cplx<T>* __restrict__ invU) {
+  constexpr int NODE = Node<T>::size, NWAVE = NODE / 64, FANIN = NODE / NB;
   __shared__ cplx<T> prow[2][NWAVE][NB];
   __shared__ cplx<T> lu[NB][NB + 1];
   __shared__ int sidx[NODE];
@@ -347,19 +351,32 @@ __global__ __launch_bounds__(NODE) void k_tslu_node(const cplx<T>* __restrict__ 
   if (tid >= ncand && tid < NB) out[tid] = -1;
 }
 
-// Apply the listed row moves to the full matrix width (column stripes of 64).
+// Apply npl consecutive row-move lists (list q at plist + q * kMoveStride, in
+// order) to the columns of up to two ranges [c0[r], c1[r]), in stripes of 64.
+struct ColRanges {
+  int64_t c0[2], c1[2];
+};
+constexpr int kMoveStrideDev = 1 + 4 * NB;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_permute_rows(cplx<T>* __restrict__ A, int64_t lda, int64_t ncols,
-                                                      const int32_t* __restrict__ plist) {
+__global__ __launch_bounds__(256) void k_permute_rows(cplx<T>* __restrict__ A, int64_t lda, ColRanges cr,
+                                                      const int32_t* __restrict__ plist, int npl) {
   __shared__ cplx<T> buf[2 * NB][64];
-  const int cnt = plist[0];
-  const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t w0 = cr.c1[0] - cr.c0[0];
+  const int64_t x = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t c = x < w0 ? cr.c0[0] + x : cr.c0[1] + (x - w0);
+  const bool live = x < w0 || (c < cr.c1[1]);
   const int g = threadIdx.x >> 6;
-  if (c < ncols)
-    for (int e = g; e < cnt; e += 4) buf[e][threadIdx.x & 63] = A[(int64_t)plist[1 + 2 * e] * lda + c];
-  __syncthreads();
-  if (c < ncols)
-    for (int e = g; e < cnt; e += 4) A[(int64_t)plist[2 + 2 * e] * lda + c] = buf[e][threadIdx.x & 63];
+  for (int q = 0; q < npl; ++q) {
+    const int32_t* pl = plist + (int64_t)q * kMoveStrideDev;
+    const int cnt = pl[0];
+    if (live)
+      for (int e = g; e < cnt; e += 4) buf[e][threadIdx.x & 63] = A[(int64_t)pl[1 + 2 * e] * lda + c];
+    __syncthreads();
+    if (live)
+      for (int e = g; e < cnt; e += 4) A[(int64_t)pl[2 + 2 * e] * lda + c] = buf[e][threadIdx.x & 63];
+    __syncthreads();
+  }
 }
 
 // Write L11\U11 into the diagonal block and form A21 U11^{-1} below it; four
@@ -515,9 +532,12 @@ struct LuRun {
   int32_t* cand;   // two candidate buffers (ping-pong), each cand_stride ints
   int64_t cand_stride;
   cplx<T>* top;
+  int64_t pc0, pc1;  // columns a panel permutes at once (the rest is the update stream's)
 };
 
 constexpr int kMoveStride = 1 + 4 * NB;
+static_assert(kMoveStride == kMoveStrideDev, "row-move list stride");
+constexpr int64_t kLookaheadMinN = 2048;  // smaller matrices: plain recursion on one stream
 
 static inline int64_t split_half(int64_t w) { return (int64_t)NB * (((w / NB) + 1) / 2); }
 
@@ -529,6 +549,7 @@ static void panel(LuRun<T>& R, int64_t k, int w) {
   int32_t* moves = R.moves + blk * kMoveStride;
   ProfScope prof(*R.ctx, FOSB_K_PANEL, 0.0, (double)sizeof(cplx<T>) * (double)m * w * 3.0);
   // leaf level over consecutive rows, then FANIN-way merges until one node remains
+  constexpr int NODE = Node<T>::size, FANIN = NODE / NB;
   int nodes = (int)((m + NODE - 1) / NODE);
   int32_t* cin = R.cand;
   int32_t* cout = R.cand + R.cand_stride;
@@ -546,7 +567,11 @@ static void panel(LuRun<T>& R, int64_t k, int w) {
     std::swap(cin, cout);
     nodes = next;
   }
-  hipLaunchKernelGGL(k_permute_rows<T>, dim3((unsigned)((R.n + 63) / 64)), dim3(256), 0, s, R.A, R.lda, R.n, moves);
+  {
+    ColRanges cr{{R.pc0, 0}, {R.pc1, 0}};
+    hipLaunchKernelGGL(k_permute_rows<T>, dim3((unsigned)((R.pc1 - R.pc0 + 63) / 64)), dim3(256), 0, s, R.A, R.lda,
+                       cr, moves, 1);
+  }
   FOSB_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_panel_finish<T>, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, R.A, R.lda, R.n, k, w,
                      R.top, R.dinvU + blk * NB * NB);
@@ -569,11 +594,71 @@ static void rec_lu(LuRun<T>& R, int64_t k, int64_t w) {
   rec_lu(R, k + w1, w - w1);
 }
 
+// Right-looking blocked LU with a lookahead of one block column, over two
+// streams.  The panel stream (the context's) factors block column j with the
+// recursion above, restricted to its own columns (its row moves touch only
+// those columns).  The update stream (a child context with its own scratch)
+// applies block j's row moves to every other column, solves and updates block
+// column j+1 first, lets the panel stream start on it, and then updates the
+// remaining columns while that panel is being factored.  The two streams never
+// touch the same columns concurrently: the panel of block j+1 reads and writes
+// only block j+1, the trailing update of step j only columns right of it, and
+// block j's multipliers are permuted by the update stream after its last read.
+template <typename T>
+static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
+  Context& P = *R.ctx;
+  hipStream_t sa = P.stream, sb = U.stream;
+  cplx<T>* A = R.A;
+  const int64_t n = R.n, lda = R.lda;
+  if (!P.lu_ev[0]) {
+    FOSB_HIP(hipEventCreateWithFlags(&P.lu_ev[0], hipEventDisableTiming));
+    FOSB_HIP(hipEventCreateWithFlags(&P.lu_ev[1], hipEventDisableTiming));
+  }
+  hipEvent_t ev_panel = P.lu_ev[0], ev_look = P.lu_ev[1];
+  auto panel_block = [&](int64_t k, int64_t w) {
+    R.pc0 = k;
+    R.pc1 = k + w;
+    rec_lu(R, k, w);
+    FOSB_HIP(hipEventRecord(ev_panel, sa));
+  };
+  panel_block(0, std::min(nb, n));
+  const int64_t nblk = (n + nb - 1) / nb;
+  for (int64_t j = 0; j < nblk; ++j) {
+    const int64_t kj = j * nb, wj = std::min(nb, n - kj);
+    FOSB_HIP(hipStreamWaitEvent(sb, ev_panel, 0));
+    {
+      ColRanges cr{{0, kj + wj}, {kj, n}};
+      const int64_t width = kj + (n - kj - wj);
+      if (width > 0) {
+        ProfScope prof(U, FOSB_K_PANEL, 0.0, 0.0);
+        hipLaunchKernelGGL(k_permute_rows<T>, dim3((unsigned)((width + 63) / 64)), dim3(256), 0, sb, A, lda, cr,
+                           R.moves + (kj / NB) * kMoveStride, (int)((wj + NB - 1) / NB));
+        FOSB_LAUNCH_CHECK();
+      }
+    }
+    if (j + 1 == nblk) break;
+    const int64_t k1 = kj + wj, w1 = std::min(nb, n - k1);
+    trsm_lower_unit<T>(U, A, lda, R.dinvL, kj, wj, A + kj * lda + k1, lda, w1);
+    gemm<T>(U, n - k1, w1, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + k1, lda, 1.0, A + k1 * lda + k1, lda);
+    FOSB_HIP(hipEventRecord(ev_look, sb));
+    FOSB_HIP(hipStreamWaitEvent(sa, ev_look, 0));
+    panel_block(k1, w1);
+    if (k1 + w1 < n) {
+      const int64_t kr = k1 + w1;
+      trsm_lower_unit<T>(U, A, lda, R.dinvL, kj, wj, A + kj * lda + kr, lda, n - kr);
+      gemm<T>(U, n - k1, n - kr, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + kr, lda, 1.0, A + k1 * lda + kr,
+              lda);
+    }
+  }
+  FOSB_HIP(hipEventRecord(ev_look, sb));
+  FOSB_HIP(hipStreamWaitEvent(sa, ev_look, 0));
+}
+
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
                   std::vector<int32_t>& perm) {
   hipStream_t s = ctx.stream;
-  const int64_t maxnodes = (n + NODE - 1) / NODE;
+  const int64_t maxnodes = (n + Node<T>::size - 1) / Node<T>::size;
   const int64_t npanel = (n + NB - 1) / NB;
   const size_t n_i32 = (size_t)(2 * maxnodes * NB + npanel * kMoveStride + 1);
   const size_t top_off = (n_i32 * sizeof(int32_t) + 255) / 256 * 256;
@@ -591,8 +676,22 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   R.moves = base + 2 * maxnodes * NB;
   R.info = R.moves + npanel * kMoveStride;
   R.top = reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(base) + top_off);
+  R.pc0 = 0;
+  R.pc1 = n;
   FOSB_HIP(hipMemsetAsync(R.info, 0, sizeof(int32_t), s));
-  rec_lu(R, 0, n);
+  if (n >= kLookaheadMinN) {
+    Context& U = ctx.la_context();
+    // the update stream starts after everything already queued on the panel stream
+    if (!ctx.lu_ev[0]) {
+      FOSB_HIP(hipEventCreateWithFlags(&ctx.lu_ev[0], hipEventDisableTiming));
+      FOSB_HIP(hipEventCreateWithFlags(&ctx.lu_ev[1], hipEventDisableTiming));
+    }
+    FOSB_HIP(hipEventRecord(ctx.lu_ev[1], s));
+    FOSB_HIP(hipStreamWaitEvent(U.stream, ctx.lu_ev[1], 0));
+    blocked_lu(R, U, n >= 16384 ? 512 : 256);
+  } else {
+    rec_lu(R, 0, n);
+  }
   std::vector<int32_t> mv((size_t)npanel * kMoveStride);
   int32_t info = 0;
   FOSB_HIP(hipMemcpyAsync(mv.data(), R.moves, mv.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));

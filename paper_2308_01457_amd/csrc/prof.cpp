@@ -30,7 +30,7 @@ static std::unique_ptr<Context> child_context(Context& parent) {
   a->device = parent.device;
   a->n_cu = parent.n_cu;
   a->max_lds = parent.max_lds;
-  a->prof_root = &parent;
+  a->prof_root = parent.prof_root ? parent.prof_root : &parent;
   FOSB_HIP(hipSetDevice(parent.device));
   FOSB_HIP(hipStreamCreateWithFlags(&a->stream, hipStreamNonBlocking));  // default priority
   a->owns_stream = true;
@@ -42,6 +42,11 @@ Context& Context::aux_context() {
   return *aux;
 }
 
+Context& Context::la_context() {
+  if (!la) la = child_context(*this);
+  return *la;
+}
+
 Context& Context::worker_context(size_t i) {
   while (workers.size() <= i) workers.push_back(child_context(*this));
   return *workers[i];
@@ -50,6 +55,9 @@ Context& Context::worker_context(size_t i) {
 Context::~Context() {
   workers.clear();
   if (aux) aux.reset();
+  if (la) la.reset();
+  for (hipEvent_t e : lu_ev)
+    if (e) (void)hipEventDestroy(e);
   if (owns_stream && stream) {
     (void)hipStreamSynchronize(stream);
     (void)hipStreamDestroy(stream);

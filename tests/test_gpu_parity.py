@@ -70,6 +70,32 @@ def test_assemble_other_wavenumber_and_gauss_order(fz):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_level_solve_blocked_lookahead_sizes(fz, precision):
+    """Sizes that take the blocked, two-stream LU: N = 2430 (geodesic sphere
+    nu = 9: neither a multiple of the 32-column panel nor of the 256-column
+    block) and N = 7680 (icosphere s = 4); backward error of X = Z^{-1} B and
+    of X = Z^{-H} B, measured on the GPU against the kept matrix."""
+    fosb, ctx, torch = fz
+    rng = np.random.default_rng(8)
+    for name, (V, F), nrhs in (("nu9", workloads.geodesic_sphere(9), 5), ("s4", workloads.icosphere(4), 3)):
+        m = fosb.Mesh(ctx, V, F)
+        Z = fosb.assemble(ctx, m, K1)
+        Zc = Z.clone()
+        prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
+        print(f"[gpu] blocked LU {precision} {name} N={m.n_edges}", flush=True)
+        lv = fosb.Level(ctx, m, K1, Z, prec)
+        B = torch.tensor(rng.standard_normal((m.n_edges, nrhs)) + 1j * rng.standard_normal((m.n_edges, nrhs)),
+                         device=ctx.torch_device)
+        nz = torch.linalg.matrix_norm(Zc).item()   # Frobenius (>= the 2-norm)
+        X = lv.solve(B.clone())
+        bwd = (torch.linalg.matrix_norm(Zc @ X - B) / (nz * torch.linalg.matrix_norm(X))).item()
+        Xa = lv.solve_adjoint(B.clone())
+        bwa = (torch.linalg.matrix_norm(Zc.conj().T.contiguous() @ Xa - B) / (nz * torch.linalg.matrix_norm(Xa))).item()
+        print(f"[gpu]   backward error {bwd:.2e}, adjoint {bwa:.2e}", flush=True)
+        assert bwd < 1e-14 and bwa < 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_level_solve_backward_error(fz, precision):
     """X = Z^{-1} B on ragged sizes (N = 120, 480, 1920; nrhs 1, 7, 33): small
     backward error and agreement with LAPACK on the same matrix."""
