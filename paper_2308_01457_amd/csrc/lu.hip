@@ -678,7 +678,8 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   R.top = reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(base) + top_off);
   R.pc0 = 0;
   R.pc1 = n;
-  FOSB_HIP(hipMemsetAsync(R.info, 0, sizeof(int32_t), s));
+  // first zero pivot, reduced with atomicMin: starts above every index (0x7f7f7f7f)
+  FOSB_HIP(hipMemsetAsync(R.info, 0x7f, sizeof(int32_t), s));
   if (n >= kLookaheadMinN) {
     Context& U = ctx.la_context();
     // the update stream starts after everything already queued on the panel stream
@@ -713,6 +714,7 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
     }
     for (int e = 0; e < cnt; ++e) perm[m[2 + 2 * e]] = src_rows[e];
   }
+  if (info == 0x7f7f7f7f) info = 0;
   return info;  // 0, or 1-based index of the first exactly zero pivot
 }
 

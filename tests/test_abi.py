@@ -98,3 +98,12 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(fosb, "LIB_PATH", str(tmp_path / "libfosb.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         fosb.lib()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stdout
