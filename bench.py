@@ -12,10 +12,9 @@ Inputs (meshes, uploaded tables) and output buffers are resident on the GPU
 before the timed region.  The metric is level-pair solves per second of the
 mixed-precision path (FP32-complex MFMA LU + FP64 refinement); the FP64 path
 is timed too and reported next to it, with the relative difference of the two
-variances.  Refinement stops once a correction is below --ir-tol (default
-1e-4) relative to the iterate: the iterate it produces is then accurate to
-about the square of that (one sweep contracts the error by the FP32 solve's
-relative accuracy), which the reported mixed-vs-FP64 difference confirms.
+variances.  Refinement stops once the estimated relative error of the
+solves (from the decay of the corrections) is below --ir-tol (default 1e-8);
+the reported mixed-vs-FP64 difference confirms the accuracy reached.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision both|mixed|fp64]
 """
@@ -70,13 +69,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--max-level", type=int, default=5)
-    ap.add_argument("--ir-tol", type=float, default=1e-4,
-                    help="mixed path: stop refining when the relative correction is below this")
+    ap.add_argument("--ir-tol", type=float, default=1e-8,
+                    help="mixed path: target relative error of the refined solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--progress", action="store_true", help="print a line after every stage of every step")
-    ap.add_argument("--workload", default="mixed_k5", choices=["mixed_k5", "ellipsoids"],
-                    help="mixed_k5: the k=5 icosphere ladder (default); ellipsoids: 64 seeded ellipsoids x 16 "
+    ap.add_argument("--workload", default="mixed_k5", choices=["mixed_k5", "superquad_k8", "ellipsoids"],
+                    help="mixed_k5: the k=5 icosphere ladder (default); superquad_k8: the superquadric ladder "
+                         "|x|^4+|y|^4+|z|^4=1, k=8, to --max-level (s=6 does not fit both precisions' matrices "
+                         "on one GPU); ellipsoids: 64 seeded ellipsoids x 16 "
                          "incidences, 3 levels each, Matern-3/2 covariance, all incidences solved together")
     ap.add_argument("--shapes", type=int, default=64, help="ellipsoids: number of shapes")
     ap.add_argument("--workers", type=int, default=4,
@@ -90,10 +91,18 @@ def parse():
 
 
 class Workload:
-    def __init__(self, max_level: int):
+    def __init__(self, name: str, max_level: int):
         import workloads
-        self.w = workloads.workload("mixed_k5", max_level=max_level)
+        self.name = name
+        self.w = workloads.workload(name, max_level=max_level)
         self.xh = self.w.angles
+
+    def describe(self, npairs: int) -> str:
+        w = self.w
+        geo = "unit icosphere" if self.name == "mixed_k5" else "superquadric |x|^4+|y|^4+|z|^4=1"
+        return (f"{self.name}: {geo} s={w.levels[0]}..{w.levels[-1]} (N up to {30 * 4 ** w.levels[-1]}), "
+                f"k={w.k:g}, Gaussian radial cov ({w.sigma:g}, {w.ell:g}), L0={w.L0} L={w.L} ({npairs} pairs), "
+                f"{w.n_angles} angles")
 
 
 def gpu_setup(fosb, torch, ctx, W):
@@ -400,7 +409,7 @@ def main():
     if args.workload == "ellipsoids":
         run_batched(args)
         return
-    W = Workload(args.max_level)
+    W = Workload(args.workload, args.max_level)
     gpu, (lu_f, solve_f, ff_f, npairs) = run_gpu(args, W)
     head = "mixed" if "mixed" in gpu else "fp64"
     h = gpu[head]
@@ -417,9 +426,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64+f64" if head == "mixed" else "c128",
         "data": "synthetic",
-        "config": {"workload": f"mixed_k5: unit icosphere s={W.w.levels[0]}..{W.w.levels[-1]} "
-                               f"(N up to {30 * 4 ** W.w.levels[-1]}), k=5, Gaussian radial cov (0.01, 0.5), "
-                               f"L0={W.w.L0} L={W.w.L} ({npairs} pairs), {W.w.n_angles} angles",
+        "config": {"workload": W.describe(npairs),
                    "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol},
         "algorithmic_flop_per_step": {"lu": lu_f, "pair_solves": solve_f, "far_field": ff_f},
     }
@@ -444,7 +451,7 @@ def main():
                             "algorithmic_bytes_per_launch": by / max(n, 1)}
         line["kernel_profile"] = {k: {"launches": v[0], "seconds": v[1], "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
                                       "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof.items()}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and W.name == "mixed_k5":
         log("[bench] cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(line), flush=True)

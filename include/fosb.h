@@ -86,7 +86,9 @@ typedef struct fosb_opts {
   int32_t n_gauss_singular; /* Gauss-Legendre points per dimension of the
                                Sauter-Schwab rules on touching pairs (1..12; 5)   */
   int32_t ir_max_sweeps;    /* refinement sweeps of the MIXED path (0..50; 10)     */
-  double ir_tol;            /* stop when ||dX||_F <= ir_tol ||X||_F (1e-10)        */
+  double ir_tol;            /* target relative error of refined solves (1e-10):
+                               after corrections of relative size r_{k-1}, r_k
+                               (r_0 = 1) the error is estimated as r_k^2/r_{k-1} */
 } fosb_opts;
 
 typedef struct fosb_stats {
@@ -104,6 +106,9 @@ fosb_status fosb_opts_default(fosb_opts* opts);
 /* Binds HIP device `device` and stream `hip_stream` (a hipStream_t; NULL = the
  * null stream).  The stream is borrowed, not destroyed. */
 fosb_status fosb_context_create(int32_t device, void* hip_stream, fosb_context** out);
+/* Waits for the context's stream, then frees it.  Meshes and levels created on
+ * it and not yet destroyed are detached: every call rejects them with
+ * FOSB_E_INVALID, and their destroy only frees their device memory. */
 fosb_status fosb_context_destroy(fosb_context* ctx);
 fosb_status fosb_context_synchronize(fosb_context* ctx);
 
@@ -120,6 +125,7 @@ fosb_status fosb_mesh_create(fosb_context* ctx, const double* V, int64_t nv, con
                              int64_t nt, fosb_mesh** out);
 fosb_status fosb_mesh_info(const fosb_mesh* mesh, int64_t* n_triangles, int64_t* n_edges,
                            int64_t* n_touching_pairs);
+/* The mesh must outlive every level built on it (levels read its geometry). */
 fosb_status fosb_mesh_destroy(fosb_mesh* mesh);
 
 /* ---------------------------------------------------------------- assembly */

@@ -87,7 +87,12 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   const c128* Z64 = static_cast<const c128*>(L.Z);
   copy_c128(s, B, ldb, Bo, nrhs, n, nrhs);
   const c128* R = Bo;  // first residual is B itself
-  double prev = INFINITY, rel = INFINITY;
+  // Each sweep contracts the error by about the FP32 solve's relative accuracy,
+  // estimated by the ratio of consecutive corrections: after a correction of
+  // relative size r_k following one of r_{k-1} (r_0 = 1, the first solve) the
+  // iterate's error is about r_k^2 / r_{k-1}.  Refinement stops once that
+  // estimate is below ir_tol.
+  double prev = 1.0, rel = INFINITY, est = INFINITY;
   int sweeps = 0;
   for (int it = 0;; ++it) {
     c128* D;  // this sweep's correction
@@ -116,8 +121,9 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     FOSB_HIP(hipMemcpyAsync(nn, ctx.norms.p, sizeof(nn), hipMemcpyDeviceToHost, s));
     FOSB_HIP(hipStreamSynchronize(s));
     rel = nn[1] > 0 ? std::sqrt(nn[0] / nn[1]) : 0.0;
+    est = it == 0 ? 1.0 : rel * rel / prev;
     if (it > 0) sweeps = it;
-    if (rel <= L.opts.ir_tol || it >= L.opts.ir_max_sweeps || (it > 1 && rel >= prev)) break;
+    if (est <= L.opts.ir_tol || it >= L.opts.ir_max_sweeps || (it > 1 && rel >= prev)) break;
     prev = rel;
     // residual R = Bo - op(Z64) X in FP64 (scratch[5])
     copy_c128(s, Bo, nrhs, Rw, nrhs, n, nrhs);
@@ -132,9 +138,9 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     st->ir_sweeps = std::max(st->ir_sweeps, sweeps);
     st->ir_rel_correction = std::max(st->ir_rel_correction, rel);
   }
-  if (rel > L.opts.ir_tol && L.opts.ir_max_sweeps > 0) {
+  if (est > L.opts.ir_tol && L.opts.ir_max_sweeps > 0) {
     FOSB_HIP(hipStreamSynchronize(s));
-    fail(FOSB_E_NOCONV, "refinement stopped at relative correction %.3e after %d sweeps (tol %.1e)", rel, sweeps,
+    fail(FOSB_E_NOCONV, "refinement stopped at estimated relative error %.3e after %d sweeps (tol %.1e)", est, sweeps,
          L.opts.ir_tol);
   }
 }
@@ -452,6 +458,11 @@ fosb_status fosb_context_destroy(fosb_context* ctx) {
   if (!ctx) return FOSB_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  {
+    std::lock_guard<std::mutex> lock(ctx->reg_mu);
+    for (Level* l : ctx->live_levels) l->ctx = nullptr;
+    for (Mesh* m : ctx->live_meshes) m->ctx = nullptr;
+  }
   delete ctx;
   API_END
 }
@@ -483,6 +494,10 @@ fosb_status fosb_mesh_create(fosb_context* ctx, const double* V, int64_t nv, con
   bind(*ctx);
   m->ctx = ctx;
   mesh_upload(*m);
+  {
+    std::lock_guard<std::mutex> lock(ctx->reg_mu);
+    ctx->live_meshes.insert(m.get());
+  }
   *out = m.release();
   API_END
 }
@@ -499,7 +514,11 @@ fosb_status fosb_mesh_info(const fosb_mesh* mesh, int64_t* n_triangles, int64_t*
 fosb_status fosb_mesh_destroy(fosb_mesh* mesh) {
   API_BEGIN
   if (!mesh) return FOSB_OK;
-  (void)hipSetDevice(mesh->ctx->device);
+  if (mesh->ctx) {  // null once its context was destroyed
+    (void)hipSetDevice(mesh->ctx->device);
+    std::lock_guard<std::mutex> lock(mesh->ctx->reg_mu);
+    mesh->ctx->live_meshes.erase(mesh);
+  }
   delete mesh;
   API_END
 }
@@ -532,7 +551,12 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
   check_level_args(mesh, k, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, field);
   fosb_opts o = opts_or_default(opts);
   bind(*ctx);
-  *out = level_build(*ctx, mesh, k, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, field, o).release();
+  auto L = level_build(*ctx, mesh, k, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, field, o);
+  {
+    std::lock_guard<std::mutex> lock(ctx->reg_mu);
+    ctx->live_levels.insert(L.get());
+  }
+  *out = L.release();
   API_END
 }
 
@@ -572,6 +596,7 @@ fosb_status fosb_level_solve_adjoint(fosb_context* ctx, const fosb_level* level,
 fosb_status fosb_level_first_moment(fosb_context* ctx, const fosb_level* level, int64_t dir, void* u) {
   API_BEGIN
   REQUIRE(ctx && level && u, "ctx/level/u is NULL");
+  REQUIRE(level->ctx == ctx, "level belongs to another context");
   REQUIRE(dir >= 0 && dir < level->n_dirs, "dir out of range");
   bind(*ctx);
   copy_c128(ctx->stream, level->u.as<c128>() + dir, level->n_dirs, static_cast<c128*>(u), 1, level->n, 1);
@@ -581,8 +606,12 @@ fosb_status fosb_level_first_moment(fosb_context* ctx, const fosb_level* level, 
 fosb_status fosb_level_destroy(fosb_level* level) {
   API_BEGIN
   if (!level) return FOSB_OK;
-  (void)hipSetDevice(level->ctx->device);
-  (void)hipStreamSynchronize(level->ctx->stream);
+  if (level->ctx) {  // null once its context was destroyed
+    (void)hipSetDevice(level->ctx->device);
+    (void)hipStreamSynchronize(level->ctx->stream);
+    std::lock_guard<std::mutex> lock(level->ctx->reg_mu);
+    level->ctx->live_levels.erase(level);
+  }
   delete level;
   API_END
 }
@@ -659,6 +688,7 @@ fosb_status fosb_far_field_matrix(fosb_context* ctx, const fosb_level* level, co
                                   void* FF) {
   API_BEGIN
   REQUIRE(ctx && level && xhat && FF, "NULL argument");
+  REQUIRE(level->ctx == ctx, "level belongs to another context");
   REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
   bind(*ctx);
   std::vector<double> x(xhat, xhat + 3 * n_a);
@@ -875,8 +905,13 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
     stats->ir_rel_correction =
         std::max(stats->ir_rel_correction, std::max(st_main.ir_rel_correction, st_aux.ir_rel_correction));
   }
-  if (levels_out)
-    for (int i = 0; i < n_levels; ++i) levels_out[i] = lv[i].release();
+  if (levels_out) {
+    std::lock_guard<std::mutex> lock(ctx->reg_mu);
+    for (int i = 0; i < n_levels; ++i) {
+      ctx->live_levels.insert(lv[i].get());
+      levels_out[i] = lv[i].release();
+    }
+  }
   API_END
 }
 

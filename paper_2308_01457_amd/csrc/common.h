@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -103,6 +104,12 @@ struct Context {
   DevBuf splitk;      // partial products of split-K GEMMs
   DevBuf tune_out;    // scratch output of autotuning runs
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
+  // handles created on this context and not yet destroyed: destroying the
+  // context detaches them (their ctx becomes null), so a later destroy of a
+  // handle never touches a freed context
+  std::set<struct Level*> live_levels;
+  std::set<struct Mesh*> live_meshes;
+  std::mutex reg_mu;
   // GEMM tile autotuner (kept by the root context): size bucket -> variant
   int autotune = 1;
   std::map<int64_t, int> tune;

@@ -66,7 +66,7 @@ def test_adjoint_solve_backward_error(fz, precision):
         Zc = Z.clone().cpu().numpy()
         prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
         print(f"[gpu] adjoint solve {precision} s={s} nrhs={nrhs}", flush=True)
-        lv = fosb.Level(ctx, m, K1, Z, prec)
+        lv = fosb.Level(ctx, m, K1, Z, prec, opts=fosb.opts_default(ir_tol=1e-13))  # refine to the FP64 floor
         B = rng.standard_normal((m.n_edges, nrhs)) + 1j * rng.standard_normal((m.n_edges, nrhs))
         X = lv.solve_adjoint(torch.tensor(B, device=ctx.torch_device)).cpu().numpy()
         ZH = Zc.conj().T

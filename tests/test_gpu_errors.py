@@ -92,3 +92,22 @@ def test_bad_arguments(fz):
     blocks = fosb.correlation(ctx, [l1, l2], 1, 2, fosb.make_cov("gaussian", 0.01, 0.5))
     var = fosb.far_field_moments(ctx, [l1, l2], 1, 2, blocks, workloads.angles_xz(9))
     assert np.isfinite(var.cpu().numpy()).all()
+
+
+def test_handles_outlive_their_context(fz):
+    """Destroying a context before its meshes and levels detaches them: a
+    detached handle is rejected by every call and destroying it only frees it."""
+    fosb, ctx, torch = fz
+    c2 = fosb.Context(0)
+    m = fosb.Mesh(c2, *workloads.icosphere(1))
+    lv = fosb.Level(c2, m, 1.0, fosb.assemble(c2, m, 1.0), fosb.FP64)
+    print("[gpu] context destroyed before its level and mesh", flush=True)
+    c2.close()
+    with pytest.raises(fosb.FosbError) as e:                  # detached level on a live context
+        fosb.correlation(ctx, [lv], 1, 1, fosb.make_cov("gaussian", 0.01, 0.5))
+    assert e.value.name == "E_INVALID"
+    lv.close()
+    m.close()
+    # the other context is unaffected
+    m2 = fosb.Mesh(ctx, *workloads.icosphere(1))
+    assert torch.isfinite(fosb.assemble(ctx, m2, 1.0).abs()).all()

@@ -83,7 +83,7 @@ def test_level_solve_blocked_lookahead_sizes(fz, precision):
         Zc = Z.clone()
         prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
         print(f"[gpu] blocked LU {precision} {name} N={m.n_edges}", flush=True)
-        lv = fosb.Level(ctx, m, K1, Z, prec)
+        lv = fosb.Level(ctx, m, K1, Z, prec, opts=fosb.opts_default(ir_tol=1e-13))  # refine to the FP64 floor
         B = torch.tensor(rng.standard_normal((m.n_edges, nrhs)) + 1j * rng.standard_normal((m.n_edges, nrhs)),
                          device=ctx.torch_device)
         nz = torch.linalg.matrix_norm(Zc).item()   # Frobenius (>= the 2-norm)
@@ -108,7 +108,7 @@ def test_level_solve_backward_error(fz, precision):
         Zc = Z.clone().cpu().numpy()
         prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
         print(f"[gpu] solve {precision} s={s} nrhs={nrhs}", flush=True)
-        lv = fosb.Level(ctx, m, K1, Z, prec)
+        lv = fosb.Level(ctx, m, K1, Z, prec, opts=fosb.opts_default(ir_tol=1e-13))  # refine to the FP64 floor
         B = rng.standard_normal((m.n_edges, nrhs)) + 1j * rng.standard_normal((m.n_edges, nrhs))
         Bt = torch.tensor(B, device=ctx.torch_device)
         st = fosb.Stats()
