@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--schedule", default="concurrent", choices=["concurrent", "sequential"],
                     help="concurrent: the library's two-stream pipeline (fosb_second_moment); sequential: the "
                          "step-by-step calls, timed per stage")
+    ap.add_argument("--autotune", default="on", choices=["on", "off"],
+                    help="GEMM tile autotuner (off: the built-in tile for every product)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -179,6 +181,7 @@ def run_gpu(args, W):
     from paper_2308_01457_amd import fosb
 
     ctx = fosb.Context(0)
+    fosb.autotune(ctx, 1 if args.autotune == "on" else 0)
     cov = fosb.make_cov(W.w.cov_kind, W.w.sigma, W.w.ell)
     opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
     meshes, Z = gpu_setup(fosb, torch, ctx, W)
@@ -252,6 +255,7 @@ def run_batched(args):
     from paper_2308_01457_amd import fosb
     shapes = workloads.batched_ellipsoids(args.shapes, 16, 0)
     ctx = fosb.Context(0)
+    fosb.autotune(ctx, 1 if args.autotune == "on" else 0)
     dev = ctx.torch_device
     xh = workloads.angles_xz(181)
     meshes = [[fosb.Mesh(ctx, V, F) for V, F in w.meshes] for w in shapes]
@@ -427,7 +431,7 @@ def main():
         "dtype": "c64+f64" if head == "mixed" else "c128",
         "data": "synthetic",
         "config": {"workload": W.describe(npairs),
-                   "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol},
+                   "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol, "autotune": args.autotune},
         "algorithmic_flop_per_step": {"lu": lu_f, "pair_solves": solve_f, "far_field": ff_f},
     }
     for pname, rec in gpu.items():

@@ -216,41 +216,56 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
   if (tid < wk && win[tid] < k + wk) inblk[win[tid] - k] = 1;
   for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
   if (zc >= 0 && tid == 0) atomicMin(info, (int)(k + zc + 1));
-  // inverses of the diagonal factors by Gauss-Jordan sweeps over the whole
-  // workgroup (identity beyond wk):  L X = I forward, U X = I backward
-  __shared__ cplx<T> sx[NB][NB + 1];
-  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
-  __syncthreads();
-  for (int r = 0; r < wk; ++r) {
-    // rows i > r: X[i][c] -= L[i][r] X[r][c], c <= r
-    const int cols = r + 1, rows = wk - r - 1;
-    for (int e = tid; e < rows * cols; e += NODE) {
-      const int i = r + 1 + e / cols, c = e % cols;
-      const cplx<T> l = tb[i][r], x = sx[r][c];
-      sx[i][c].re -= l.re * x.re - l.im * x.im;
-      sx[i][c].im -= l.re * x.im + l.im * x.re;
+  // Inverses of the diagonal factors (identity beyond wk), one column c per
+  // thread and no barriers: lanes 0..NB-1 of wave 0 solve L X = I forward,
+  // lanes 0..NB-1 of wave 1 solve U X = I backward, reading the factors as LDS
+  // broadcasts.  Right-looking: once entry i of the column is final it is
+  // stored and subtracted from the pending entries, which sit in a register
+  // window that moves by one per step (y[0] is entry i; the loops unroll, so
+  // the moves are register renaming).
+  {
+    const int wv = tid >> 6, c = tid & 63;
+    if (wv == 0 && c < NB) {
+      cplx<T> y[NB];  // y[m] = entry i + m
+#pragma unroll
+      for (int m = 0; m < NB; ++m) y[m] = cplx<T>{m == c ? T(1) : T(0), T(0)};
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const cplx<T> x = y[0];
+        invL[i * NB + c] = x;
+#pragma unroll
+        for (int m = 1; m < NB; ++m)
+          if (m < NB - i) {  // entry i + m -= L[i + m][i] x  (zero rows beyond wk)
+            const cplx<T> l = tb[i + m][i];
+            y[m].re -= l.re * x.re - l.im * x.im;
+            y[m].im -= l.re * x.im + l.im * x.re;
+          }
+#pragma unroll
+        for (int m = 0; m + 1 < NB; ++m) y[m] = y[m + 1];
+      }
+    } else if (wv == 1 && c < NB) {
+      cplx<T> y[NB];  // y[m] = entry i - m
+#pragma unroll
+      for (int m = 0; m < NB; ++m) y[m] = cplx<T>{NB - 1 - m == c ? T(1) : T(0), T(0)};
+#pragma unroll
+      for (int i = NB - 1; i >= 0; --i) {
+        cplx<T> x = y[0];
+        if (i < wk) {
+          x = cmul(x, cinv(tb[i][i]));
+#pragma unroll
+          for (int m = 1; m < NB; ++m)
+            if (m <= i) {  // entry i - m -= U[i - m][i] x
+              const cplx<T> u = tb[i - m][i];
+              y[m].re -= u.re * x.re - u.im * x.im;
+              y[m].im -= u.re * x.im + u.im * x.re;
+            }
+        }
+        invU[i * NB + c] = x;
+#pragma unroll
+        for (int m = 0; m + 1 < NB; ++m) y[m] = y[m + 1];
+      }
     }
-    __syncthreads();
   }
-  for (int e = tid; e < NB * NB; e += NODE) invL[e] = sx[e / NB][e % NB];
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
-  __syncthreads();
-  for (int r = wk - 1; r >= 0; --r) {
-    const cplx<T> inv = cinv(tb[r][r]);
-    if (tid >= r && tid < wk) sx[r][tid] = cmul(sx[r][tid], inv);  // row r scaled: X[r][c], c >= r
-    __syncthreads();
-    // rows i < r: X[i][c] -= U[i][r] X[r][c], c >= r
-    const int cols = wk - r;
-    for (int e = tid; e < r * cols; e += NODE) {
-      const int i = e / cols, c = r + e % cols;
-      const cplx<T> u = tb[i][r], x = sx[r][c];
-      sx[i][c].re -= u.re * x.re - u.im * x.im;
-      sx[i][c].im -= u.re * x.im + u.im * x.re;
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < NB * NB; e += NODE) invU[e] = sx[e / NB][e % NB];
   // move list, built by the first wavefront (every thread reaches the barrier)
   __shared__ int vsorted[NB];
   const int lane = tid;  // meaningful for tid < 64 only
@@ -291,10 +306,10 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
 // Leaf nodes (cand_in == nullptr) take NODE consecutive rows; inner nodes take
 // the candidates of up to FANIN children of the previous level.  Candidates
 // of node p are written to cand_out[p*NB .. p*NB + NB) (-1 = none).
-template <typename T>
+template <typename T, bool IS_ROOT>
 __global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __restrict__ A, int64_t lda, int64_t n, int64_t k,
                                                     int w, const int32_t* __restrict__ cand_in, int n_in,
-                                                    int32_t* __restrict__ cand_out, int is_root,
+                                                    int32_t* __restrict__ cand_out,
                                                     int32_t* __restrict__ moves, int32_t* __restrict__ info,
                                                     cplx<T>* __restrict__ top, cplx<T>* __restrict__ invL,
                                                     cplx<T>* __restrict__ invU) {
@@ -340,7 +355,7 @@ __global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __re
   int step;
   const int zc = gepp_node(a, valid, nvalid, w, tid, step, prow, lu, skey);
   const int ncand = min(nvalid, w);
-  if (is_root) {
+  if constexpr (IS_ROOT) {
     if (step >= 0) win[step] = row;
     __syncthreads();
     panel_root(lu, win, ncand, w, zc, k, tid, moves, info, top, invL, invU);
@@ -554,16 +569,20 @@ static void panel(LuRun<T>& R, int64_t k, int w) {
   int32_t* cin = R.cand;
   int32_t* cout = R.cand + R.cand_stride;
   bool root = nodes == 1;
-  hipLaunchKernelGGL(k_tslu_node<T>, dim3(nodes), dim3(NODE), 0, s, R.A, R.lda, R.n, k, w, (const int32_t*)nullptr,
-                     0, cin, (int)root, moves, R.info, R.top, R.dinvL + blk * NB * NB, R.dinvU + blk * NB * NB);
-  FOSB_LAUNCH_CHECK();
+  auto node = [&](int grid, const int32_t* in, int n_in, int32_t* out) {
+    if (root)
+      hipLaunchKernelGGL((k_tslu_node<T, true>), dim3(grid), dim3(NODE), 0, s, R.A, R.lda, R.n, k, w, in, n_in, out,
+                         moves, R.info, R.top, R.dinvL + blk * NB * NB, R.dinvU + blk * NB * NB);
+    else
+      hipLaunchKernelGGL((k_tslu_node<T, false>), dim3(grid), dim3(NODE), 0, s, R.A, R.lda, R.n, k, w, in, n_in, out,
+                         moves, R.info, R.top, R.dinvL + blk * NB * NB, R.dinvU + blk * NB * NB);
+    FOSB_LAUNCH_CHECK();
+  };
+  node(nodes, nullptr, 0, cin);
   while (!root) {
     const int next = (nodes + FANIN - 1) / FANIN;
     root = next == 1;
-    hipLaunchKernelGGL(k_tslu_node<T>, dim3(next), dim3(NODE), 0, s, R.A, R.lda, R.n, k, w, (const int32_t*)cin,
-                       nodes, cout, (int)root, moves, R.info, R.top, R.dinvL + blk * NB * NB,
-                       R.dinvU + blk * NB * NB);
-    FOSB_LAUNCH_CHECK();
+    node(next, cin, nodes, cout);
     std::swap(cin, cout);
     nodes = next;
   }
