@@ -553,6 +553,7 @@ struct LuRun {
 constexpr int kMoveStride = 1 + 4 * NB;
 static_assert(kMoveStride == kMoveStrideDev, "row-move list stride");
 constexpr int64_t kLookaheadMinN = 2048;  // smaller matrices: plain recursion on one stream
+constexpr int64_t kTrailChunk = 4096;      // columns per trailing-update launch (measured: 2048..8192)
 
 static inline int64_t split_half(int64_t w) { return (int64_t)NB * (((w / NB) + 1) / 2); }
 
@@ -664,9 +665,13 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
     panel_block(k1, w1);
     if (k1 + w1 < n) {
       const int64_t kr = k1 + w1;
-      trsm_lower_unit<T>(U, A, lda, R.dinvL, kj, wj, A + kj * lda + kr, lda, n - kr);
-      gemm<T>(U, n - k1, n - kr, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + kr, lda, 1.0, A + k1 * lda + kr,
-              lda);
+      // in column chunks: between two chunk launches the panel stream's small
+      // kernels get workgroup slots instead of queueing behind one huge grid
+      for (int64_t c0 = kr; c0 < n; c0 += kTrailChunk) {
+        const int64_t cn = std::min<int64_t>(kTrailChunk, n - c0);
+        trsm_lower_unit<T>(U, A, lda, R.dinvL, kj, wj, A + kj * lda + c0, lda, cn);
+        gemm<T>(U, n - k1, cn, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + c0, lda, 1.0, A + k1 * lda + c0, lda);
+      }
     }
   }
   FOSB_HIP(hipEventRecord(ev_look, sb));
