@@ -112,6 +112,10 @@ struct Context {
   std::mutex reg_mu;
   // GEMM tile autotuner (kept by the root context): size bucket -> variant
   int autotune = 1;
+  // > 0: GEMMs launched on this context use the tile variant with the smallest
+  // register and LDS footprint instead of the tuned one (set while this
+  // context's kernels share the chip with a saturating GEMM on another stream)
+  int lean_tiles = 0;
   std::map<int64_t, int> tune;
   std::mutex tune_mu;
   DevBuf ss[13];

@@ -216,56 +216,41 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
   if (tid < wk && win[tid] < k + wk) inblk[win[tid] - k] = 1;
   for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
   if (zc >= 0 && tid == 0) atomicMin(info, (int)(k + zc + 1));
-  // Inverses of the diagonal factors (identity beyond wk), one column c per
-  // thread and no barriers: lanes 0..NB-1 of wave 0 solve L X = I forward,
-  // lanes 0..NB-1 of wave 1 solve U X = I backward, reading the factors as LDS
-  // broadcasts.  Right-looking: once entry i of the column is final it is
-  // stored and subtracted from the pending entries, which sit in a register
-  // window that moves by one per step (y[0] is entry i; the loops unroll, so
-  // the moves are register renaming).
-  {
-    const int wv = tid >> 6, c = tid & 63;
-    if (wv == 0 && c < NB) {
-      cplx<T> y[NB];  // y[m] = entry i + m
-#pragma unroll
-      for (int m = 0; m < NB; ++m) y[m] = cplx<T>{m == c ? T(1) : T(0), T(0)};
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const cplx<T> x = y[0];
-        invL[i * NB + c] = x;
-#pragma unroll
-        for (int m = 1; m < NB; ++m)
-          if (m < NB - i) {  // entry i + m -= L[i + m][i] x  (zero rows beyond wk)
-            const cplx<T> l = tb[i + m][i];
-            y[m].re -= l.re * x.re - l.im * x.im;
-            y[m].im -= l.re * x.im + l.im * x.re;
-          }
-#pragma unroll
-        for (int m = 0; m + 1 < NB; ++m) y[m] = y[m + 1];
-      }
-    } else if (wv == 1 && c < NB) {
-      cplx<T> y[NB];  // y[m] = entry i - m
-#pragma unroll
-      for (int m = 0; m < NB; ++m) y[m] = cplx<T>{NB - 1 - m == c ? T(1) : T(0), T(0)};
-#pragma unroll
-      for (int i = NB - 1; i >= 0; --i) {
-        cplx<T> x = y[0];
-        if (i < wk) {
-          x = cmul(x, cinv(tb[i][i]));
-#pragma unroll
-          for (int m = 1; m < NB; ++m)
-            if (m <= i) {  // entry i - m -= U[i - m][i] x
-              const cplx<T> u = tb[i - m][i];
-              y[m].re -= u.re * x.re - u.im * x.im;
-              y[m].im -= u.re * x.im + u.im * x.re;
-            }
-        }
-        invU[i * NB + c] = x;
-#pragma unroll
-        for (int m = 0; m + 1 < NB; ++m) y[m] = y[m + 1];
-      }
+  // inverses of the diagonal factors by Gauss-Jordan sweeps over the whole
+  // workgroup (identity beyond wk):  L X = I forward, U X = I backward
+  __shared__ cplx<T> sx[NB][NB + 1];
+  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  __syncthreads();
+  for (int r = 0; r < wk; ++r) {
+    // rows i > r: X[i][c] -= L[i][r] X[r][c], c <= r
+    const int cols = r + 1, rows = wk - r - 1;
+    for (int e = tid; e < rows * cols; e += NODE) {
+      const int i = r + 1 + e / cols, c = e % cols;
+      const cplx<T> l = tb[i][r], x = sx[r][c];
+      sx[i][c].re -= l.re * x.re - l.im * x.im;
+      sx[i][c].im -= l.re * x.im + l.im * x.re;
     }
+    __syncthreads();
   }
+  for (int e = tid; e < NB * NB; e += NODE) invL[e] = sx[e / NB][e % NB];
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  __syncthreads();
+  for (int r = wk - 1; r >= 0; --r) {
+    const cplx<T> inv = cinv(tb[r][r]);
+    if (tid >= r && tid < wk) sx[r][tid] = cmul(sx[r][tid], inv);  // row r scaled: X[r][c], c >= r
+    __syncthreads();
+    // rows i < r: X[i][c] -= U[i][r] X[r][c], c >= r
+    const int cols = wk - r;
+    for (int e = tid; e < r * cols; e += NODE) {
+      const int i = e / cols, c = r + e % cols;
+      const cplx<T> u = tb[i][r], x = sx[r][c];
+      sx[i][c].re -= u.re * x.re - u.im * x.im;
+      sx[i][c].im -= u.re * x.im + u.im * x.re;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += NODE) invU[e] = sx[e / NB][e % NB];
   // move list, built by the first wavefront (every thread reaches the barrier)
   __shared__ int vsorted[NB];
   const int lane = tid;  // meaningful for tid < 64 only
@@ -635,6 +620,13 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
     FOSB_HIP(hipEventCreateWithFlags(&P.lu_ev[1], hipEventDisableTiming));
   }
   hipEvent_t ev_panel = P.lu_ev[0], ev_look = P.lu_ev[1];
+  // the panel stream's GEMMs run beside the trailing update: small tiles, so a
+  // workgroup fits where one of the update's workgroups has just retired
+  struct Lean {
+    Context& c;
+    explicit Lean(Context& x) : c(x) { ++c.lean_tiles; }
+    ~Lean() { --c.lean_tiles; }
+  } lean(P);
   auto panel_block = [&](int64_t k, int64_t w) {
     R.pc0 = k;
     R.pc1 = k + w;
