@@ -87,6 +87,9 @@ def parse():
                          "step-by-step calls, timed per stage")
     ap.add_argument("--autotune", default="on", choices=["on", "off"],
                     help="GEMM tile autotuner (off: the built-in tile for every product)")
+    ap.add_argument("--tune-load", default=None, metavar="JSON",
+                    help="load a GEMM tile table ({bucket key: variant}, from --tune-dump) before the warmup")
+    ap.add_argument("--tune-dump", default=None, metavar="JSON", help="write the GEMM tile table after the run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -182,6 +185,9 @@ def run_gpu(args, W):
 
     ctx = fosb.Context(0)
     fosb.autotune(ctx, 1 if args.autotune == "on" else 0)
+    if args.tune_load:
+        with open(args.tune_load) as f:
+            fosb.autotune_load(ctx, {int(k): v for k, v in json.load(f).items()})
     cov = fosb.make_cov(W.w.cov_kind, W.w.sigma, W.w.ell)
     opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
     meshes, Z = gpu_setup(fosb, torch, ctx, W)
@@ -239,6 +245,9 @@ def run_gpu(args, W):
             fosb.profile_enable(ctx, False)
             rec["profile"] = prof
         out[pname] = rec
+    if args.tune_dump:
+        with open(args.tune_dump, "w") as f:
+            json.dump({str(k): v for k, v in sorted(fosb.autotune_table(ctx).items())}, f, indent=0)
     return out, (lu_f, solve_f, ff_f, npairs)
 
 

@@ -304,6 +304,19 @@ fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* 
  * shape: the first listed), 1 on, 2 on and forget the table, -1 query only.
  * n_entries (may be NULL) receives the number of tuned buckets. */
 fosb_status fosb_autotune(fosb_context* ctx, int32_t mode, int32_t* n_entries);
+/* Export of the tuned table, in increasing key order: up to capacity entries
+ * into keys / variants (host arrays, may be NULL when capacity is 0);
+ * *n_entries (required) receives the table's size.  A key packs the bucket:
+ * bits 0-12 floor(log2 K), 13-25 floor(log2 N), 26-38 floor(log2 M), bit 39 set
+ * for A^H products, bit 40 set for complex128.  A variant indexes the shape
+ * list above for the key's precision. */
+fosb_status fosb_autotune_table(fosb_context* ctx, int64_t* keys, int32_t* variants, int64_t capacity,
+                                int64_t* n_entries);
+/* Adds n entries (host arrays) to the table, replacing entries with equal
+ * keys, so that a table exported from one run settles the same buckets in
+ * another without timing.  A variant out of range for its key's precision,
+ * or a key with bits above 40 set, gives FOSB_E_INVALID and loads nothing. */
+fosb_status fosb_autotune_load(fosb_context* ctx, const int64_t* keys, const int32_t* variants, int64_t n);
 
 /* ---------------------------------------------------------------- profiling */
 /* Kernel classes timed by the profiler. */

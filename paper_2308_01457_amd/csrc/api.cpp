@@ -993,6 +993,40 @@ fosb_status fosb_autotune(fosb_context* ctx, int32_t mode, int32_t* n_entries) {
   API_END
 }
 
+fosb_status fosb_autotune_table(fosb_context* ctx, int64_t* keys, int32_t* variants, int64_t capacity,
+                                int64_t* n_entries) {
+  API_BEGIN
+  REQUIRE(ctx && n_entries, "ctx/n_entries is NULL");
+  REQUIRE(capacity >= 0, "capacity must be >= 0");
+  REQUIRE(capacity == 0 || (keys && variants), "keys/variants is NULL");
+  std::lock_guard<std::mutex> lock(ctx->tune_mu);
+  int64_t i = 0;
+  for (const auto& kv : ctx->tune) {  // std::map: increasing key order
+    if (i >= capacity) break;
+    keys[i] = kv.first;
+    variants[i] = kv.second;
+    ++i;
+  }
+  *n_entries = (int64_t)ctx->tune.size();
+  API_END
+}
+
+fosb_status fosb_autotune_load(fosb_context* ctx, const int64_t* keys, const int32_t* variants, int64_t n) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  REQUIRE(n >= 0, "n must be >= 0");
+  REQUIRE(n == 0 || (keys && variants), "keys/variants is NULL");
+  for (int64_t i = 0; i < n; ++i) {
+    REQUIRE(keys[i] >= 0 && (keys[i] >> 41) == 0, "entry %lld: key has bits above 40 set", (long long)i);
+    const int nv = tile_variant_count((keys[i] >> 40) & 1);
+    REQUIRE(variants[i] >= 0 && variants[i] < nv, "entry %lld: variant %d out of range 0..%d", (long long)i,
+            (int)variants[i], nv - 1);
+  }
+  std::lock_guard<std::mutex> lock(ctx->tune_mu);
+  for (int64_t i = 0; i < n; ++i) ctx->tune[keys[i]] = variants[i];
+  API_END
+}
+
 fosb_status fosb_profile_enable(fosb_context* ctx, int32_t on) {
   API_BEGIN
   REQUIRE(ctx, "ctx is NULL");

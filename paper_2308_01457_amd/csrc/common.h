@@ -241,6 +241,9 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
 template <typename T>
 void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
           const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc);
+// number of GEMM tile variants (gemm.hip, Tiles<T>::n) for complex64 (fp64 = 0)
+// or complex128 (fp64 = 1)
+inline int tile_variant_count(int fp64) { return fp64 ? 3 : 4; }
 // C = beta*C + alpha*A^H*B; A is stored K x M (row-major, leading dimension lda)
 template <typename T>
 void gemm_ch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,

@@ -92,6 +92,8 @@ _SIGS = {
     "fosb_second_moment_batch": (C.c_int, [_P, C.POINTER(BatchShape), _I64, _I32, _P, _I64, C.POINTER(Opts), _I32,
                                            C.POINTER(Stats)]),
     "fosb_autotune": (C.c_int, [_P, _I32, C.POINTER(_I32)]),
+    "fosb_autotune_table": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), _I64, C.POINTER(_I64)]),
+    "fosb_autotune_load": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), _I64]),
     "fosb_profile_enable": (C.c_int, [_P, _I32]),
     "fosb_profile_read": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
 }
@@ -202,6 +204,24 @@ def autotune(ctx: "Context", mode: int = -1) -> int:
     n = _I32()
     _check(lib().fosb_autotune(ctx.h, mode, C.byref(n)))
     return n.value
+
+
+def autotune_table(ctx: "Context") -> dict:
+    """fosb_autotune_table: the tuned table as {bucket key: tile variant}."""
+    n = _I64()
+    _check(lib().fosb_autotune_table(ctx.h, None, None, 0, C.byref(n)))
+    keys = (_I64 * max(n.value, 1))()
+    var = (_I32 * max(n.value, 1))()
+    _check(lib().fosb_autotune_table(ctx.h, keys, var, n.value, C.byref(n)))
+    return {int(keys[i]): int(var[i]) for i in range(n.value)}
+
+
+def autotune_load(ctx: "Context", table: dict) -> None:
+    """fosb_autotune_load: add {bucket key: tile variant} entries to the table."""
+    items = sorted((int(k), int(v)) for k, v in table.items())
+    keys = (_I64 * max(len(items), 1))(*[k for k, _ in items])
+    var = (_I32 * max(len(items), 1))(*[v for _, v in items])
+    _check(lib().fosb_autotune_load(ctx.h, keys, var, len(items)))
 
 
 def profile_enable(ctx: "Context", on: bool = True) -> None:

@@ -178,3 +178,31 @@ def test_autotune_does_not_change_results(fz, precision):
     assert np.array_equal(v0.cpu().numpy(), v1.cpu().numpy())
     for x, y in zip(b0, b1):
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+def test_autotune_table_export_and_load(fz):
+    """A tuned table exported from one context and loaded into a fresh one
+    settles the same buckets (no timing) and gives identical results; a
+    variant out of range is rejected and loads nothing."""
+    fosb, ctx, torch = fz
+    xh = workloads.angles_xz(31)
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    c1, c2 = fosb.Context(0), fosb.Context(0)
+    fosb.autotune(c1, 2)
+    m1 = [fosb.Mesh(c1, *workloads.icosphere(s)) for s in (1, 2, 3)]
+    v1, _, _ = fosb.second_moment(c1, m1, 1, 3, K1, fosb.MIXED, cov, xh)
+    table = fosb.autotune_table(c1)
+    print(f"[gpu] autotune table: {len(table)} buckets", flush=True)
+    assert len(table) == fosb.autotune(c1, -1) > 0
+    fosb.autotune(c2, 2)
+    fosb.autotune_load(c2, table)
+    assert fosb.autotune_table(c2) == table
+    m2 = [fosb.Mesh(c2, *workloads.icosphere(s)) for s in (1, 2, 3)]
+    v2, _, _ = fosb.second_moment(c2, m2, 1, 3, K1, fosb.MIXED, cov, xh)
+    assert fosb.autotune_table(c2) == table          # every bucket was already settled
+    assert np.array_equal(v1.cpu().numpy(), v2.cpu().numpy())
+    key = next(iter(table))
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.autotune_load(c2, {key + 1: 0, key: 7})
+    assert e.value.name == "E_INVALID"
+    assert fosb.autotune_table(c2) == table
