@@ -29,6 +29,48 @@ struct Rule6 {
 
 static constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
 
+// sin and cos of x for the Green's function phase k |x - y|.  Reduction by
+// pi/2 in the manner of Cody and Waite (1980): n = rint(2x/pi),
+// r = x - n (P1 + P2 + P3) with pi/2 split into three doubles and each product
+// applied by one fused multiply-add; then the Taylor series of sin and cos on
+// |r| <= pi/4 (about), cut where the first omitted term is below 1e-16 (sin:
+// through r^17, cos: through r^16); the quadrant n mod 4 picks and signs the
+// pair.  Accurate to about an ulp for |x| up to kTrigPhaseMax, which
+// assemble_efie enforces (k times the mesh's bounding-box diagonal).
+static constexpr double kTrigPhaseMax = 1.0e5;
+__device__ __forceinline__ void sincos_phase(double x, double* sn, double* cs) {
+  constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+  constexpr double P1 = 0x1.921fb54442d18p+0, P2 = 0x1.1a62633145c07p-54, P3 = -0x1.f1976b7ed8fbcp-110;
+  const double n = rint(x * kTwoOverPi);
+  double r = fma(-n, P1, x);
+  r = fma(-n, P2, r);
+  r = fma(-n, P3, r);
+  const double r2 = r * r;
+  // coefficients (-1)^j / (2j+1)! and (-1)^j / (2j)!
+  double ps = 2.8114572543455206e-15;
+  ps = fma(ps, r2, -7.647163731819816e-13);
+  ps = fma(ps, r2, 1.6059043836821613e-10);
+  ps = fma(ps, r2, -2.505210838544172e-08);
+  ps = fma(ps, r2, 2.7557319223985893e-06);
+  ps = fma(ps, r2, -0.0001984126984126984);
+  ps = fma(ps, r2, 0.008333333333333333);
+  ps = fma(ps, r2, -0.16666666666666666);
+  ps = fma(ps * r2, r, r);
+  double pc = 4.779477332387385e-14;
+  pc = fma(pc, r2, -1.1470745597729725e-11);
+  pc = fma(pc, r2, 2.08767569878681e-09);
+  pc = fma(pc, r2, -2.755731922398589e-07);
+  pc = fma(pc, r2, 2.48015873015873e-05);
+  pc = fma(pc, r2, -0.001388888888888889);
+  pc = fma(pc, r2, 0.041666666666666664);
+  pc = fma(pc, r2, -0.5);
+  pc = fma(pc, r2, 1.0);
+  const int q = (int)n & 3;  // two's complement: n mod 4 also for n < 0
+  const double s0 = (q & 1) ? pc : ps, c0 = (q & 1) ? ps : pc;
+  *sn = (q & 2) ? -s0 : s0;
+  *cs = ((q + 1) & 2) ? -c0 : c0;
+}
+
 __device__ __forceinline__ void write_local_block(const MeshDev& md, int i, int j, int jj, double k,
                                                   const double Li[3][3], const double Lj[3][3], double I0r,
                                                   double I0i, const double Ixr[3], const double Ixi[3],
@@ -121,7 +163,7 @@ __global__ __launch_bounds__(256) void k_assemble_regular(MeshDev md, Rule6 R, d
       const double ir = rsqrt(r2);
       const double r = r2 * ir;
       double sn, cs;
-      sincos(k * r, &sn, &cs);
+      sincos_phase(k * r, &sn, &cs);
       const double g = wq[q] * ir;
       const double gr = cs * g, gi = sn * g;
       Sr += gr;
@@ -288,6 +330,18 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
   hipStream_t s = ctx.stream;
   const MeshHost& h = m.h;
   const int nt = (int)h.nt, ne = (int)h.ne;
+  {  // every phase k |x - y| stays within the range of sincos_phase
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < h.nv; ++v)
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = std::min(lo[q], h.V[3 * v + q]);
+        hi[q] = std::max(hi[q], h.V[3 * v + q]);
+      }
+    const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                  (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    if (!(k * diag <= kTrigPhaseMax))
+      fail(FOSB_E_INVALID, "k * (mesh bounding-box diagonal) = %g exceeds %g", k * diag, kTrigPhaseMax);
+  }
   ensure_ss_table(ctx, n_gauss);
   Rule6 R;
   rule6(R.l, R.w);

@@ -111,3 +111,16 @@ def test_handles_outlive_their_context(fz):
     # the other context is unaffected
     m2 = fosb.Mesh(ctx, *workloads.icosphere(1))
     assert torch.isfinite(fosb.assemble(ctx, m2, 1.0).abs()).all()
+
+
+def test_phase_range_is_enforced(fz):
+    """The assembly's sin/cos is exact to an ulp for phases k |x - y| up to 1e5;
+    k times the mesh's bounding-box diagonal beyond that is rejected."""
+    fosb, ctx, torch = fz
+    m = fosb.Mesh(ctx, *workloads.icosphere(1))      # unit sphere: diagonal 2 sqrt(3) at most
+    print("[gpu] wavenumber beyond the phase range", flush=True)
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.assemble(ctx, m, 1.0e5)
+    assert e.value.name == "E_INVALID"
+    assert "bounding-box" in fosb.lib().fosb_last_error().decode()
+    assert torch.isfinite(fosb.assemble(ctx, m, 1.0e4).abs()).all()
