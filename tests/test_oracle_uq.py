@@ -175,3 +175,22 @@ def test_weighted_adjoint_route(oracle_levels):
     Vm = uq.second_moment(None, 1.0, 0, 2, "gaussian", sig, ell - h, xh, levels=levels)[0]
     fd = np.sum(g * (Vp - Vm)) / (2 * h)
     assert abs(fd - grad[1]) < 1e-6 * abs(grad[1]), (fd, grad[1])
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "matern32"])
+def test_full_tensor_variance_is_nonnegative(oracle_levels, kind):
+    """Single-level (full tensor) variance Re diag(FF Sigma FF^H) is a variance:
+    C = W K W^H is Hermitian PSD for a PSD covariance, so Sigma = Z^-1 C Z^-H is
+    too, and every component at every angle is >= 0 (to rounding).  A missing
+    conjugation or a sign error in W breaks positivity."""
+    xh = workloads.angles_xz(61)
+    for s in (1, 2):
+        lv = oracle_levels(s)
+        C = uq.rhs_correlation(lv, lv, kind, 0.01, 0.5)
+        S = uq.two_sided_solve(lv, lv, C)
+        FF = uq.far_field_matrix(lv, xh)
+        V = uq.pair_variance(FF, S, FF)
+        assert V.min() >= -1e-12 * V.max(), (s, V.min(), V.max())
+        # the off-diagonal far-field correlation is Hermitian in the angle pair
+        Cor = uq.pair_correlation(FF, S, FF)
+        assert np.abs(Cor - np.conj(np.transpose(Cor, (0, 2, 1)))).max() < 1e-10 * np.abs(Cor).max()
