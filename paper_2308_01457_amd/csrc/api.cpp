@@ -78,7 +78,7 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   ctx.scratch[3].reserve(bytes128);
   ctx.scratch[4].reserve((size_t)n * nrhs * sizeof(c64));
   ctx.scratch[5].reserve(bytes128);
-  ctx.norms.reserve(2 * sizeof(double));
+  ctx.norms.reserve((2 + 2 * kNormBlocks) * sizeof(double));
   c128* Bo = ctx.scratch[2].as<c128>();
   c128* X = ctx.scratch[3].as<c128>();
   c64* R32 = ctx.scratch[4].as<c64>();

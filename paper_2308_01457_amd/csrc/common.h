@@ -100,7 +100,7 @@ struct Context {
   DevBuf small;       // small per-panel buffers
   // Sauter-Schwab point tables per Gauss order n (1..12): 5 doubles per point,
   // kinds 0/1/2 concatenated; offsets and counts in points.
-  DevBuf norms;       // 2 doubles for refinement norms
+  DevBuf norms;       // refinement norms: 2 doubles + per-block partials
   DevBuf splitk;      // partial products of split-K GEMMs
   DevBuf tune_out;    // scratch output of autotuning runs
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
@@ -277,7 +277,10 @@ void copy_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t l
 void conj_transpose_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows,
                          int64_t cols, const double* row_scale = nullptr);
 void axpy_c128(hipStream_t s, const c128* x, int64_t ldx, c128* y, int64_t ldy, int64_t rows, int64_t cols);
-// squared Frobenius norms of x and of y (two doubles written to out, device)
+// squared Frobenius norms of x and of y (two doubles written to out, device);
+// out has room for 2 + 2 * kNormBlocks doubles (per-block partial sums follow
+// the two results, reduced in a fixed order)
+constexpr int kNormBlocks = 1024;
 void norms2_c128(hipStream_t s, const c128* x, int64_t ldx, const c128* y, int64_t ldy, int64_t rows,
                  int64_t cols, double* out);
 // uq.hip

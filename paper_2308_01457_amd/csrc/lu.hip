@@ -941,8 +941,12 @@ void axpy_c128(hipStream_t s, const c128* x, int64_t ldx, c128* y, int64_t ldy, 
   FOSB_LAUNCH_CHECK();
 }
 
+// Squared Frobenius norms of x and y.  Each block writes its partial sums to
+// its own slot and one block then adds the slots in a fixed order, so the
+// result does not depend on the order in which blocks finish (the refinement
+// takes its stopping decisions from these norms).
 __global__ __launch_bounds__(256) void k_norms2(const c128* __restrict__ x, int64_t ldx, const c128* __restrict__ y,
-                                                int64_t ldy, int64_t rows, int64_t cols, double* out) {
+                                                int64_t ldy, int64_t rows, int64_t cols, double* __restrict__ part) {
   __shared__ double sx[256], sy[256];
   double ax = 0, ay = 0;
   const int64_t total = rows * cols;
@@ -963,18 +967,43 @@ __global__ __launch_bounds__(256) void k_norms2(const c128* __restrict__ x, int6
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(out, sx[0]);
-    atomicAdd(out + 1, sy[0]);
+    part[2 * blockIdx.x] = sx[0];
+    part[2 * blockIdx.x + 1] = sy[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_norms2_finish(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sx[256], sy[256];
+  double ax = 0, ay = 0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    ax += part[2 * b];
+    ay += part[2 * b + 1];
+  }
+  sx[threadIdx.x] = ax;
+  sy[threadIdx.x] = ay;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sx[threadIdx.x] += sx[threadIdx.x + o];
+      sy[threadIdx.x] += sy[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sx[0];
+    out[1] = sy[0];
   }
 }
 
 void norms2_c128(hipStream_t s, const c128* x, int64_t ldx, const c128* y, int64_t ldy, int64_t rows, int64_t cols,
                  double* out) {
-  FOSB_HIP(hipMemsetAsync(out, 0, 2 * sizeof(double), s));
-  if (rows <= 0 || cols <= 0) return;
-  const int64_t total = rows * cols;
-  const unsigned blocks = (unsigned)std::min<int64_t>(1024, (total + 255) / 256);
-  hipLaunchKernelGGL(k_norms2, dim3(blocks), dim3(256), 0, s, x, ldx, y, ldy, rows, cols, out);
+  const int64_t total = std::max<int64_t>(rows, 0) * std::max<int64_t>(cols, 0);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kNormBlocks, (total + 255) / 256));
+  double* part = out + 2;
+  hipLaunchKernelGGL(k_norms2, dim3((unsigned)blocks), dim3(256), 0, s, x, ldx, y, ldy, std::max<int64_t>(rows, 0),
+                     std::max<int64_t>(cols, 0), part);
+  FOSB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_norms2_finish, dim3(1), dim3(256), 0, s, (const double*)part, blocks, out);
   FOSB_LAUNCH_CHECK();
 }
 
