@@ -519,6 +519,98 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A
   }
 }
 
+// One right-hand side per workgroup, for grids smaller than the chip (e.g. a
+// first moment): the same block steps as k_trsm_leaf, software-pipelined.
+// Each step's loads of the next block's inverse and of the row's next factor
+// segment are issued into registers before the step computes, so that the
+// step's dependent global loads are off the critical chain.
+template <typename T, bool LOWER, bool CONJT>
+__global__ __launch_bounds__(256) void k_trsm_leaf1(const cplx<T>* __restrict__ A, int64_t lda,
+                                                    const cplx<T>* __restrict__ dinv, int64_t k0, int n,
+                                                    cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs) {
+  static_assert(NL == 256, "one row per thread");
+  constexpr int IPT = NB * NB / 256;  // inverse entries staged per thread
+  __shared__ cplx<T> sb[NL];
+  __shared__ cplx<T> si[NB][NB + 1];
+  const int tid = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  sb[tid] = (tid < n && c < nrhs) ? B[(int64_t)tid * ldb + c] : cplx<T>{T(0), T(0)};
+  const int nblk = (n + NB - 1) / NB;
+  cplx<T> invn[IPT], ln[NB];
+  auto fetch = [&](int bi) {  // the inverse and this row's factor segment for step bi
+    const int b = LOWER ? bi : nblk - 1 - bi;
+    const int r0 = b * NB, rn = min(NB, n - r0);
+    const cplx<T>* inv = dinv + (k0 / NB + b) * NB * NB;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const int e = tid + 256 * q;
+      if (CONJT) {
+        const cplx<T> v = inv[(e % NB) * NB + e / NB];
+        invn[q] = cplx<T>{v.re, -v.im};
+      } else {
+        invn[q] = inv[e];
+      }
+    }
+    const int u0 = LOWER ? r0 + rn : 0, u1 = LOWER ? n : r0;
+    if (tid >= u0 && tid < u1) {
+      if (CONJT) {  // column tid of the stored factor
+        const cplx<T>* acol = A + (k0 + r0) * lda + k0 + tid;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          const cplx<T> v = t < rn ? acol[(int64_t)t * lda] : cplx<T>{T(0), T(0)};
+          ln[t] = cplx<T>{v.re, -v.im};
+        }
+      } else {
+        const cplx<T>* arow = A + (k0 + tid) * lda + k0 + r0;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) ln[t] = t < rn ? arow[t] : cplx<T>{T(0), T(0)};
+      }
+    }
+  };
+  fetch(0);
+  for (int bi = 0; bi < nblk; ++bi) {
+    const int b = LOWER ? bi : nblk - 1 - bi;
+    const int r0 = b * NB, rn = min(NB, n - r0);
+    const int u0 = LOWER ? r0 + rn : 0, u1 = LOWER ? n : r0;
+    const bool upd = tid >= u0 && tid < u1;
+    cplx<T> l[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) l[t] = ln[t];
+    // si was last read before the previous step's second barrier
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) si[(tid + 256 * q) / NB][(tid + 256 * q) % NB] = invn[q];
+    if (bi + 1 < nblk) fetch(bi + 1);
+    __syncthreads();
+    T xr = 0, xi = 0;
+    if (tid < rn) {
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        if (t < rn) {
+          const cplx<T> u = si[tid][t], v = sb[r0 + t];
+          xr += u.re * v.re - u.im * v.im;
+          xi += u.re * v.im + u.im * v.re;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < rn) sb[r0 + tid] = cplx<T>{xr, xi};
+    __syncthreads();
+    if (upd) {
+      T ur = 0, ui = 0;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const cplx<T> v = sb[r0 + t];
+        ur += l[t].re * v.re - l[t].im * v.im;
+        ui += l[t].re * v.im + l[t].im * v.re;
+      }
+      sb[tid].re -= ur;
+      sb[tid].im -= ui;
+    }
+  }
+  __syncthreads();
+  if (tid < n && c < nrhs) B[(int64_t)tid * ldb + c] = sb[tid];
+}
+
 // ------------------------------------------------------------------ host drivers
 template <typename T>
 struct LuRun {
@@ -737,6 +829,14 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
 template <typename T, bool LOWER, int CS, bool CONJT>
 static void trsm_leaf_go(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinv, int64_t k0, int64_t n,
                          cplx<T>* B, int64_t ldb, int64_t nrhs) {
+  if constexpr (CS == 1 && sizeof(T) == 4) {
+    if (nrhs < ctx.n_cu) {  // latency-bound: the pipelined one-column form
+      hipLaunchKernelGGL((k_trsm_leaf1<T, LOWER, CONJT>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda,
+                         dinv, k0, (int)n, B, ldb, nrhs);
+      FOSB_LAUNCH_CHECK();
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_trsm_leaf<T, LOWER, CS, CONJT>), dim3((unsigned)((nrhs + CS - 1) / CS)), dim3(256), 0,
                      ctx.stream, A, lda, dinv, k0, (int)n, B, ldb, nrhs);
   FOSB_LAUNCH_CHECK();
