@@ -519,8 +519,9 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A
   }
 }
 
-// One right-hand side per workgroup, for grids smaller than the chip (e.g. a
-// first moment): the same block steps as k_trsm_leaf, software-pipelined.
+// One right-hand side per workgroup (the stripe the launcher picks for narrow
+// solves, e.g. a first moment or a pair with a coarse partner level): the same
+// block steps as k_trsm_leaf, software-pipelined.
 // Each step's loads of the next block's inverse and of the row's next factor
 // segment are issued into registers before the step computes, so that the
 // step's dependent global loads are off the critical chain.
@@ -829,13 +830,11 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
 template <typename T, bool LOWER, int CS, bool CONJT>
 static void trsm_leaf_go(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinv, int64_t k0, int64_t n,
                          cplx<T>* B, int64_t ldb, int64_t nrhs) {
-  if constexpr (CS == 1 && sizeof(T) == 4) {
-    if (nrhs < ctx.n_cu) {  // latency-bound: the pipelined one-column form
-      hipLaunchKernelGGL((k_trsm_leaf1<T, LOWER, CONJT>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda,
-                         dinv, k0, (int)n, B, ldb, nrhs);
-      FOSB_LAUNCH_CHECK();
-      return;
-    }
+  if constexpr (CS == 1 && sizeof(T) == 4) {  // narrow solves: the pipelined one-column form
+    hipLaunchKernelGGL((k_trsm_leaf1<T, LOWER, CONJT>), dim3((unsigned)nrhs), dim3(256), 0, ctx.stream, A, lda, dinv,
+                       k0, (int)n, B, ldb, nrhs);
+    FOSB_LAUNCH_CHECK();
+    return;
   }
   hipLaunchKernelGGL((k_trsm_leaf<T, LOWER, CS, CONJT>), dim3((unsigned)((nrhs + CS - 1) / CS)), dim3(256), 0,
                      ctx.stream, A, lda, dinv, k0, (int)n, B, ldb, nrhs);
