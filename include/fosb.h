@@ -137,7 +137,10 @@ fosb_status fosb_mesh_destroy(fosb_mesh* mesh);
  * triangle pairs and Sauter-Schwab rules (opts->n_gauss_singular points per
  * dimension) on identical, edge- and vertex-adjacent pairs.  FP64 throughout.
  * Z: device, N x N complex128, row stride ldz >= N (N = number of edges).
- * k > 0.  opts may be NULL (defaults). */
+ * k > 0, and k times the diagonal of the mesh's bounding box at most 1e5 (the
+ * range of the kernel's own sin/cos of the phase), else FOSB_E_INVALID.
+ * opts may be NULL (defaults).  The whole-pass entry points assemble through
+ * the same path. */
 fosb_status fosb_assemble(fosb_context* ctx, const fosb_mesh* mesh, double k, const fosb_opts* opts,
                           void* Z, int64_t ldz);
 
