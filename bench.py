@@ -87,6 +87,9 @@ def parse():
                          "step-by-step calls, timed per stage")
     ap.add_argument("--autotune", default="on", choices=["on", "off"],
                     help="GEMM tile autotuner (off: the built-in tile for every product)")
+    ap.add_argument("--profile-mode", default="separate", choices=["separate", "timed"],
+                    help="where the per-launch HIP events for the roofline are recorded: separate (one extra step "
+                         "after the timed ones, same work) or timed (during the timed steps themselves)")
     ap.add_argument("--tune-load", default=None, metavar="JSON",
                     help="load a GEMM tile table ({bucket key: variant}, from --tune-dump) before the warmup")
     ap.add_argument("--tune-dump", default=None, metavar="JSON", help="write the GEMM tile table after the run")
@@ -217,6 +220,9 @@ def run_gpu(args, W):
         times = []
         keep_var = None
         st = None
+        prof_timed = not args.no_profile and args.profile_mode == "timed"
+        if prof_timed:
+            fosb.profile_enable(ctx, True)
         for i in range(args.steps):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if args.schedule == "sequential" else None
             torch.cuda.synchronize()
@@ -237,7 +243,11 @@ def run_gpu(args, W):
             rec["stage_s"] = {"assemble": stage[0], "lu_first_moment": stage[1], "pairs": stage[2],
                               "far_field": stage[3]}
             rec["lu_tflops"] = lu_f / stage[1] / 1e12
-        if not args.no_profile:
+        if prof_timed:
+            rec["profile"] = {k: (v[0] // max(1, args.steps), v[1] / max(1, args.steps), v[2] / max(1, args.steps),
+                                  v[3] / max(1, args.steps)) for k, v in fosb.profile_read(ctx).items()}
+            fosb.profile_enable(ctx, False)
+        elif not args.no_profile:
             log(f"[bench] {pname}: profiled step")
             fosb.profile_enable(ctx, True)
             step(prec)
@@ -440,7 +450,8 @@ def main():
         "dtype": "c64+f64" if head == "mixed" else "c128",
         "data": "synthetic",
         "config": {"workload": W.describe(npairs),
-                   "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol, "autotune": args.autotune},
+                   "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol, "autotune": args.autotune,
+                   "profile_mode": args.profile_mode},
         "algorithmic_flop_per_step": {"lu": lu_f, "pair_solves": solve_f, "far_field": ff_f},
     }
     for pname, rec in gpu.items():
