@@ -3,17 +3,16 @@
 // LU (P Z = L U, L unit lower, row-major storage): recursive column splitting
 // (left half, TRSM of the right half's top rows, GEMM update of the rest,
 // right half) down to 32-column panels.  A panel is factorised with
-// tournament pivoting: each 64-row block of the panel runs Gaussian
-// elimination with partial pivoting in LDS and nominates 32 candidate rows,
-// and the candidates are merged pairwise up a binary tree (the second
-// workgroup to reach a tree node merges; a device-scope acquire/release
-// counter per node orders the hand-over) until 32 pivot rows remain.  The
-// pivot rows are swapped into place across the full matrix width, the panel
-// below the diagonal block becomes A21 U11^{-1}, and the inverses of the
-// 32x32 diagonal blocks of L and U are kept for the triangular solves.
+// tournament pivoting: each 256-row leaf of the panel runs Gaussian
+// elimination with partial pivoting in registers and nominates 32 candidate
+// rows; one launch per tree level then merges the candidates of up to eight
+// children per node the same way, until a single root node chooses the 32
+// pivot rows.  The pivot rows are moved into place across the panel's columns,
+// the panel below the diagonal block becomes A21 U11^{-1}, and the inverses
+// of the 32x32 diagonal blocks of L and U are kept for the triangular solves.
 //
 // Triangular solves are recursive as well: halves are coupled by a GEMM and
-// the 32-row leaves multiply by the stored diagonal-block inverse.
+// the 256-row leaves solve with the stored 32x32 diagonal-block inverses.
 #include <algorithm>
 #include <cmath>
 
@@ -22,8 +21,6 @@
 namespace fosb {
 
 constexpr int NB = kPanel;   // panel width (32)
-constexpr int RB = 64;       // rows per tournament leaf block
-constexpr int SLD = NB + 1;  // LDS row pitch of a panel block
 
 template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
@@ -48,55 +45,36 @@ __device__ __forceinline__ T cabs1(cplx<T> a) {
 // entries in registers.  Gaussian elimination with partial pivoting on the
 // node picks, at step j, the largest |re|+|im| in column j among the rows not
 // chosen yet, broadcasts that row through LDS and eliminates column j from the
-// remaining rows.  The pivot search reduces one 64-bit key per row,
-// (float(|re|+|im|) bits << 32) | ~row, so the maximum key is the largest
-// modulus with ties going to the lowest row; a wave butterfly is followed by a
-// maximum over the four waves' keys in LDS.  Broadcast slots are double
-// buffered, so a step needs two barriers.  The step loop is unrolled, which
-// keeps every register index constant; the row chosen at step j then holds
-// row j of the node's L\U factors and writes it to lu[j][*] (LDS).
+// remaining rows; ties go to the lowest thread.  The step loop is unrolled,
+// which keeps every register index constant; the row chosen at step j then
+// holds row j of the node's L\U factors and writes it to lu[j][*] (LDS).
 // Rows per tree node = threads per workgroup (one row per thread); a node
 // merges NODE / NB children.  Wider nodes (512, 1024 rows: fewer tree levels)
 // measured slower: the per-column barrier and key reduction grow with the
 // number of waves.
 template <typename T> struct Node { static constexpr int size = 256; };
 
-// Maximum of a 64-bit key over the wavefront, returned to every lane: DPP
+// Largest 32-bit value over the wavefront, returned to every lane: DPP
 // exchanges within each row of 16 lanes (xor 1, xor 2, half-row mirror, row
 // mirror), then the four row maxima through readlane.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
-  int hi = (int)(k >> 32), lo = (int)(unsigned)(k & 0xffffffffull);
-#define FOSB_DPP_MAX(ctrl)                                                               \
-  {                                                                                      \
-    const int ohi = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xf, 0xf, false);         \
-    const int olo = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xf, 0xf, false);         \
-    const unsigned long long o = ((unsigned long long)(unsigned)ohi << 32) | (unsigned)olo; \
-    const unsigned long long c = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;   \
-    if (o > c) {                                                                         \
-      hi = ohi;                                                                          \
-      lo = olo;                                                                          \
-    }                                                                                    \
-  }
-  FOSB_DPP_MAX(0xB1)   // quad_perm [1,0,3,2]
-  FOSB_DPP_MAX(0x4E)   // quad_perm [2,3,0,1]
-  FOSB_DPP_MAX(0x141)  // row_half_mirror
-  FOSB_DPP_MAX(0x140)  // row_mirror
-#undef FOSB_DPP_MAX
-  unsigned long long m = 0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const unsigned h = (unsigned)__builtin_amdgcn_readlane(hi, 16 * r);
-    const unsigned l = (unsigned)__builtin_amdgcn_readlane(lo, 16 * r);
-    const unsigned long long x = ((unsigned long long)h << 32) | l;
-    m = x > m ? x : m;
-  }
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));  // row_mirror
+  unsigned m = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  m = max(m, (unsigned)__builtin_amdgcn_readlane((int)v, 16));
+  m = max(m, (unsigned)__builtin_amdgcn_readlane((int)v, 32));
+  m = max(m, (unsigned)__builtin_amdgcn_readlane((int)v, 48));
   return m;
 }
 
+// Pivot-search key of a candidate: the bits of float(|re| + |im|) plus one.
+// Non-negative floats order like their bit patterns, so keys order like the
+// moduli; 0 is left for rows that are not candidates.
 template <typename T>
-__device__ __forceinline__ unsigned long long pivot_key(cplx<T> v, int row) {
-  const float m = (float)cabs1(v);
-  return ((unsigned long long)__float_as_uint(m) << 32) | (unsigned long long)(~(unsigned)row);
+__device__ __forceinline__ unsigned pivot_key(cplx<T> v) {
+  return (__float_as_uint((float)cabs1(v)) & 0x7fffffffu) + 1u;
 }
 
 // 1/a for the panel's multipliers: FP32 through the hardware reciprocal with
@@ -119,15 +97,19 @@ __device__ __forceinline__ cplx<double> cinv_panel(cplx<double> a) { return cinv
 // Partial-pivoting elimination of the node's rows (one row per thread, the
 // row's NB columns in registers).  The step loop is unrolled, so column j is
 // addressed statically and every row stays in place: a row chosen at step j
-// then holds L[j][0..j) (its multipliers) followed by U[j][j..].  Per step,
-// each wave's best candidate publishes its key and its row; one barrier, then
-// every thread picks the largest key and reads that row.  Slots alternate
-// between two buffers, so a wave entering step j+1 never overwrites a slot
-// that another wave still reads at step j.
+// then holds L[j][0..j) (its multipliers) followed by U[j][j..].  Per step:
+// * every candidate forms its key and, speculatively, the reciprocal of its
+//   entry in column j (off the critical path: it overlaps the reduction);
+// * a wave maximum of the keys, and a ballot for the lowest lane holding it;
+// * that lane publishes the key, its row and its reciprocal; one barrier;
+// * every thread takes the largest of the wave keys (ties to the lowest
+//   wave), reads that wave's row and reciprocal, and eliminates column j.
+// Slots alternate between two buffers, so a wave entering step j+1 never
+// overwrites a slot that another wave still reads at step j.
 template <typename T, int NW>
 __device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvalid, int w, int tid, int& step,
-                                         cplx<T> (*prow)[NW][NB], cplx<T> (*lu)[NB + 1],
-                                         unsigned long long (*skey)[NW]) {
+                                         cplx<T> (*prow)[NW][NB], cplx<T> (*pinv)[NW], cplx<T> (*lu)[NB + 1],
+                                         unsigned (*skey)[NW]) {
   int zero_col = -1;
   const int steps = min(nvalid, w);
   const int lane = tid & 63, wave = tid >> 6;
@@ -136,36 +118,43 @@ __device__ __forceinline__ int gepp_node(cplx<T> (&a)[NB], bool valid, int nvali
   for (int j = 0; j < NB; ++j) {
     if (j < steps) {  // uniform over the workgroup
       const int b = j & 1;
-      const unsigned long long mine = (valid && step < 0) ? pivot_key(a[j], tid) : 0ull;
-      const unsigned long long wmax = wave_max_u64(mine);
-      if (mine != 0ull && mine == wmax) {  // keys are unique: one publisher per wave
+      const bool cand = valid && step < 0;
+      const unsigned mine = cand ? pivot_key(a[j]) : 0u;
+      const cplx<T> rinv = cinv_panel(a[j]);
+      const unsigned wmax = wave_max_u32(mine);
+      const unsigned long long hit = __ballot(mine != 0u && mine == wmax);
+      const int wl = hit ? __ffsll((unsigned long long)hit) - 1 : -1;  // this wave's nominee
+      if (lane == wl) {
         skey[b][wave] = wmax;
+        pinv[b][wave] = rinv;
 #pragma unroll
-        for (int c = j; c < NB; ++c) prow[b][wave][c] = a[c];
-      } else if (wmax == 0ull && lane == 0) {
-        skey[b][wave] = 0ull;
+        for (int c = j & ~1; c < NB; ++c) prow[b][wave][c] = a[c];  // from an even column: 16-byte stores
+      } else if (wl < 0 && lane == 0) {
+        skey[b][wave] = 0u;
       }
       __syncthreads();
-      unsigned long long key = 0ull;
+      unsigned key = 0u;
       int q = 0;
 #pragma unroll
       for (int v = 0; v < NW; ++v) {
-        const unsigned long long o = skey[b][v];
+        const unsigned o = skey[b][v];
         if (o > key) {
           key = o;
           q = v;
         }
       }
-      if (mine != 0ull && mine == key) step = j;
+      if (wave == q && lane == wl) step = j;
       const cplx<T> piv = prow[b][q][j];
+      const cplx<T> pr = pinv[b][q];
       if (piv.re == T(0) && piv.im == T(0) && zero_col < 0) zero_col = j;
-      if (valid && step < 0) {
-        const cplx<T> l = cmul(a[j], cinv_panel(piv));
+      if (cand && step < 0) {
+        const cplx<T> l = cmul(a[j], pr);
+        const T nlr = -l.re, nli = -l.im;
 #pragma unroll
         for (int c = j + 1; c < NB; ++c) {
           const cplx<T> u = prow[b][q][c];
-          a[c].re -= l.re * u.re - l.im * u.im;
-          a[c].im -= l.re * u.im + l.im * u.re;
+          a[c].re = fma(nlr, u.re, fma(l.im, u.im, a[c].re));  // a - (l.re u.re - l.im u.im)
+          a[c].im = fma(nlr, u.im, fma(nli, u.re, a[c].im));   // a - (l.re u.im + l.im u.re)
         }
         a[j] = l;
       }
@@ -194,8 +183,7 @@ __device__ __forceinline__ void load_row(const cplx<T>* A, int64_t lda, int64_t 
 
 // Root of the tournament: lu[][] holds L11 \ U11 of the chosen rows (in pivot
 // order) and win[] their row indices.  Writes the top block, the inverses of
-// both diagonal factors (one column per thread, in registers), the row moves
-// and the first zero pivot.  Row moves: pivot r goes to position k + r; the
+// both diagonal factors, the row moves and the first zero pivot.  Row moves: pivot r goes to position k + r; the
 // rows that held positions k..k+wk-1 and are not pivots go, in increasing row
 // order, to the positions the pivots below the block vacate (in increasing
 // order).
@@ -206,7 +194,6 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
                                            cplx<T>* __restrict__ invU) {
   constexpr int NODE = Node<T>::size;
   __shared__ int inblk[NB];   // 1 if row k + r is itself a pivot
-  __shared__ int s_cnt[2];
   for (int e = tid; e < NB * NB; e += NODE) {
     const int r = e / NB, c = e % NB;
     if (r >= wk || c >= w) tb[r][c] = cplx<T>{T(0), T(0)};
@@ -216,8 +203,12 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
   if (tid < wk && win[tid] < k + wk) inblk[win[tid] - k] = 1;
   for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
   if (zc >= 0 && tid == 0) atomicMin(info, (int)(k + zc + 1));
-  // inverses of the diagonal factors by Gauss-Jordan sweeps over the whole
-  // workgroup (identity beyond wk):  L X = I forward, U X = I backward
+  // Inverses of the diagonal factors (identity beyond wk) by Gauss-Jordan
+  // sweeps over the whole workgroup, one barrier per step: L X = I forward,
+  // then U Y = I backward.  At backward step r every thread forms row r's
+  // scaled entries Y[r][c] / U[r][r] (r <= c < wk) itself; the threads on row
+  // r store them to invU (they are final), the others eliminate column r from
+  // rows i < r with them.  Row r of Y is not read again after step r.
   __shared__ cplx<T> sx[NB][NB + 1];
   for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
   __syncthreads();
@@ -232,25 +223,32 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
     }
     __syncthreads();
   }
-  for (int e = tid; e < NB * NB; e += NODE) invL[e] = sx[e / NB][e % NB];
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  for (int e = tid; e < NB * NB; e += NODE) {  // each thread reads, then resets, its own entries
+    invL[e] = sx[e / NB][e % NB];
+    sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  }
   __syncthreads();
   for (int r = wk - 1; r >= 0; --r) {
-    const cplx<T> inv = cinv(tb[r][r]);
-    if (tid >= r && tid < wk) sx[r][tid] = cmul(sx[r][tid], inv);  // row r scaled: X[r][c], c >= r
-    __syncthreads();
-    // rows i < r: X[i][c] -= U[i][r] X[r][c], c >= r
+    // rows i < r: Y[i][c] -= U[i][r] (Y[r][c] / U[r][r]), c >= r
     const int cols = wk - r;
-    for (int e = tid; e < r * cols; e += NODE) {
+    const cplx<T> inv = cinv(tb[r][r]);
+    for (int e = tid; e < (r + 1) * cols; e += NODE) {
       const int i = e / cols, c = r + e % cols;
-      const cplx<T> u = tb[i][r], x = sx[r][c];
-      sx[i][c].re -= u.re * x.re - u.im * x.im;
-      sx[i][c].im -= u.re * x.im + u.im * x.re;
+      const cplx<T> x = cmul(sx[r][c], inv);
+      if (i == r) {
+        invU[r * NB + c] = x;
+      } else {
+        const cplx<T> u = tb[i][r];
+        sx[i][c].re -= u.re * x.re - u.im * x.im;
+        sx[i][c].im -= u.re * x.im + u.im * x.re;
+      }
     }
     __syncthreads();
   }
-  for (int e = tid; e < NB * NB; e += NODE) invU[e] = sx[e / NB][e % NB];
+  for (int e = tid; e < NB * NB; e += NODE) {
+    const int r = e / NB, c = e % NB;
+    if (r >= wk || c < r || c >= wk) invU[e] = cplx<T>{(r == c) ? T(1) : T(0), T(0)};  // the rest stored above
+  }
   // move list, built by the first wavefront (every thread reaches the barrier)
   __shared__ int vsorted[NB];
   const int lane = tid;  // meaningful for tid < 64 only
@@ -299,11 +297,12 @@ __global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __re
                                                     cplx<T>* __restrict__ top, cplx<T>* __restrict__ invL,
                                                     cplx<T>* __restrict__ invU) {
   constexpr int NODE = Node<T>::size, NWAVE = NODE / 64, FANIN = NODE / NB;
-  __shared__ cplx<T> prow[2][NWAVE][NB];
+  __shared__ __align__(16) cplx<T> prow[2][NWAVE][NB];
   __shared__ cplx<T> lu[NB][NB + 1];
   __shared__ int sidx[NODE];
   __shared__ int win[NB];
-  __shared__ unsigned long long skey[2][NWAVE];
+  __shared__ cplx<T> pinv[2][NWAVE];
+  __shared__ unsigned skey[2][NWAVE];
   __shared__ int scnt[NWAVE];
   __shared__ int s_cnt;
   const int tid = threadIdx.x;
@@ -338,7 +337,7 @@ __global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __re
   cplx<T> a[NB];
   load_row(A, lda, k, w, row, a);
   int step;
-  const int zc = gepp_node(a, valid, nvalid, w, tid, step, prow, lu, skey);
+  const int zc = gepp_node(a, valid, nvalid, w, tid, step, prow, pinv, lu, skey);
   const int ncand = min(nvalid, w);
   if constexpr (IS_ROOT) {
     if (step >= 0) win[step] = row;
