@@ -54,6 +54,12 @@ __device__ __forceinline__ T cabs1(cplx<T> a) {
 // number of waves.
 template <typename T> struct Node { static constexpr int size = 256; };
 
+// The panel chain (tournament nodes, row moves, panel finish) and the
+// triangular-solve leaves are latency-bound kernels that share compute units
+// with the trailing update's GEMM waves.  They raise their waves' issue
+// priority, so each SIMD issues their instructions ahead of the GEMM's.
+__device__ __forceinline__ void raise_wave_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Largest 32-bit value over the wavefront, returned to every lane: DPP
 // exchanges within each row of 16 lanes (xor 1, xor 2, half-row mirror, row
 // mirror), then the four row maxima through readlane.
@@ -307,6 +313,7 @@ __global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __re
   __shared__ int s_cnt;
   const int tid = threadIdx.x;
   const int p = blockIdx.x;
+  raise_wave_priority();
   int nvalid = 0;
   if (cand_in == nullptr) {
     nvalid = (int)min<int64_t>(NODE, n - k - (int64_t)p * NODE);
@@ -361,6 +368,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_permute_rows(cplx<T>* __restrict__ A, int64_t lda, ColRanges cr,
                                                       const int32_t* __restrict__ plist, int npl) {
   __shared__ cplx<T> buf[2 * NB][64];
+  raise_wave_priority();
   const int64_t w0 = cr.c1[0] - cr.c0[0];
   const int64_t x = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int64_t c = x < w0 ? cr.c0[0] + x : cr.c0[1] + (x - w0);
@@ -385,6 +393,7 @@ __global__ __launch_bounds__(256) void k_panel_finish(cplx<T>* __restrict__ A, i
                                                       int w, const cplx<T>* __restrict__ top,
                                                       const cplx<T>* __restrict__ invU) {
   __shared__ cplx<T> su[NB][NB + 1];
+  raise_wave_priority();
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) su[e / NB][e % NB] = invU[e];
   const int64_t r = k + (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2);
   const int q = threadIdx.x & 3;
@@ -433,6 +442,7 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A
                                                    const cplx<T>* __restrict__ dinv, int64_t k0, int n,
                                                    cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs) {
   constexpr int XPT = (NB * CS + 255) / 256;
+  raise_wave_priority();
   __shared__ cplx<T> sb[NL][CS + 1];
   __shared__ cplx<T> si[NB][NB + 1];
   const int tid = threadIdx.x;
@@ -530,6 +540,7 @@ __global__ __launch_bounds__(256) void k_trsm_leaf1(const cplx<T>* __restrict__ 
                                                     cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs) {
   static_assert(NL == 256, "one row per thread");
   constexpr int IPT = NB * NB / 256;  // inverse entries staged per thread
+  raise_wave_priority();
   __shared__ cplx<T> sb[NL];
   __shared__ cplx<T> si[NB][NB + 1];
   const int tid = threadIdx.x;
