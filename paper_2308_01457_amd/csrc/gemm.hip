@@ -107,8 +107,28 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   const int64_t kb = (int64_t)blockIdx.z * kc;
   const int64_t ke = min(K, kb + kc);
   cplx<T> ra[AE], rb[BE];
+  const bool interior = m0 + BM <= M && n0 + BN <= N;  // no tile edge in M or N
   auto load_tiles = [&](int64_t k0) {
     const int64_t gr = m0 + a_row;
+    // FP32: the whole slice inside the operands loads without edge checks.  (For
+    // FP64 the separate path made the compiler wait for A's loads before
+    // issuing B's, and was slower.)
+    if (sizeof(T) == 4 && interior && k0 + BK <= ke) {
+#pragma unroll
+      for (int e = 0; e < AE; ++e) {
+        const int64_t gk = k0 + a_k + e;
+        if (CONJ_A) {
+          const cplx<T> v = A[gk * lda + gr];
+          ra[e] = cplx<T>{v.re, -v.im};
+        } else {
+          ra[e] = A[gr * lda + gk];
+        }
+      }
+      const cplx<T>* brow = B + (k0 + b_k) * ldb + n0 + b_col;
+#pragma unroll
+      for (int e = 0; e < BE; ++e) rb[e] = brow[e];
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < AE; ++e) {
       const int64_t gk = k0 + a_k + e;
