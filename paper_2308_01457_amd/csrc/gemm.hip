@@ -110,10 +110,13 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   const bool interior = m0 + BM <= M && n0 + BN <= N;  // no tile edge in M or N
   auto load_tiles = [&](int64_t k0) {
     const int64_t gr = m0 + a_row;
-    // FP32: the whole slice inside the operands loads without edge checks.  (For
-    // FP64 the separate path made the compiler wait for A's loads before
-    // issuing B's, and was slower.)
-    if (sizeof(T) == 4 && interior && k0 + BK <= ke) {
+    if (interior && k0 + BK <= ke) {  // the whole slice is inside the operands: no edge checks
+      // B's loads first: issued last, they would equal the checked path's
+      // closing loads, and the compiler would merge the two tails and wait for
+      // A's loads before issuing them.
+      const cplx<T>* brow = B + (k0 + b_k) * ldb + n0 + b_col;
+#pragma unroll
+      for (int e = 0; e < BE; ++e) rb[e] = brow[e];
 #pragma unroll
       for (int e = 0; e < AE; ++e) {
         const int64_t gk = k0 + a_k + e;
@@ -124,9 +127,6 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
           ra[e] = A[gr * lda + gk];
         }
       }
-      const cplx<T>* brow = B + (k0 + b_k) * ldb + n0 + b_col;
-#pragma unroll
-      for (int e = 0; e < BE; ++e) rb[e] = brow[e];
       return;
     }
 #pragma unroll
