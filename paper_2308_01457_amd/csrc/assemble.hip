@@ -345,8 +345,10 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
   ensure_ss_table(ctx, n_gauss);
   Rule6 R;
   rule6(R.l, R.w);
-  // band width: scratch Zc of 3nt x 3jc complex128 limited to ~512 MB
-  const int64_t budget = (int64_t)512 << 20;
+  // band width: scratch Zc of 3nt x 3jc complex128 limited to ~1 GiB (wider
+  // bands mean fewer launches with longer gathers; at nt = 20480 a 1 GiB band
+  // assembled faster than 256 and 512 MiB ones, and about as fast as 2 GiB)
+  const int64_t budget = (int64_t)1024 << 20;
   int jc = (int)std::max<int64_t>(1, std::min<int64_t>(nt, budget / (9LL * nt * (int64_t)sizeof(c128))));
   if (jc < nt) jc = std::max(64, jc / 64 * 64);
   jc = std::min(jc, nt);
