@@ -302,8 +302,10 @@ fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* 
  * (the default) the first product of each size bucket (precision, operand
  * form, floor(log2) of M, N, K) times every shape on its real operands into
  * scratch output and keeps the fastest for the bucket; the table belongs to
- * the context and its auxiliary and worker streams.  All shapes give
- * identical results, so tuning never changes outputs.  mode: 0 off (built-in
+ * the context and its auxiliary and worker streams.  The trailing update of
+ * the blocked LU takes the 64x64 shape for its large complex64 products
+ * without tuning.  All shapes give identical results, so tuning never changes
+ * outputs.  mode: 0 off (built-in
  * shape: the first listed), 1 on, 2 on and forget the table, -1 query only.
  * n_entries (may be NULL) receives the number of tuned buckets. */
 fosb_status fosb_autotune(fosb_context* ctx, int32_t mode, int32_t* n_entries);

@@ -116,6 +116,9 @@ struct Context {
   // register and LDS footprint instead of the tuned one (set while this
   // context's kernels share the chip with a saturating GEMM on another stream)
   int lean_tiles = 0;
+  // > 0: this context runs the trailing update of a blocked LU; its large
+  // complex64 GEMMs take the 64 x 64 tile instead of the tuned one
+  int trailing_update = 0;
   std::map<int64_t, int> tune;
   std::mutex tune_mu;
   DevBuf ss[13];

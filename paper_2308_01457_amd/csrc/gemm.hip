@@ -468,8 +468,15 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
     ctx.splitk.reserve((size_t)nz * M * N * sizeof(cplx<T>));
     P = static_cast<cplx<T>*>(ctx.splitk.p);
   }
+  // The trailing update's large complex64 products (at least four 128 x 64
+  // tiles per CU) take the 64 x 64 tile.  Timed beside the panel stream, the
+  // tuner often prefers the 64 x 32 tile for them, whose five workgroups per
+  // CU leave the panel stream's kernels no room: the step is then ~4% slower.
+  const bool update_big =
+      sizeof(T) == 4 && ctx.trailing_update > 0 && ((M + 127) / 128) * ((N + 63) / 64) >= 4LL * ctx.n_cu;
   const int var = (nz != 1 || Kp <= 0) ? 0
                   : ctx.lean_tiles > 0 ? Tiles<T>::lean
+                  : update_big         ? 0
                                        : pick_variant<T, CONJ_A>(ctx, M, N, Kp, A, lda, B, ldb);
   {
     ProfScope prof(ctx, sizeof(T) == 8 ? FOSB_K_GEMM_F64 : FOSB_K_GEMM_F32, flops, bytes);

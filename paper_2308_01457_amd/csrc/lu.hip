@@ -730,6 +730,11 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
     explicit Lean(Context& x) : c(x) { ++c.lean_tiles; }
     ~Lean() { --c.lean_tiles; }
   } lean(P);
+  struct Update {
+    Context& c;
+    explicit Update(Context& x) : c(x) { ++c.trailing_update; }
+    ~Update() { --c.trailing_update; }
+  } update(U);
   auto panel_block = [&](int64_t k, int64_t w) {
     R.pc0 = k;
     R.pc1 = k + w;
