@@ -83,6 +83,8 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   c128* X = ctx.scratch[3].as<c128>();
   c64* R32 = ctx.scratch[4].as<c64>();
   c128* Rw = ctx.scratch[5].as<c128>();
+  ctx.solve_tmp.reserve((size_t)kInvBlock * nrhs * sizeof(c64));
+  c64* tmp = ctx.solve_tmp.as<c64>();
   const c64* A32 = static_cast<const c64*>(L.Zlow);
   const c128* Z64 = static_cast<const c128*>(L.Z);
   copy_c128(s, B, ldb, Bo, nrhs, n, nrhs);
@@ -99,8 +101,8 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     if (!adjoint) {
       permute_rows_gather(s, perm, R, nrhs, T, nrhs, n, nrhs);
       copy_c128_to_c64(s, T, nrhs, R32, nrhs, n, nrhs);
-      trsm_lower_unit<float>(ctx, A32, L.ldzlow, L.dinv_L.as<c64>(), 0, n, R32, nrhs, nrhs);
-      trsm_upper<float>(ctx, A32, L.ldzlow, L.dinv_U.as<c64>(), 0, n, R32, nrhs, nrhs);
+      trsm_lower_unit_inv<float>(ctx, A32, L.ldzlow, L.inv_L.as<c64>(), n, R32, nrhs, nrhs, tmp);
+      trsm_upper_inv<float>(ctx, A32, L.ldzlow, L.inv_U.as<c64>(), n, R32, nrhs, nrhs, tmp);
       copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
       D = T;
     } else {
@@ -266,6 +268,13 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(), L->perm);
   }
   if (info != 0) fail(FOSB_E_SINGULAR, "exactly zero pivot at index %lld", (long long)(info - 1));
+  if (precision == FOSB_PREC_MIXED) {  // the refined solves apply the factors through their block inverses
+    const size_t bytes = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(c64);
+    L->inv_L.alloc(bytes);
+    L->inv_U.alloc(bytes);
+    diag_block_inverses<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
+                               L->inv_L.as<c64>(), L->inv_U.as<c64>());
+  }
   upload(L->d_perm, L->perm, s);
   // quadrature nodes, first moments and RHS weights
   L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));

@@ -96,6 +96,7 @@ struct Context {
   size_t max_lds = 65536;
   // reusable scratch (grow-only); each user documents which slot it uses
   DevBuf scratch[6];
+  DevBuf solve_tmp;   // kInvBlock x nrhs leaf products of the block-inverse solves
   DevBuf counters;    // int32 tree counters for panel factorisation
   DevBuf small;       // small per-panel buffers
   // Sauter-Schwab point tables per Gauss order n (1..12): 5 doubles per point,
@@ -229,6 +230,7 @@ struct Level {
   std::vector<int32_t> perm;   // host: row permutation (position i holds original row perm[i])
   DevBuf d_perm;               // int32 [n]
   DevBuf dinv_L, dinv_U;       // inverted nb x nb diagonal blocks of L and U (LU precision)
+  DevBuf inv_L, inv_U;         // MIXED: inverted kInvBlock x kInvBlock diagonal blocks of L and U (complex64)
   DevBuf u;                    // c128 [n_dirs][n]
   DevBuf W;                    // c128 [n_dirs][nt][3][6] RHS weights
   DevBuf qx;                   // double [3][6*nt] quadrature nodes (component-major)
@@ -268,6 +270,21 @@ void trsm_upper_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* d
 template <typename T>
 void trsm_lower_unit_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0, int64_t n,
                         cplx<T>* B, int64_t ldb, int64_t nrhs);
+// Inverses of the kInvBlock x kInvBlock diagonal blocks of the unit lower and
+// upper factors (block b at inv + b kInvBlock^2, row-major, row stride
+// kInvBlock; the last block's slot is the identity outside its corner), and
+// triangular solves of a whole factor that apply them at the leaves
+// (tmp: kInvBlock x nrhs scratch).  Complex64 factors only.
+constexpr int kInvBlock = 256;
+template <typename T>
+void diag_block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinvL,
+                         const cplx<T>* dinvU, cplx<T>* invL, cplx<T>* invU);
+template <typename T>
+void trsm_lower_unit_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invL, int64_t n, cplx<T>* B,
+                         int64_t ldb, int64_t nrhs, cplx<T>* tmp);
+template <typename T>
+void trsm_upper_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invU, int64_t n, cplx<T>* B,
+                    int64_t ldb, int64_t nrhs, cplx<T>* tmp);
 void permute_rows_gather(hipStream_t s, const int32_t* perm, const c128* src, int64_t lds, c128* dst,
                          int64_t ldd, int64_t n, int64_t ncols);
 // dst[perm[i]] = src[i]

@@ -438,15 +438,14 @@ template <typename T> struct LeafCS { static constexpr int v = 16; };
 template <> struct LeafCS<double> { static constexpr int v = 8; };
 
 template <typename T, bool LOWER, int CS, bool CONJT>
-__global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A, int64_t lda,
-                                                   const cplx<T>* __restrict__ dinv, int64_t k0, int n,
-                                                   cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs) {
+__device__ __forceinline__ void trsm_leaf_body(const cplx<T>* __restrict__ A, int64_t lda,
+                                               const cplx<T>* __restrict__ dinv, int64_t k0, int n,
+                                               cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs, int64_t c0) {
   constexpr int XPT = (NB * CS + 255) / 256;
   raise_wave_priority();
   __shared__ cplx<T> sb[NL][CS + 1];
   __shared__ cplx<T> si[NB][NB + 1];
   const int tid = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * CS;
   for (int e = tid; e < NL * CS; e += 256) {  // rows >= n are zero (they meet zero factor entries)
     const int r = e / CS, c = e % CS;
     sb[r][c] = (r < n && c0 + c < nrhs) ? B[(int64_t)r * ldb + c0 + c] : cplx<T>{T(0), T(0)};
@@ -526,6 +525,36 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A
     const int r = e / CS, c = e % CS;
     if (c0 + c < nrhs) B[(int64_t)r * ldb + c0 + c] = sb[r][c];
   }
+}
+
+template <typename T, bool LOWER, int CS, bool CONJT>
+__global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A, int64_t lda,
+                                                   const cplx<T>* __restrict__ dinv, int64_t k0, int n,
+                                                   cplx<T>* __restrict__ B, int64_t ldb, int64_t nrhs) {
+  trsm_leaf_body<T, LOWER, CS, CONJT>(A, lda, dinv, k0, n, B, ldb, nrhs, (int64_t)blockIdx.x * CS);
+}
+
+// The inverses of all NL x NL diagonal blocks of an n x n factor in one launch:
+// block blockIdx.y (rows and columns k0 .. k0 + NL) is solved against its own
+// identity block, W + blockIdx.y NL^2 (NL x NL, row stride NL), in stripes of
+// CS columns.  The last block may be smaller; its slot keeps the identity
+// outside its nb x nb corner.
+template <typename T, bool LOWER, int CS>
+__global__ __launch_bounds__(256) void k_trsm_leaf_blocks(const cplx<T>* __restrict__ A, int64_t lda,
+                                                          const cplx<T>* __restrict__ dinv, int64_t n,
+                                                          cplx<T>* __restrict__ W) {
+  const int64_t k0 = (int64_t)blockIdx.y * NL;
+  const int nb = (int)min<int64_t>(NL, n - k0);
+  trsm_leaf_body<T, LOWER, CS, false>(A, lda, dinv, k0, nb, W + (int64_t)blockIdx.y * NL * NL, NL, nb,
+                                      (int64_t)blockIdx.x * CS);
+}
+
+template <typename T>
+__global__ void k_identity_blocks(cplx<T>* __restrict__ W, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const int r = (int)((i / NL) % NL), c = (int)(i % NL);
+  W[i] = cplx<T>{r == c ? T(1) : T(0), T(0)};
 }
 
 // One right-hand side per workgroup (the stripe the launcher picks for narrow
@@ -1120,5 +1149,69 @@ void norms2_c128(hipStream_t s, const c128* x, int64_t ldx, const c128* y, int64
   hipLaunchKernelGGL(k_norms2_finish, dim3(1), dim3(256), 0, s, (const double*)part, blocks, out);
   FOSB_LAUNCH_CHECK();
 }
+
+// ------------------------------------------------------------------ solves with block inverses
+static_assert(NL == kInvBlock, "inverse block size");
+
+template <typename T>
+void diag_block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinvL,
+                         const cplx<T>* dinvU, cplx<T>* invL, cplx<T>* invU) {
+  if (n <= 0) return;
+  hipStream_t s = ctx.stream;
+  const int64_t nblk = (n + NL - 1) / NL, count = nblk * NL * NL;
+  constexpr int CS = LeafCS<T>::v;
+  const dim3 gi((unsigned)((count + 255) / 256)), gs((unsigned)(NL / CS), (unsigned)nblk);
+  hipLaunchKernelGGL(k_identity_blocks<T>, gi, dim3(256), 0, s, invL, count);
+  FOSB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_identity_blocks<T>, gi, dim3(256), 0, s, invU, count);
+  FOSB_LAUNCH_CHECK();
+  ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 2.0 * 4.0 * NL * NL * (double)n, 2.0 * sizeof(cplx<T>) * NL * (double)n);
+  hipLaunchKernelGGL((k_trsm_leaf_blocks<T, true, CS>), gs, dim3(256), 0, s, A, lda, dinvL, n, invL);
+  FOSB_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_trsm_leaf_blocks<T, false, CS>), gs, dim3(256), 0, s, A, lda, dinvU, n, invU);
+  FOSB_LAUNCH_CHECK();
+}
+
+// B <- T^{-1} B for rows k0 .. k0 + n of the unit lower (LOWER) or upper factor,
+// k0 a multiple of NL: halves split at multiples of NL, coupled by a GEMM; a
+// leaf block is X = inv_b B_b, a product into tmp (NL x nrhs) copied back.
+template <typename T, bool LOWER>
+static void trsm_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* inv, int64_t k0, int64_t n,
+                     cplx<T>* B, int64_t ldb, int64_t nrhs, cplx<T>* tmp) {
+  if (n <= 0 || nrhs <= 0) return;
+  if (n <= NL) {
+    gemm<T>(ctx, n, nrhs, n, 1.0, inv + (k0 / NL) * NL * NL, NL, B, ldb, 0.0, tmp, nrhs);
+    copy2d<T, T>(ctx.stream, tmp, nrhs, B, ldb, n, nrhs);
+    return;
+  }
+  const int64_t n1 = NL * (((n + NL - 1) / NL + 1) / 2);
+  if (LOWER) {
+    trsm_inv<T, true>(ctx, A, lda, inv, k0, n1, B, ldb, nrhs, tmp);
+    gemm<T>(ctx, n - n1, nrhs, n1, -1.0, A + (k0 + n1) * lda + k0, lda, B, ldb, 1.0, B + n1 * ldb, ldb);
+    trsm_inv<T, true>(ctx, A, lda, inv, k0 + n1, n - n1, B + n1 * ldb, ldb, nrhs, tmp);
+  } else {
+    trsm_inv<T, false>(ctx, A, lda, inv, k0 + n1, n - n1, B + n1 * ldb, ldb, nrhs, tmp);
+    gemm<T>(ctx, n1, nrhs, n - n1, -1.0, A + k0 * lda + (k0 + n1), lda, B + n1 * ldb, ldb, 1.0, B, ldb);
+    trsm_inv<T, false>(ctx, A, lda, inv, k0, n1, B, ldb, nrhs, tmp);
+  }
+}
+
+template <typename T>
+void trsm_lower_unit_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invL, int64_t n, cplx<T>* B,
+                         int64_t ldb, int64_t nrhs, cplx<T>* tmp) {
+  trsm_inv<T, true>(ctx, A, lda, invL, 0, n, B, ldb, nrhs, tmp);
+}
+template <typename T>
+void trsm_upper_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invU, int64_t n, cplx<T>* B,
+                    int64_t ldb, int64_t nrhs, cplx<T>* tmp) {
+  trsm_inv<T, false>(ctx, A, lda, invU, 0, n, B, ldb, nrhs, tmp);
+}
+
+template void diag_block_inverses<float>(Context&, const c64*, int64_t, int64_t, const c64*, const c64*, c64*,
+                                         c64*);
+template void trsm_lower_unit_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, int64_t,
+                                         c64*);
+template void trsm_upper_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, int64_t,
+                                    c64*);
 
 }  // namespace fosb
