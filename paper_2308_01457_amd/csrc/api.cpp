@@ -265,16 +265,17 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
     L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
     copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
-    info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(), L->perm);
-  }
-  if (info != 0) fail(FOSB_E_SINGULAR, "exactly zero pivot at index %lld", (long long)(info - 1));
-  if (precision == FOSB_PREC_MIXED) {  // the refined solves apply the factors through their block inverses
+    // the refined solves apply the factors through their diagonal-block inverses
     const size_t bytes = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(c64);
     L->inv_L.alloc(bytes);
     L->inv_U.alloc(bytes);
-    diag_block_inverses<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
-                               L->inv_L.as<c64>(), L->inv_U.as<c64>());
+    info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(), L->perm,
+                            L->inv_L.as<c64>());
+    if (info == 0)
+      upper_block_inverses<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, L->dinv_U.as<c64>(),
+                                  L->inv_U.as<c64>());
   }
+  if (info != 0) fail(FOSB_E_SINGULAR, "exactly zero pivot at index %lld", (long long)(info - 1));
   upload(L->d_perm, L->perm, s);
   // quadrature nodes, first moments and RHS weights
   L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));

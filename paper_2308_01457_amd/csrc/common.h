@@ -254,9 +254,12 @@ template <typename T>
 void gemm_ch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
              const cplx<T>* B, int64_t ldb, double beta, cplx<T>* C, int64_t ldc);
 // lu.hip
+// invL (optional, complex64 factors): receives the kInvBlock x kInvBlock
+// diagonal-block inverses of L (layout as for upper_block_inverses); the
+// blocked factorisation then also solves its block rows through them.
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
-                  std::vector<int32_t>& perm);
+                  std::vector<int32_t>& perm, cplx<T>* invL = nullptr);
 template <typename T>
 void trsm_lower_unit(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0,
                      int64_t n, cplx<T>* B, int64_t ldb, int64_t nrhs);
@@ -270,15 +273,15 @@ void trsm_upper_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* d
 template <typename T>
 void trsm_lower_unit_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0, int64_t n,
                         cplx<T>* B, int64_t ldb, int64_t nrhs);
-// Inverses of the kInvBlock x kInvBlock diagonal blocks of the unit lower and
-// upper factors (block b at inv + b kInvBlock^2, row-major, row stride
-// kInvBlock; the last block's slot is the identity outside its corner), and
+// Inverses of the kInvBlock x kInvBlock diagonal blocks of the upper factor
+// (block b at inv + b kInvBlock^2, row-major, row stride kInvBlock; the last
+// block's slot is the identity outside its corner; lu_factor makes L's), and
 // triangular solves of a whole factor that apply them at the leaves
 // (tmp: kInvBlock x nrhs scratch).  Complex64 factors only.
 constexpr int kInvBlock = 256;
 template <typename T>
-void diag_block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinvL,
-                         const cplx<T>* dinvU, cplx<T>* invL, cplx<T>* invU);
+void upper_block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinvU,
+                          cplx<T>* invU);
 template <typename T>
 void trsm_lower_unit_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invL, int64_t n, cplx<T>* B,
                          int64_t ldb, int64_t nrhs, cplx<T>* tmp);

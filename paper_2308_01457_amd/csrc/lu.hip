@@ -534,19 +534,18 @@ __global__ __launch_bounds__(256) void k_trsm_leaf(const cplx<T>* __restrict__ A
   trsm_leaf_body<T, LOWER, CS, CONJT>(A, lda, dinv, k0, n, B, ldb, nrhs, (int64_t)blockIdx.x * CS);
 }
 
-// The inverses of all NL x NL diagonal blocks of an n x n factor in one launch:
-// block blockIdx.y (rows and columns k0 .. k0 + NL) is solved against its own
-// identity block, W + blockIdx.y NL^2 (NL x NL, row stride NL), in stripes of
-// CS columns.  The last block may be smaller; its slot keeps the identity
-// outside its nb x nb corner.
+// Inverses of NL x NL diagonal blocks of an n x n factor in one launch: block
+// b = b0 + blockIdx.y (rows and columns b NL .. b NL + NL) is solved against
+// its own identity block, W + b NL^2 (NL x NL, row stride NL), in stripes of CS
+// columns.  The last block may be smaller; its slot keeps the identity outside
+// its nb x nb corner.
 template <typename T, bool LOWER, int CS>
 __global__ __launch_bounds__(256) void k_trsm_leaf_blocks(const cplx<T>* __restrict__ A, int64_t lda,
                                                           const cplx<T>* __restrict__ dinv, int64_t n,
-                                                          cplx<T>* __restrict__ W) {
-  const int64_t k0 = (int64_t)blockIdx.y * NL;
+                                                          cplx<T>* __restrict__ W, int64_t b0) {
+  const int64_t b = b0 + blockIdx.y, k0 = b * NL;
   const int nb = (int)min<int64_t>(NL, n - k0);
-  trsm_leaf_body<T, LOWER, CS, false>(A, lda, dinv, k0, nb, W + (int64_t)blockIdx.y * NL * NL, NL, nb,
-                                      (int64_t)blockIdx.x * CS);
+  trsm_leaf_body<T, LOWER, CS, false>(A, lda, dinv, k0, nb, W + b * NL * NL, NL, nb, (int64_t)blockIdx.x * CS);
 }
 
 template <typename T>
@@ -555,6 +554,25 @@ __global__ void k_identity_blocks(cplx<T>* __restrict__ W, int64_t count) {
   if (i >= count) return;
   const int r = (int)((i / NL) % NL), c = (int)(i % NL);
   W[i] = cplx<T>{r == c ? T(1) : T(0), T(0)};
+}
+
+// Inverses of diagonal blocks b0 .. b0 + nbk of the unit lower (LOWER) or
+// upper factor into W (block b at W + b NL^2), on ctx's stream.
+template <typename T, bool LOWER>
+static void block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinv,
+                           cplx<T>* W, int64_t b0, int64_t nbk) {
+  if (nbk <= 0) return;
+  hipStream_t s = ctx.stream;
+  constexpr int CS = LeafCS<T>::v;
+  const int64_t count = nbk * NL * NL;
+  hipLaunchKernelGGL(k_identity_blocks<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                     W + b0 * NL * NL, count);
+  FOSB_LAUNCH_CHECK();
+  ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 4.0 * NL * NL * (double)std::min(n, nbk * NL),
+                 2.0 * sizeof(cplx<T>) * NL * (double)std::min(n, nbk * NL));
+  hipLaunchKernelGGL((k_trsm_leaf_blocks<T, LOWER, CS>), dim3((unsigned)(NL / CS), (unsigned)nbk), dim3(256), 0, s,
+                     A, lda, dinv, n, W, b0);
+  FOSB_LAUNCH_CHECK();
 }
 
 // One right-hand side per workgroup (the stripe the launcher picks for narrow
@@ -665,6 +683,7 @@ struct LuRun {
   int64_t cand_stride;
   cplx<T>* top;
   int64_t pc0, pc1;  // columns a panel permutes at once (the rest is the update stream's)
+  cplx<T>* invL = nullptr;  // optional: NL x NL diagonal-block inverses of L, filled per block
 };
 
 constexpr int kMoveStride = 1 + 4 * NB;
@@ -741,6 +760,23 @@ static void rec_lu(LuRun<T>& R, int64_t k, int64_t w) {
 // touch the same columns concurrently: the panel of block j+1 reads and writes
 // only block j+1, the trailing update of step j only columns right of it, and
 // block j's multipliers are permuted by the update stream after its last read.
+template <typename T, bool LOWER>
+static void trsm_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* inv, int64_t k0, int64_t n,
+                     cplx<T>* B, int64_t ldb, int64_t nrhs, cplx<T>* tmp);
+
+// B <- L_jj^{-1} B for the block row of block j (rows kj .. kj + wj): through
+// the block inverses when the run keeps them (they are final once block j's
+// panels are done), else with the leaf kernel.
+template <typename T>
+static void block_row_solve(LuRun<T>& R, Context& U, int64_t kj, int64_t wj, cplx<T>* B, int64_t ncols) {
+  if (R.invL) {
+    U.solve_tmp.reserve((size_t)NL * ncols * sizeof(cplx<T>));
+    trsm_inv<T, true>(U, R.A, R.lda, R.invL, kj, wj, B, R.lda, ncols, U.solve_tmp.as<cplx<T>>());
+  } else {
+    trsm_lower_unit<T>(U, R.A, R.lda, R.dinvL, kj, wj, B, R.lda, ncols);
+  }
+}
+
 template <typename T>
 static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
   Context& P = *R.ctx;
@@ -775,6 +811,7 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
   for (int64_t j = 0; j < nblk; ++j) {
     const int64_t kj = j * nb, wj = std::min(nb, n - kj);
     FOSB_HIP(hipStreamWaitEvent(sb, ev_panel, 0));
+    if (R.invL) block_inverses<T, true>(U, A, n, lda, R.dinvL, R.invL, kj / NL, (wj + NL - 1) / NL);
     {
       ColRanges cr{{0, kj + wj}, {kj, n}};
       const int64_t width = kj + (n - kj - wj);
@@ -787,7 +824,7 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
     }
     if (j + 1 == nblk) break;
     const int64_t k1 = kj + wj, w1 = std::min(nb, n - k1);
-    trsm_lower_unit<T>(U, A, lda, R.dinvL, kj, wj, A + kj * lda + k1, lda, w1);
+    block_row_solve(R, U, kj, wj, A + kj * lda + k1, w1);
     gemm<T>(U, n - k1, w1, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + k1, lda, 1.0, A + k1 * lda + k1, lda);
     FOSB_HIP(hipEventRecord(ev_look, sb));
     FOSB_HIP(hipStreamWaitEvent(sa, ev_look, 0));
@@ -798,7 +835,7 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
       // kernels get workgroup slots instead of queueing behind one huge grid
       for (int64_t c0 = kr; c0 < n; c0 += kTrailChunk) {
         const int64_t cn = std::min<int64_t>(kTrailChunk, n - c0);
-        trsm_lower_unit<T>(U, A, lda, R.dinvL, kj, wj, A + kj * lda + c0, lda, cn);
+        block_row_solve(R, U, kj, wj, A + kj * lda + c0, cn);
         gemm<T>(U, n - k1, cn, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + c0, lda, 1.0, A + k1 * lda + c0, lda);
       }
     }
@@ -809,7 +846,7 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
 
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
-                  std::vector<int32_t>& perm) {
+                  std::vector<int32_t>& perm, cplx<T>* invL) {
   hipStream_t s = ctx.stream;
   const int64_t maxnodes = (n + Node<T>::size - 1) / Node<T>::size;
   const int64_t npanel = (n + NB - 1) / NB;
@@ -831,6 +868,7 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   R.top = reinterpret_cast<cplx<T>*>(reinterpret_cast<char*>(base) + top_off);
   R.pc0 = 0;
   R.pc1 = n;
+  R.invL = invL;
   // first zero pivot, reduced with atomicMin: starts above every index (0x7f7f7f7f)
   FOSB_HIP(hipMemsetAsync(R.info, 0x7f, sizeof(int32_t), s));
   if (n >= kLookaheadMinN) {
@@ -845,6 +883,7 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
     blocked_lu(R, U, n >= 16384 ? 512 : 256);
   } else {
     rec_lu(R, 0, n);
+    if (invL) block_inverses<T, true>(ctx, A, n, lda, dinvL, invL, 0, (n + NL - 1) / NL);
   }
   std::vector<int32_t> mv((size_t)npanel * kMoveStride);
   int32_t info = 0;
@@ -952,8 +991,8 @@ void trsm_lower_unit_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<
   trsm_lower_unit_ch<T>(ctx, A, lda, dinvL, k0, n1, B, ldb, nrhs);
 }
 
-template int64_t lu_factor<double>(Context&, c128*, int64_t, int64_t, c128*, c128*, std::vector<int32_t>&);
-template int64_t lu_factor<float>(Context&, c64*, int64_t, int64_t, c64*, c64*, std::vector<int32_t>&);
+template int64_t lu_factor<double>(Context&, c128*, int64_t, int64_t, c128*, c128*, std::vector<int32_t>&, c128*);
+template int64_t lu_factor<float>(Context&, c64*, int64_t, int64_t, c64*, c64*, std::vector<int32_t>&, c64*);
 template void trsm_lower_unit<double>(Context&, const c128*, int64_t, const c128*, int64_t, int64_t, c128*,
                                       int64_t, int64_t);
 template void trsm_lower_unit<float>(Context&, const c64*, int64_t, const c64*, int64_t, int64_t, c64*, int64_t,
@@ -1154,22 +1193,9 @@ void norms2_c128(hipStream_t s, const c128* x, int64_t ldx, const c128* y, int64
 static_assert(NL == kInvBlock, "inverse block size");
 
 template <typename T>
-void diag_block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinvL,
-                         const cplx<T>* dinvU, cplx<T>* invL, cplx<T>* invU) {
-  if (n <= 0) return;
-  hipStream_t s = ctx.stream;
-  const int64_t nblk = (n + NL - 1) / NL, count = nblk * NL * NL;
-  constexpr int CS = LeafCS<T>::v;
-  const dim3 gi((unsigned)((count + 255) / 256)), gs((unsigned)(NL / CS), (unsigned)nblk);
-  hipLaunchKernelGGL(k_identity_blocks<T>, gi, dim3(256), 0, s, invL, count);
-  FOSB_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_identity_blocks<T>, gi, dim3(256), 0, s, invU, count);
-  FOSB_LAUNCH_CHECK();
-  ProfScope prof(ctx, FOSB_K_TRSM_LEAF, 2.0 * 4.0 * NL * NL * (double)n, 2.0 * sizeof(cplx<T>) * NL * (double)n);
-  hipLaunchKernelGGL((k_trsm_leaf_blocks<T, true, CS>), gs, dim3(256), 0, s, A, lda, dinvL, n, invL);
-  FOSB_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_trsm_leaf_blocks<T, false, CS>), gs, dim3(256), 0, s, A, lda, dinvU, n, invU);
-  FOSB_LAUNCH_CHECK();
+void upper_block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinvU,
+                          cplx<T>* invU) {
+  if (n > 0) block_inverses<T, false>(ctx, A, n, lda, dinvU, invU, 0, (n + NL - 1) / NL);
 }
 
 // B <- T^{-1} B for rows k0 .. k0 + n of the unit lower (LOWER) or upper factor,
@@ -1207,8 +1233,7 @@ void trsm_upper_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* 
   trsm_inv<T, false>(ctx, A, lda, invU, 0, n, B, ldb, nrhs, tmp);
 }
 
-template void diag_block_inverses<float>(Context&, const c64*, int64_t, int64_t, const c64*, const c64*, c64*,
-                                         c64*);
+template void upper_block_inverses<float>(Context&, const c64*, int64_t, int64_t, const c64*, c64*);
 template void trsm_lower_unit_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, int64_t,
                                          c64*);
 template void trsm_upper_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, int64_t,
