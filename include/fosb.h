@@ -14,9 +14,11 @@
  *     torch tensors); they must stay valid until the context's stream has run
  *     the enqueued work.  "host" pointers are read during the call only.
  *   - Handles (context, mesh, level) are owned by the library until *_destroy.
- *     The library allocates its own O(N) tables and O(N*nrhs) work buffers with
- *     hipMalloc on the context's device; O(N^2) matrices are always caller
- *     buffers.
+ *     The library allocates its own O(N) tables (a MIXED level also keeps the
+ *     inverses of the 256 x 256 diagonal blocks of its factors, 4 KiB per
+ *     unknown) and work buffers (O(N*nrhs) for solves, up to 1 GiB for the
+ *     assembly's column band) with hipMalloc on the context's device; O(N^2)
+ *     matrices are always caller buffers.
  *   - All work is enqueued on the context's stream.  Calls that must inspect a
  *     device result (pivot breakdown, refinement convergence) synchronise that
  *     stream before returning.
@@ -155,7 +157,9 @@ fosb_status fosb_assemble(fosb_context* ctx, const fosb_mesh* mesh, double k, co
  *                    its LU factors; Zlow must be NULL.
  *   precision MIXED: Z is kept read-only for FP64 refinement residuals and
  *                    must outlive the level; Zlow (device complex64, N x N,
- *                    ldzlow) receives the FP32 LU factors.
+ *                    ldzlow) receives the FP32 LU factors, which the level's
+ *                    solves apply through the inverses of their 256 x 256
+ *                    diagonal blocks (kept by the level).
  * dirs, pols: host, n_dirs x 3 float64 (unit incidence direction, real
  * polarisation).  field: fosb_field.  On an exactly zero pivot returns
  * FOSB_E_SINGULAR. */
