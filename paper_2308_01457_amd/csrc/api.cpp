@@ -83,8 +83,8 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   c128* X = ctx.scratch[3].as<c128>();
   c64* R32 = ctx.scratch[4].as<c64>();
   c128* Rw = ctx.scratch[5].as<c128>();
-  ctx.solve_tmp.reserve((size_t)kInvBlock * nrhs * sizeof(c64));
-  c64* tmp = ctx.solve_tmp.as<c64>();
+  ctx.solve_tmp.reserve((size_t)n * nrhs * sizeof(c64));
+  c64* Y32 = ctx.solve_tmp.as<c64>();  // L^{-1} P R between the two triangular solves
   const c64* A32 = static_cast<const c64*>(L.Zlow);
   const c128* Z64 = static_cast<const c128*>(L.Z);
   copy_c128(s, B, ldb, Bo, nrhs, n, nrhs);
@@ -101,8 +101,8 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     if (!adjoint) {
       permute_rows_gather(s, perm, R, nrhs, T, nrhs, n, nrhs);
       copy_c128_to_c64(s, T, nrhs, R32, nrhs, n, nrhs);
-      trsm_lower_unit_inv<float>(ctx, A32, L.ldzlow, L.inv_L.as<c64>(), n, R32, nrhs, nrhs, tmp);
-      trsm_upper_inv<float>(ctx, A32, L.ldzlow, L.inv_U.as<c64>(), n, R32, nrhs, nrhs, tmp);
+      trsm_lower_unit_inv<float>(ctx, A32, L.ldzlow, L.inv_L.as<c64>(), n, R32, nrhs, Y32, nrhs, nrhs);
+      trsm_upper_inv<float>(ctx, A32, L.ldzlow, L.inv_U.as<c64>(), n, Y32, nrhs, R32, nrhs, nrhs);
       copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
       D = T;
     } else {

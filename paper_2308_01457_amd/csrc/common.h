@@ -96,7 +96,7 @@ struct Context {
   size_t max_lds = 65536;
   // reusable scratch (grow-only); each user documents which slot it uses
   DevBuf scratch[6];
-  DevBuf solve_tmp;   // kInvBlock x nrhs leaf products of the block-inverse solves
+  DevBuf solve_tmp;   // block-inverse solves: leaf products (LU block rows), intermediate (refined solves)
   DevBuf counters;    // int32 tree counters for panel factorisation
   DevBuf small;       // small per-panel buffers
   // Sauter-Schwab point tables per Gauss order n (1..12): 5 doubles per point,
@@ -276,18 +276,19 @@ void trsm_lower_unit_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<
 // Inverses of the kInvBlock x kInvBlock diagonal blocks of the upper factor
 // (block b at inv + b kInvBlock^2, row-major, row stride kInvBlock; the last
 // block's slot is the identity outside its corner; lu_factor makes L's), and
-// triangular solves of a whole factor that apply them at the leaves
-// (tmp: kInvBlock x nrhs scratch).  Complex64 factors only.
+// out-of-place triangular solves of a whole factor that apply them at the
+// leaves: X <- T^{-1} B, with B (n x nrhs) consumed as workspace.  Complex64
+// factors only.
 constexpr int kInvBlock = 256;
 template <typename T>
 void upper_block_inverses(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, const cplx<T>* dinvU,
                           cplx<T>* invU);
 template <typename T>
 void trsm_lower_unit_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invL, int64_t n, cplx<T>* B,
-                         int64_t ldb, int64_t nrhs, cplx<T>* tmp);
+                         int64_t ldb, cplx<T>* X, int64_t ldx, int64_t nrhs);
 template <typename T>
 void trsm_upper_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invU, int64_t n, cplx<T>* B,
-                    int64_t ldb, int64_t nrhs, cplx<T>* tmp);
+                    int64_t ldb, cplx<T>* X, int64_t ldx, int64_t nrhs);
 void permute_rows_gather(hipStream_t s, const int32_t* perm, const c128* src, int64_t lds, c128* dst,
                          int64_t ldd, int64_t n, int64_t ncols);
 // dst[perm[i]] = src[i]

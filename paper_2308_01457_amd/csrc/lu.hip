@@ -1222,21 +1222,44 @@ static void trsm_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>*
   }
 }
 
+// X <- T^{-1} B out of place, same splits: B (rows k0 .. k0 + n) is consumed
+// as workspace, each leaf product writes its block of X directly, and the
+// coupling products read the solved part of X.  No copies.
+template <typename T, bool LOWER>
+static void trsm_inv_oop(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* inv, int64_t k0, int64_t n,
+                         cplx<T>* B, int64_t ldb, cplx<T>* X, int64_t ldx, int64_t nrhs) {
+  if (n <= 0 || nrhs <= 0) return;
+  if (n <= NL) {
+    gemm<T>(ctx, n, nrhs, n, 1.0, inv + (k0 / NL) * NL * NL, NL, B, ldb, 0.0, X, ldx);
+    return;
+  }
+  const int64_t n1 = NL * (((n + NL - 1) / NL + 1) / 2);
+  if (LOWER) {
+    trsm_inv_oop<T, true>(ctx, A, lda, inv, k0, n1, B, ldb, X, ldx, nrhs);
+    gemm<T>(ctx, n - n1, nrhs, n1, -1.0, A + (k0 + n1) * lda + k0, lda, X, ldx, 1.0, B + n1 * ldb, ldb);
+    trsm_inv_oop<T, true>(ctx, A, lda, inv, k0 + n1, n - n1, B + n1 * ldb, ldb, X + n1 * ldx, ldx, nrhs);
+  } else {
+    trsm_inv_oop<T, false>(ctx, A, lda, inv, k0 + n1, n - n1, B + n1 * ldb, ldb, X + n1 * ldx, ldx, nrhs);
+    gemm<T>(ctx, n1, nrhs, n - n1, -1.0, A + k0 * lda + (k0 + n1), lda, X + n1 * ldx, ldx, 1.0, B, ldb);
+    trsm_inv_oop<T, false>(ctx, A, lda, inv, k0, n1, B, ldb, X, ldx, nrhs);
+  }
+}
+
 template <typename T>
 void trsm_lower_unit_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invL, int64_t n, cplx<T>* B,
-                         int64_t ldb, int64_t nrhs, cplx<T>* tmp) {
-  trsm_inv<T, true>(ctx, A, lda, invL, 0, n, B, ldb, nrhs, tmp);
+                         int64_t ldb, cplx<T>* X, int64_t ldx, int64_t nrhs) {
+  trsm_inv_oop<T, true>(ctx, A, lda, invL, 0, n, B, ldb, X, ldx, nrhs);
 }
 template <typename T>
 void trsm_upper_inv(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* invU, int64_t n, cplx<T>* B,
-                    int64_t ldb, int64_t nrhs, cplx<T>* tmp) {
-  trsm_inv<T, false>(ctx, A, lda, invU, 0, n, B, ldb, nrhs, tmp);
+                    int64_t ldb, cplx<T>* X, int64_t ldx, int64_t nrhs) {
+  trsm_inv_oop<T, false>(ctx, A, lda, invU, 0, n, B, ldb, X, ldx, nrhs);
 }
 
 template void upper_block_inverses<float>(Context&, const c64*, int64_t, int64_t, const c64*, c64*);
-template void trsm_lower_unit_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, int64_t,
-                                         c64*);
-template void trsm_upper_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, int64_t,
-                                    c64*);
+template void trsm_lower_unit_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, c64*,
+                                         int64_t, int64_t);
+template void trsm_upper_inv<float>(Context&, const c64*, int64_t, const c64*, int64_t, c64*, int64_t, c64*, int64_t,
+                                    int64_t);
 
 }  // namespace fosb
