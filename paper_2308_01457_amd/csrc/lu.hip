@@ -689,7 +689,7 @@ struct LuRun {
 constexpr int kMoveStride = 1 + 4 * NB;
 static_assert(kMoveStride == kMoveStrideDev, "row-move list stride");
 constexpr int64_t kLookaheadMinN = 2048;  // smaller matrices: plain recursion on one stream
-constexpr int64_t kTrailChunk = 4096;      // columns per trailing-update launch (measured: 2048..8192)
+constexpr int64_t kTrailChunk = 16384;     // columns per trailing-update launch (measured: 2048..16384)
 
 static inline int64_t split_half(int64_t w) { return (int64_t)NB * (((w / NB) + 1) / 2); }
 
