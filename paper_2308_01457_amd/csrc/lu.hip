@@ -51,7 +51,7 @@ __device__ __forceinline__ T cabs1(cplx<T> a) {
 // Rows per tree node = threads per workgroup (one row per thread); a node
 // merges NODE / NB children.  Wider nodes (512, 1024 rows: fewer tree levels)
 // measured slower: the per-column barrier and key reduction grow with the
-// number of waves.
+// number of waves; narrower ones (128 rows) too: one more tree level.
 template <typename T> struct Node { static constexpr int size = 256; };
 
 // The panel chain (tournament nodes, row moves, panel finish) and the
