@@ -194,3 +194,47 @@ def test_full_tensor_variance_is_nonnegative(oracle_levels, kind):
         # the off-diagonal far-field correlation is Hermitian in the angle pair
         Cor = uq.pair_correlation(FF, S, FF)
         assert np.abs(Cor - np.conj(np.transpose(Cor, (0, 2, 1)))).max() < 1e-10 * np.abs(Cor).max()
+
+
+def test_covariance_hand_values():
+    """Hand-computed values of the covariance models at chosen distances
+    (amplitude sigma is the standard deviation, r the Euclidean distance):
+    Gaussian sigma^2 exp(-r^2/(2 ell^2)) at r = ell is sigma^2 e^{-1/2} and at
+    r = 2 ell sigma^2 e^{-2}; Matern-3/2 sigma^2 (1 + sqrt3 r/ell) e^{-sqrt3 r/ell}
+    at r = ell/sqrt3 is 2 sigma^2 e^{-1} and at r = 0 sigma^2; the rigid
+    translation model is sigma^2 n(x).n(y)."""
+    sig, ell = 0.3, 0.7
+    X1 = np.array([[0.0, 0.0, 0.0]])
+    dirn = np.array([0.6, 0.0, 0.8])
+    pts = np.array([[0.0, 0.0, 0.0], ell * dirn, 2 * ell * dirn, ell / np.sqrt(3.0) * dirn])
+    g = uq.covariance("gaussian", sig, ell, X1, None, pts, None)[0]
+    assert np.allclose(g, sig ** 2 * np.array([1.0, np.exp(-0.5), np.exp(-2.0), np.exp(-1.0 / 6.0)]),
+                       rtol=1e-14, atol=0)
+    m = uq.covariance("matern32", sig, ell, X1, None, pts, None)[0]
+    a = np.sqrt(3.0) * np.array([0.0, 1.0, 2.0, 1.0 / np.sqrt(3.0)])
+    assert abs(m[3] - 2.0 * sig ** 2 * np.exp(-1.0)) < 1e-14 * sig ** 2
+    assert abs(m[0] - sig ** 2) < 1e-15
+    assert abs(m[1] - sig ** 2 * (1 + np.sqrt(3.0)) * np.exp(-np.sqrt(3.0))) < 1e-14 * sig ** 2
+    assert np.allclose(m, sig ** 2 * (1 + a) * np.exp(-a), rtol=1e-13, atol=0)
+    N1 = np.array([[0.0, 0.0, 1.0]])
+    N2 = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.0, 0.6, 0.8]])
+    nd = uq.covariance("normal_dot", sig, ell, X1, N1, pts[:3], N2)[0]
+    assert np.allclose(nd, sig ** 2 * np.array([1.0, 0.0, 0.8]), rtol=0, atol=1e-16)
+    assert np.all(uq.covariance("constant", sig, ell, X1, None, pts, None) == sig ** 2)
+    # d/d ell: Gaussian K r^2/ell^3 at r = ell is sigma^2 e^{-1/2}/ell
+    dg = uq.covariance_dell("gaussian", sig, ell, X1, None, pts[1:2], None)[0, 0]
+    assert abs(dg - sig ** 2 * np.exp(-0.5) / ell) < 1e-14 * sig ** 2 / ell
+    # Matern-3/2: sigma^2 a^2 e^{-a}/ell, a = sqrt3 r/ell; at r = ell/sqrt3 (a = 1): sigma^2 e^{-1}/ell
+    dm = uq.covariance_dell("matern32", sig, ell, X1, None, pts[3:4], None)[0, 0]
+    assert abs(dm - sig ** 2 * np.exp(-1.0) / ell) < 1e-14 * sig ** 2 / ell
+
+
+def test_rcs_db_values():
+    """Display transform 10 log10(4 pi V / |p|^2): V = 1/(4 pi) is 0 dB, ten
+    times that is 10 dB, |p|^2 = 2 subtracts 10 log10 2, and negative
+    combination-technique values are clamped (very low dB, finite)."""
+    V = np.array([1.0, 10.0, 1e-3, -1e-9]) / (4.0 * np.pi)
+    db = uq.rcs_db(V)
+    assert abs(db[0]) < 1e-13 and abs(db[1] - 10.0) < 1e-13 and abs(db[2] + 30.0) < 1e-12
+    assert np.isfinite(db[3]) and db[3] < -2900.0
+    assert abs(uq.rcs_db(V[:1], pol_norm2=2.0)[0] + 10.0 * np.log10(2.0)) < 1e-13
