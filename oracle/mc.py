@@ -53,7 +53,7 @@ def far_field(V: np.ndarray, F: np.ndarray, k: float, xh: np.ndarray, d=(0.0, 0.
     """Far field (n_a, 3) of the Galerkin EFIE solution on the mesh (V, F)."""
     m = meshmod.build(V, F)
     Z = efie.assemble(m, k, n_gauss=n_gauss)
-    b = efie.incident_rhs(m, k, np.asarray(d, float), np.asarray(pol, float))
+    b = efie.incident_rhs(m, k, np.asarray(d, float), np.asarray(pol))
     u = sla.lu_solve(sla.lu_factor(Z), b)
     return efie.far_field(m, k, u, xh)
 
@@ -74,6 +74,16 @@ def first_order_far_field(level: uq.Level, F: np.ndarray, vr: np.ndarray, xh: np
     dj = sla.lu_solve(level.lu, bp)
     FF = uq.far_field_matrix(level, xh)               # (3, n_a, N)
     return np.einsum("cim,mk->kci", FF, dj)
+
+
+def first_order_far_field_vector(level: uq.Level, vfield, xh: np.ndarray) -> np.ndarray:
+    """F'[v] (3, n_a) for a deterministic vector perturbation field v (a
+    function of points (..., 3)): its normal component v.n at the quadrature
+    nodes feeds the first-order map of a level built with field_kind
+    'normal'."""
+    vn = np.sum(vfield(level.X) * level.Nq, axis=-1)
+    dj = sla.lu_solve(level.lu, level.Wgt @ vn)
+    return np.einsum("cim,m->ci", uq.far_field_matrix(level, xh), dj)
 
 
 def mc_far_fields(V: np.ndarray, F: np.ndarray, k: float, xh: np.ndarray, vr: np.ndarray, t: float,

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads
-from oracle import mc
+from oracle import efie, mc, uq
 
 K = 1.0
 TS = (0.04, 0.02, 0.01, 0.005)
@@ -91,3 +91,26 @@ def test_mc_floor_shrinks_with_the_mesh(oracle_levels, sweep_s1):
             for t in TS[-2:]]
     floor2 = _rel((4.0 * Vmc2[1] - Vmc2[0]) / 3.0, Vlin2)
     assert floor2 < 1.5e-2 and floor1 / floor2 > 2.5, (floor1, floor2)
+
+
+def test_foa_versus_zoa_t_sweep():
+    """Deterministic perturbation x -> x + t v(x) with the kite experiment's
+    field v, applied to the 320-triangle sphere (its incidence, made
+    transverse): the zeroth-order approximation F misses F_t by O(t), the
+    first-order one F + t F'[v] by O(t^2), down to a small h-floor."""
+    V, F = workloads.icosphere(2)
+    d, p = workloads.kite_incidence()
+    lv = uq.make_level(V, F, K, d, p, "normal")
+    xh = workloads.angles_xz(37)
+    F0 = efie.far_field(lv.mesh, K, lv.u, xh).T
+    Fp = mc.first_order_far_field_vector(lv, workloads.kite_field, xh)
+    zoa, foa = [], []
+    for t in (0.2, 0.1, 0.05, 0.025):
+        Ft = mc.far_field(V + t * workloads.kite_field(V), F, K, xh, d=d, pol=p).T
+        zoa.append(_rel(F0, Ft))
+        foa.append(_rel(F0 + t * Fp, Ft))
+    rz = [zoa[i] / zoa[i + 1] for i in range(3)]
+    rf = [foa[i] / foa[i + 1] for i in range(3)]
+    assert all(1.8 < r < 2.1 for r in rz), (zoa, rz)
+    assert rf[0] > 3.4 and rf[1] > 3.4 and rf[2] > 3.0, (foa, rf)
+    assert foa[-1] < 1e-3 and foa[-1] < 0.05 * zoa[-1], (foa, zoa)

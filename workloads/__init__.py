@@ -28,6 +28,8 @@ __all__ = [
     "ellipsoid",
     "superquadric",
     "angles_xz",
+    "kite_field",
+    "kite_incidence",
     "Workload",
     "workload",
     "batched_ellipsoids",
@@ -149,6 +151,24 @@ def angles_xz(n: int) -> np.ndarray:
     x_hat = (sin theta, 0, cos theta)."""
     th = np.pi * np.arange(n) / (n - 1)
     return np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], axis=1)
+
+
+def kite_field(X: np.ndarray) -> np.ndarray:
+    """Deterministic perturbation field of the FOA-versus-ZOA experiment
+    (kite experiment of the paper), evaluated at points X (..., 3):
+    v(x) = ((z^2 - 1)(cos th - 1), 0.25 sin th (1 - z^2), 0), th = atan2(y, x)."""
+    th = np.arctan2(X[..., 1], X[..., 0])
+    z = X[..., 2]
+    return np.stack([(z ** 2 - 1.0) * (np.cos(th) - 1.0), 0.25 * np.sin(th) * (1.0 - z ** 2), np.zeros_like(z)], -1)
+
+
+def kite_incidence() -> tuple[np.ndarray, np.ndarray]:
+    """Incidence (d, p) of the FOA-versus-ZOA experiment: d = (1, 2, 3)/sqrt(14)
+    and the printed p = (i, 2, -1 - i/3) with its component along d removed
+    (the printed vector has p.d != 0, which no plane wave satisfies)."""
+    d = np.array([1.0, 2.0, 3.0]) / np.sqrt(14.0)
+    p = np.array([1j, 2.0, -1.0 - 1j / 3.0])
+    return d, p - (p @ d) * d
 
 
 def polarisation_for(d: np.ndarray) -> np.ndarray:
