@@ -17,8 +17,15 @@
  *     The library allocates its own O(N) tables (a MIXED level also keeps the
  *     inverses of the 256 x 256 diagonal blocks of its factors, 4 KiB per
  *     unknown) and work buffers (O(N*nrhs) for solves, up to 1 GiB for the
- *     assembly's column band) with hipMalloc on the context's device; O(N^2)
- *     matrices are always caller buffers.
+ *     assembly's column band) on the context's device; O(N^2) matrices are
+ *     always caller buffers.  These device blocks come from a caching pool
+ *     per context (and per stream the context creates): a released block is
+ *     kept and handed out again, so once a pass has run, repeating it on
+ *     shapes of the same sizes makes no device allocation and no hipFree
+ *     (fosb_context_memory counts them; fosb_context_trim returns the cache
+ *     to the device).  fosb_level_workspace_size gives a level's own bytes,
+ *     and calls that build levels check, on the host and before any launch,
+ *     that the device can still hold what they need (FOSB_E_OOM otherwise).
  *   - All work is enqueued on the context's stream.  Calls that must inspect a
  *     device result (pivot breakdown, refinement convergence) synchronise that
  *     stream before returning.
@@ -91,12 +98,30 @@ typedef struct fosb_opts {
   double ir_tol;            /* target relative error of refined solves (1e-10):
                                after corrections of relative size r_{k-1}, r_k
                                (r_0 = 1) the error is estimated as r_k^2/r_{k-1} */
+  int32_t certify;          /* 0 (default) or 1: also report, in fosb_stats, the
+                               backward error of every refined solve (one more
+                               FP64 residual product per solve), a 1-norm
+                               condition estimate and the growth factor of every
+                               level built (a few extra solves per level)       */
+  int32_t reserved;         /* must be 0                                          */
 } fosb_opts;
 
+/* Counters of a call; accumulate over calls (zero-initialise before the first).
+ * The three certificate fields are filled only with opts.certify = 1 and
+ * stay 0 otherwise. */
 typedef struct fosb_stats {
   int32_t ir_sweeps;        /* largest number of refinement sweeps used            */
   int32_t n_solves;         /* level-pair solves performed                         */
   double ir_rel_correction; /* largest final ||dX||/||X||                          */
+  double backward_error;    /* largest normwise backward error of a refined solve,
+                               ||B - op(Z) X||_F / (||Z||_F ||X||_F + ||B||_F), with
+                               the FP64 matrix Z and the returned iterate X (MIXED
+                               levels; FP64 levels keep no copy of Z)            */
+  double kappa1;            /* largest estimate of ||Z||_1 ||Z^{-1}||_1 of a level
+                               built (Hager-Higham 1-norm estimator: a lower bound,
+                               within a small factor of the true value)           */
+  double growth;            /* largest max|U_ij| / max|Z_ij| of a level built
+                               (U: the upper LU factor, in its stored precision)  */
 } fosb_stats;
 
 /* Thread-local message of the last failing call ("" if none). */
@@ -113,6 +138,15 @@ fosb_status fosb_context_create(int32_t device, void* hip_stream, fosb_context**
  * FOSB_E_INVALID, and their destroy only frees their device memory. */
 fosb_status fosb_context_destroy(fosb_context* ctx);
 fosb_status fosb_context_synchronize(fosb_context* ctx);
+/* Device-memory counters of the context and the streams it created: the
+ * number of device allocations made so far, the bytes held in its caching
+ * pools for reuse, and the bytes handed out and not yet released (any output
+ * pointer may be NULL). */
+fosb_status fosb_context_memory(fosb_context* ctx, int64_t* n_device_allocs, int64_t* bytes_cached,
+                                int64_t* bytes_in_use);
+/* Waits for the context's streams and returns every cached (unused) block to
+ * the device. */
+fosb_status fosb_context_trim(fosb_context* ctx);
 
 /* ---------------------------------------------------------------- mesh */
 /* Host-only check (no device work): V (host, nv x 3 float64), F (host, nt x 3
@@ -168,6 +202,17 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
                               const double* pols, int64_t n_dirs, int32_t field,
                               const fosb_opts* opts, fosb_level** out);
 fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precision, int64_t* n_dirs);
+/* Device bytes a level built on mesh with this precision and n_dirs
+ * incidences keeps for its lifetime (permutation, diagonal-block inverses,
+ * first moments, RHS weights, quadrature nodes), and the largest work buffer
+ * bytes its construction and a refined solve with nrhs right-hand sides take
+ * from the context's pool (nrhs <= 0: n_dirs).  Host-only. */
+fosb_status fosb_level_workspace_size(const fosb_mesh* mesh, int32_t precision, int64_t n_dirs, int64_t nrhs,
+                                      int64_t* level_bytes, int64_t* work_bytes);
+/* The level's certificate from construction with opts.certify = 1 (0 otherwise):
+ * the 1-norm condition estimate of Z and the growth factor of its factors, as
+ * described for fosb_stats. */
+fosb_status fosb_level_certificate(const fosb_level* level, double* kappa1, double* growth);
 /* B <- Z^{-1} B (device complex128, N x nrhs, row stride ldb >= nrhs).  MIXED
  * levels refine in FP64 against the kept Z.  stats may be NULL. */
 fosb_status fosb_level_solve(fosb_context* ctx, const fosb_level* level, void* B, int64_t ldb,
@@ -214,15 +259,21 @@ fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels,
  * xhat: host, n_a x 3 unit vectors.  FF: device, (3 n_a) x N complex128. */
 fosb_status fosb_far_field_matrix(fosb_context* ctx, const fosb_level* level, const double* xhat,
                                   int64_t n_a, void* FF);
-/* Combination-technique far-field variance
+/* Combination-technique far-field variance (problem setting: far-field
+ * expansion and RCS; combination-technique sub-systems)
  *   var[c*n_a + i] = sum_{Lambda_H} sign mult Re (FF_l1 Sigma FF_l2^H)[(c,i),(c,i)]
- * (device, 3 n_a float64), from the blocks of fosb_correlation.  mean_F
- * (device, 3 n_a complex128, may be NULL) receives the first-moment far field of
- * the finest level. */
+ * (device, 3 n_a float64), from the blocks of fosb_correlation.  cor (device,
+ * 3 x n_a x n_a complex128, may be NULL) receives the far-field correlation
+ * between angles, per component c:
+ *   cor[c][i][j] = sum_{Lambda_H} sign P[i][j] (l1 = l2), sign (P + P^H)[i][j] (l1 != l2),
+ *   P = (FF_l1 Sigma FF_l2^H) restricted to component c,
+ * a Hermitian matrix whose diagonal has real part var (the transposed pair of
+ * Lambda contributes P^H).  mean_F (device, 3 n_a complex128, may be NULL)
+ * receives the first-moment far field of the finest level. */
 fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* levels,
                                    int32_t n_levels, int32_t L0, int32_t L, void* const* blocks,
                                    const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir,
-                                   double* var, void* mean_F);
+                                   double* var, void* cor, void* mean_F);
 
 /* Adjoint of the combination-technique variance with respect to the
  * covariance parameters.  With upstream weights g = dvar (device, 3 n_a

@@ -31,6 +31,8 @@ static void check_opts(const fosb_opts& o) {
   if (o.n_gauss_singular < 1 || o.n_gauss_singular > 12) fail(FOSB_E_INVALID, "opts: n_gauss_singular must be 1..12");
   if (o.ir_max_sweeps < 0 || o.ir_max_sweeps > 50) fail(FOSB_E_INVALID, "opts: ir_max_sweeps must be 0..50");
   if (!(o.ir_tol > 0.0) || !std::isfinite(o.ir_tol)) fail(FOSB_E_INVALID, "opts: ir_tol must be positive");
+  if (o.certify != 0 && o.certify != 1) fail(FOSB_E_INVALID, "opts: certify must be 0 or 1");
+  if (o.reserved != 0) fail(FOSB_E_INVALID, "opts: reserved must be 0");
 }
 
 static fosb_opts opts_or_default(const fosb_opts* o) {
@@ -38,12 +40,34 @@ static fosb_opts opts_or_default(const fosb_opts* o) {
   r.n_gauss_singular = 5;
   r.ir_max_sweeps = 10;
   r.ir_tol = 1e-10;
+  r.certify = 0;
+  r.reserved = 0;
   if (o) r = *o;
   check_opts(r);
   return r;
 }
 
-static void bind(Context& ctx) { FOSB_HIP(hipSetDevice(ctx.device)); }
+// Makes ctx's device current and its caching pool the calling thread's pool.
+static void bind(Context& ctx) {
+  FOSB_HIP(hipSetDevice(ctx.device));
+  bind_pool(ctx);
+}
+
+static void merge_stats(fosb_stats* dst, const fosb_stats& src) {
+  if (!dst) return;
+  dst->ir_sweeps = std::max(dst->ir_sweeps, src.ir_sweeps);
+  dst->n_solves += src.n_solves;
+  dst->ir_rel_correction = std::max(dst->ir_rel_correction, src.ir_rel_correction);
+  dst->backward_error = std::max(dst->backward_error, src.backward_error);
+  dst->kappa1 = std::max(dst->kappa1, src.kappa1);
+  dst->growth = std::max(dst->growth, src.growth);
+}
+
+static void merge_level_certificate(fosb_stats* dst, const Level& L) {
+  if (!dst) return;
+  dst->kappa1 = std::max(dst->kappa1, L.kappa1);
+  dst->growth = std::max(dst->growth, L.growth);
+}
 
 // ------------------------------------------------------------------ level solve
 // B <- Z^{-1} B (or Z^{-H} B) for a factorised level; MIXED levels refine in FP64.
@@ -136,6 +160,23 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     R = Rw;
   }
   copy_c128(s, X, nrhs, B, ldb, n, nrhs);
+  if (st && L.opts.certify && L.z_fro > 0) {
+    // normwise backward error of the returned iterate: ||Bo - op(Z64) X|| / (||Z|| ||X|| + ||Bo||)
+    copy_c128(s, Bo, nrhs, Rw, nrhs, n, nrhs);
+    if (!adjoint)
+      gemm<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
+    else
+      gemm_ch<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
+    double rx[2], bb[2];
+    norms2_c128(s, Rw, nrhs, X, nrhs, n, nrhs, ctx.norms.as<double>());
+    FOSB_HIP(hipMemcpyAsync(rx, ctx.norms.p, sizeof(rx), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+    norms2_c128(s, Bo, nrhs, Bo, nrhs, n, nrhs, ctx.norms.as<double>());
+    FOSB_HIP(hipMemcpyAsync(bb, ctx.norms.p, sizeof(bb), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+    const double den = L.z_fro * std::sqrt(rx[1]) + std::sqrt(bb[0]);
+    if (den > 0) st->backward_error = std::max(st->backward_error, std::sqrt(rx[0]) / den);
+  }
   if (st) {
     st->ir_sweeps = std::max(st->ir_sweeps, sweeps);
     st->ir_rel_correction = std::max(st->ir_rel_correction, rel);
@@ -169,7 +210,15 @@ static void two_sided(Context& ctx, const Level& l1, const Level& l2, c128* C, i
 using namespace fosb;
 
 
-#define API_BEGIN try {
+// Every entry point drops the thread's pool binding when it returns, so a
+// thread holds no reference to a context's pool between calls.
+struct PoolRelease {
+  ~PoolRelease() { fosb::thread_pool().reset(); }
+};
+
+#define API_BEGIN \
+  PoolRelease pool_release_; \
+  try {
 #define API_END                                                   \
   }                                                               \
   catch (const fosb::Error& e) {                                  \
@@ -235,6 +284,62 @@ static void check_level_args(const fosb_mesh* mesh, double k, int32_t precision,
   }
 }
 
+// Estimate of ||Z^{-1}||_1 from a few solves with Z and Z^H: the 1-norm
+// estimator of Hager (1984) in Higham's form (ACM TOMS 14, 1988), for complex
+// matrices.  x starts uniform; each step solves y = Z^{-1} x, takes the
+// complex signs xi of y, solves z = Z^{-H} xi and moves x to the unit vector of
+// the largest |z_j|, until ||y||_1 stops growing or j repeats (at most five
+// steps).  An alternating-sign test vector guards against the estimator's
+// known bad cases.  The result is a lower bound of ||Z^{-1}||_1.
+static double inverse_norm1_estimate(Context& c, const Level& L) {
+  const int64_t n = L.n;
+  hipStream_t s = c.stream;
+  std::vector<c128> h(n);
+  DevBuf v((size_t)n * sizeof(c128));
+  auto solve = [&](bool adjoint) {
+    FOSB_HIP(hipMemcpyAsync(v.p, h.data(), n * sizeof(c128), hipMemcpyHostToDevice, s));
+    level_solve_inplace(c, L, v.as<c128>(), 1, 1, nullptr, adjoint);
+    FOSB_HIP(hipMemcpyAsync(h.data(), v.p, n * sizeof(c128), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+  };
+  auto norm1 = [&]() {
+    double a = 0;
+    for (const c128& z : h) a += std::hypot(z.re, z.im);
+    return a;
+  };
+  for (auto& z : h) z = c128{1.0 / (double)n, 0.0};
+  double est = 0;
+  int64_t jlast = -1;
+  for (int it = 0; it < 5; ++it) {
+    solve(false);
+    const double e = norm1();
+    if (it > 0 && e <= est) break;
+    est = e;
+    for (auto& z : h) {
+      const double m = std::hypot(z.re, z.im);
+      z = m > 0 ? c128{z.re / m, z.im / m} : c128{1.0, 0.0};
+    }
+    solve(true);
+    int64_t j = 0;
+    double best = -1;
+    for (int64_t i = 0; i < n; ++i) {
+      const double m = std::hypot(h[i].re, h[i].im);
+      if (m > best) {
+        best = m;
+        j = i;
+      }
+    }
+    if (j == jlast) break;
+    jlast = j;
+    for (auto& z : h) z = c128{0.0, 0.0};
+    h[j] = c128{1.0, 0.0};
+  }
+  for (int64_t i = 0; i < n; ++i)
+    h[i] = c128{(i % 2 ? -1.0 : 1.0) * (1.0 + (n > 1 ? (double)i / (double)(n - 1) : 0.0)), 0.0};
+  solve(false);
+  return std::max(est, 2.0 * norm1() / (3.0 * (double)n));
+}
+
 // Factorisation, first moments and RHS weights of one level, on c's stream.
 static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh, double k, int32_t precision,
                                                void* Z, int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs,
@@ -257,6 +362,17 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
   L->opts = o;
   const int64_t nblk = (n + kPanel - 1) / kPanel;
   int64_t info = 0;
+  DevBuf cert;
+  if (o.certify) {  // norms of the assembled matrix, before an FP64 factorisation overwrites it
+    cert.alloc(6 * sizeof(double));
+    matrix_norms<double>(c, static_cast<const c128*>(Z), n, ldz, false, cert.as<double>());
+    double zn[3];
+    FOSB_HIP(hipMemcpyAsync(zn, cert.p, sizeof(zn), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+    L->z_max = zn[0];
+    L->z_fro = std::sqrt(zn[1]);
+    L->z_one = zn[2];
+  }
   if (precision == FOSB_PREC_FP64) {
     L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
     L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
@@ -277,6 +393,16 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
   }
   if (info != 0) fail(FOSB_E_SINGULAR, "exactly zero pivot at index %lld", (long long)(info - 1));
   upload(L->d_perm, L->perm, s);
+  if (o.certify) {  // growth factor max|U| / max|Z| of the stored factors
+    double un[3];
+    if (precision == FOSB_PREC_FP64)
+      matrix_norms<double>(c, static_cast<const c128*>(Z), n, ldz, true, cert.as<double>() + 3);
+    else
+      matrix_norms<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, true, cert.as<double>() + 3);
+    FOSB_HIP(hipMemcpyAsync(un, cert.as<double>() + 3, sizeof(un), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+    L->growth = L->z_max > 0 ? un[0] / L->z_max : 0.0;
+  }
   // quadrature nodes, first moments and RHS weights
   L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));
   quad_nodes(s, *mesh, L->qx.as<double>());
@@ -290,10 +416,38 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
   L->W.alloc((size_t)n_dirs * mesh->h.nt * 18 * sizeof(c128));
   for (int64_t d = 0; d < n_dirs; ++d)
     rhs_weights(s, *mesh, k, field, L->u.as<c128>() + d, n_dirs, L->W.as<c128>() + d * mesh->h.nt * 18);
+  if (o.certify) L->kappa1 = L->z_one * inverse_norm1_estimate(c, *L);
   FOSB_HIP(hipStreamSynchronize(s));
   return L;
 }
 
+
+// Device bytes a level keeps for its lifetime.
+static int64_t level_bytes(int64_t n, int64_t nt, int32_t precision, int64_t n_dirs) {
+  const int64_t nblk = (n + kPanel - 1) / kPanel;
+  const int64_t es = precision == FOSB_PREC_FP64 ? 16 : 8;
+  int64_t b = 4 * n + 2 * nblk * kPanel * kPanel * es + 18 * nt * 8 + 16 * n * n_dirs + 18 * nt * n_dirs * 16;
+  if (precision == FOSB_PREC_MIXED) b += 2 * ((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * 8;
+  return b;
+}
+
+// Largest work buffer bytes of a solve with nrhs right-hand sides (refined for MIXED).
+static int64_t solve_work_bytes(int64_t n, int32_t precision, int64_t nrhs) {
+  return precision == FOSB_PREC_FP64 ? 16 * n * nrhs : (4 * 16 + 2 * 8) * n * nrhs;
+}
+
+// Fails with FOSB_E_OOM, before any launch, when `need` bytes exceed the
+// device's free memory plus what the context's pools hold for reuse.
+static void check_device_memory(Context& ctx, int64_t need, const char* what) {
+  size_t free_b = 0, total_b = 0;
+  FOSB_HIP(hipMemGetInfo(&free_b, &total_b));
+  int64_t n_alloc = 0, cached = 0, live = 0;
+  pool_totals(ctx, n_alloc, cached, live);
+  const int64_t avail = (int64_t)free_b + cached;
+  if (need > avail)
+    fail(FOSB_E_OOM, "%s needs about %.2f GB of device memory; %.2f GB are free (%.2f GB of it cached by the context)",
+         what, need / 1e9, avail / 1e9, cached / 1e9);
+}
 
 static void check_pair(const fosb_context* ctx, const fosb_level* a, const fosb_level* b) {
   REQUIRE(a && b, "level is NULL");
@@ -343,7 +497,7 @@ static void check_far_field_args(const double* xhat, int64_t n_a, int32_t L0, in
 // maps are formed once.  Synchronises c's stream.
 static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t L0, int32_t L, void* const* blocks,
                            const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir0, int64_t nd, double* var,
-                           void* mean_F) {
+                           void* mean_F, void* cor = nullptr) {
   const int32_t n_levels = L - L0 + 1;
   hipStream_t s = c.stream;
   std::vector<double> x(xhat, xhat + 3 * n_a);
@@ -357,6 +511,10 @@ static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t 
     far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
   }
   FOSB_HIP(hipMemsetAsync(var, 0, nd * rows * sizeof(double), s));
+  if (cor) {
+    if (nd != 1) fail(FOSB_E_UNSUPPORTED, "the angular correlation is computed for one incidence at a time");
+    FOSB_HIP(hipMemsetAsync(cor, 0, 3 * n_a * n_a * sizeof(c128), s));
+  }
   // one product FF_l1 [Sigma_0 | Sigma_1 | ...] per pair covers every incidence
   int64_t maxn2 = 0;
   for (auto& q : v) maxn2 = std::max(maxn2, levels[q[1] - L0]->n);
@@ -369,6 +527,16 @@ static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t 
     for (int64_t d = 0; d < nd; ++d)
       row_dot_re_accumulate(s, P.as<c128>() + d * n2, nd * n2, FF[i2].as<c128>(), rows, n2,
                             (double)(v[p][2] * v[p][3]), var + d * rows);
+    if (cor) {  // per component c: (FF1 Sigma)_c FF2_c^H, with its conjugate transpose for l1 != l2
+      DevBuf F2h((size_t)n2 * rows * sizeof(c128)), T((size_t)n_a * n_a * sizeof(c128));
+      conj_transpose_c128(s, FF[i2].as<c128>(), n2, F2h.as<c128>(), rows, rows, n2);
+      for (int cc = 0; cc < 3; ++cc) {
+        gemm<double>(c, n_a, n_a, n2, 1.0, P.as<c128>() + cc * n_a * n2, n2, F2h.as<c128>() + cc * n_a, rows, 0.0,
+                     T.as<c128>(), n_a);
+        herm_accumulate(s, T.as<c128>(), n_a, n_a, (double)v[p][2], v[p][0] != v[p][1],
+                        static_cast<c128*>(cor) + cc * n_a * n_a, n_a);
+      }
+    }
   }
   if (mean_F) {
     const int iL = n_levels - 1;
@@ -427,7 +595,10 @@ static void shape_pipeline(Context& c, const fosb_mesh* const* meshes, int32_t n
     two_sided(c, a, b, C, ldb[p], st, n_dirs);
   }
   std::vector<const fosb_level*> lp(n_levels);
-  for (int32_t i = 0; i < n_levels; ++i) lp[i] = lv[i].get();
+  for (int32_t i = 0; i < n_levels; ++i) {
+    lp[i] = lv[i].get();
+    merge_level_certificate(st, *lv[i]);
+  }
   far_field_impl(c, lp.data(), L0, L, bp.data(), ldb.data(), xhat, n_a, 0, n_dirs, var, nullptr);
 }
 
@@ -482,6 +653,30 @@ fosb_status fosb_context_synchronize(fosb_context* ctx) {
   REQUIRE(ctx, "ctx is NULL");
   bind(*ctx);
   FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  API_END
+}
+
+fosb_status fosb_context_memory(fosb_context* ctx, int64_t* n_device_allocs, int64_t* bytes_cached,
+                                int64_t* bytes_in_use) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  int64_t a = 0, c = 0, l = 0;
+  pool_totals(*ctx, a, c, l);
+  if (n_device_allocs) *n_device_allocs = a;
+  if (bytes_cached) *bytes_cached = c;
+  if (bytes_in_use) *bytes_in_use = l;
+  API_END
+}
+
+fosb_status fosb_context_trim(fosb_context* ctx) {
+  API_BEGIN
+  REQUIRE(ctx, "ctx is NULL");
+  bind(*ctx);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->aux) FOSB_HIP(hipStreamSynchronize(ctx->aux->stream));
+  if (ctx->la) FOSB_HIP(hipStreamSynchronize(ctx->la->stream));
+  for (auto& w : ctx->workers) FOSB_HIP(hipStreamSynchronize(w->stream));
+  pool_trim(*ctx);
   API_END
 }
 
@@ -561,6 +756,10 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
   check_level_args(mesh, k, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, field);
   fosb_opts o = opts_or_default(opts);
   bind(*ctx);
+  check_device_memory(*ctx,
+                      level_bytes(mesh->h.ne, mesh->h.nt, precision, n_dirs) +
+                          solve_work_bytes(mesh->h.ne, precision, std::max<int64_t>(n_dirs, 256)),
+                      "the level");
   auto L = level_build(*ctx, mesh, k, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, field, o);
   {
     std::lock_guard<std::mutex> lock(ctx->reg_mu);
@@ -576,6 +775,26 @@ fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precis
   if (n) *n = level->n;
   if (precision) *precision = level->precision;
   if (n_dirs) *n_dirs = level->n_dirs;
+  API_END
+}
+
+fosb_status fosb_level_workspace_size(const fosb_mesh* mesh, int32_t precision, int64_t n_dirs, int64_t nrhs,
+                                      int64_t* level_b, int64_t* work_b) {
+  API_BEGIN
+  REQUIRE(mesh, "mesh is NULL");
+  REQUIRE(precision == FOSB_PREC_FP64 || precision == FOSB_PREC_MIXED, "unknown precision %d", precision);
+  REQUIRE(n_dirs >= 1 && n_dirs <= 4096, "need 1..4096 incidence directions");
+  if (nrhs <= 0) nrhs = n_dirs;
+  if (level_b) *level_b = level_bytes(mesh->h.ne, mesh->h.nt, precision, n_dirs);
+  if (work_b) *work_b = std::max<int64_t>((int64_t)1 << 30, solve_work_bytes(mesh->h.ne, precision, nrhs));
+  API_END
+}
+
+fosb_status fosb_level_certificate(const fosb_level* level, double* kappa1, double* growth) {
+  API_BEGIN
+  REQUIRE(level, "level is NULL");
+  if (kappa1) *kappa1 = level->kappa1;
+  if (growth) *growth = level->growth;
   API_END
 }
 
@@ -711,7 +930,7 @@ fosb_status fosb_far_field_matrix(fosb_context* ctx, const fosb_level* level, co
 
 fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels, int32_t L0,
                                    int32_t L, void* const* blocks, const int64_t* ldb, const double* xhat,
-                                   int64_t n_a, int64_t dir, double* var, void* mean_F) {
+                                   int64_t n_a, int64_t dir, double* var, void* cor, void* mean_F) {
   API_BEGIN
   REQUIRE(ctx && levels && blocks && ldb && xhat && var, "NULL argument");
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
@@ -719,7 +938,8 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
   REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
   check_far_field_args(xhat, n_a, L0, L, levels, blocks, ldb);
   bind(*ctx);
-  far_field_impl(*ctx, levels, L0, L, blocks, ldb, xhat, n_a, dir, 1, var, mean_F);
+  if (cor) REQUIRE(n_a <= 4096, "the angular correlation takes at most 4096 angles");
+  far_field_impl(*ctx, levels, L0, L, blocks, ldb, xhat, n_a, dir, 1, var, mean_F, cor);
   API_END
 }
 
@@ -827,6 +1047,17 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   }
   const fosb_opts o = opts_or_default(opts);
   bind(*ctx);
+  {
+    int64_t need = (int64_t)1 << 30;  // assembly band
+    for (int32_t i = 0; i < n_levels; ++i) need += level_bytes(meshes[i]->h.ne, meshes[i]->h.nt, precision, n_dirs);
+    int64_t pair_max = 0;
+    for (auto& q : v) {
+      const int64_t n1 = meshes[q[0] - L0]->h.ne, n2 = meshes[q[1] - L0]->h.ne;
+      pair_max = std::max(pair_max, 16 * n1 * n2 * nd + solve_work_bytes(n1, precision, nd * n2) +
+                                        solve_work_bytes(n2, precision, nd * n1));
+    }
+    check_device_memory(*ctx, need + 2 * pair_max, "the pass");
+  }
   Context& aux = ctx->aux_context();
   const int top = n_levels - 1;
   std::vector<std::unique_ptr<fosb_level>> lv(n_levels);
@@ -865,8 +1096,9 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   bool coarse_ready = false;
   std::exception_ptr aux_err;
   std::thread worker([&] {
+    PoolRelease pool_release;
     try {
-      FOSB_HIP(hipSetDevice(ctx->device));
+      bind(aux);
       for (int i = top - 1; i >= 0; --i) build(aux, i);
     } catch (...) {
       aux_err = std::current_exception();
@@ -909,12 +1141,9 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
     lp[i] = lv[i].get();
   }
   far_field_impl(*ctx, lp.data(), L0, L, blocks, ldb, xhat, n_a, d0, nd, var, nullptr);
-  if (stats) {
-    stats->ir_sweeps = std::max(stats->ir_sweeps, std::max(st_main.ir_sweeps, st_aux.ir_sweeps));
-    stats->n_solves += st_main.n_solves + st_aux.n_solves;
-    stats->ir_rel_correction =
-        std::max(stats->ir_rel_correction, std::max(st_main.ir_rel_correction, st_aux.ir_rel_correction));
-  }
+  merge_stats(stats, st_main);
+  merge_stats(stats, st_aux);
+  for (int i = 0; i < n_levels; ++i) merge_level_certificate(stats, *lv[i]);
   if (levels_out) {
     std::lock_guard<std::mutex> lock(ctx->reg_mu);
     for (int i = 0; i < n_levels; ++i) {
@@ -963,8 +1192,9 @@ fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* 
   for (int w = 0; w < nw; ++w)
     pool.emplace_back([&, w] {
       Context& c = *ctx->workers[w];
+      PoolRelease pool_release;
       try {
-        FOSB_HIP(hipSetDevice(ctx->device));
+        bind(c);
         for (;;) {
           if (stop.load()) break;
           const int64_t s = next.fetch_add(1);
@@ -982,12 +1212,7 @@ fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* 
   for (auto& t : pool) t.join();
   for (auto& e : err)
     if (e) std::rethrow_exception(e);
-  if (stats)
-    for (const fosb_stats& x : st) {
-      stats->ir_sweeps = std::max(stats->ir_sweeps, x.ir_sweeps);
-      stats->n_solves += x.n_solves;
-      stats->ir_rel_correction = std::max(stats->ir_rel_correction, x.ir_rel_correction);
-    }
+  for (const fosb_stats& x : st) merge_stats(stats, x);
   API_END
 }
 

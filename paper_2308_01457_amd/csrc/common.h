@@ -46,31 +46,78 @@ using c128 = cplx<double>;
 using c64 = cplx<float>;
 
 // ------------------------------------------------------------------ device buffers
+// Caching device allocator of one context.  Every context runs its work on
+// one stream, so a block returned to its pool may be handed out again at once:
+// later work on that stream is ordered after the work that used it.  Blocks
+// are only returned to the device (hipFree, which synchronises the device) by
+// trim() or when the last owner of the pool goes away, so a pass repeated on
+// the same shapes allocates nothing after its first run.
+struct Pool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;  // cached blocks by capacity
+  size_t cached_bytes = 0;                   // capacity held in free_blocks
+  size_t live_bytes = 0;                     // capacity handed out and not returned
+  int64_t n_device_allocs = 0;               // hipMalloc calls made
+  void* get(size_t n, size_t& cap);
+  void put(void* p, size_t cap);
+  void trim();
+  ~Pool();
+};
+
+// The pool used by buffers that are not bound to one: that of the context
+// whose work the calling thread is enqueueing (set by bind_pool).
+std::shared_ptr<Pool>& thread_pool();
+
 struct DevBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;                 // requested size
+  size_t cap = 0;                   // capacity of the block
+  std::shared_ptr<Pool> home;       // pool this buffer always draws from (context members)
+  std::shared_ptr<Pool> from;       // pool the current block came from
   DevBuf() = default;
   explicit DevBuf(size_t n) { alloc(n); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept
+      : p(o.p), bytes(o.bytes), cap(o.cap), home(std::move(o.home)), from(std::move(o.from)) {
+    o.p = nullptr; o.bytes = o.cap = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; cap = o.cap; home = std::move(o.home); from = std::move(o.from);
+      o.p = nullptr; o.bytes = o.cap = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t n) {
     release();
     if (n == 0) return;
-    FOSB_HIP(hipMalloc(&p, n));
+    std::shared_ptr<Pool> pool = home ? home : thread_pool();
+    if (pool) {
+      p = pool->get(n, cap);
+      from = std::move(pool);
+    } else {
+      FOSB_HIP(hipMalloc(&p, n));
+      cap = n;
+    }
     bytes = n;
   }
-  // grow-only reallocation (contents are not preserved)
-  void reserve(size_t n) { if (n > bytes) alloc(n); }
+  // grow-only (contents are not preserved when it grows past the block's capacity)
+  void reserve(size_t n) {
+    if (n <= bytes) return;
+    if (p && n <= cap) { bytes = n; return; }
+    alloc(n);
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (from) from->put(p, cap);
+      else (void)hipFree(p);
+    }
     p = nullptr;
-    bytes = 0;
+    bytes = cap = 0;
+    from.reset();
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
@@ -90,6 +137,8 @@ struct ProfRec {
 
 // ------------------------------------------------------------------ context
 struct Context {
+  std::shared_ptr<Pool> pool = std::make_shared<Pool>();   // declared first: destroyed last
+  Context();
   int device = 0;
   hipStream_t stream = nullptr;
   int n_cu = 256;
@@ -148,6 +197,12 @@ struct Context {
   Context& worker_context(size_t i);
   ~Context();
 };
+
+// Makes ctx's pool the calling thread's pool (thread_pool()).
+void bind_pool(Context& ctx);
+// Sums of the pool counters of a context and its auxiliary, update and worker contexts.
+void pool_totals(Context& ctx, int64_t& n_allocs, int64_t& cached, int64_t& live);
+void pool_trim(Context& ctx);
 
 // Brackets the launches issued during its lifetime with a pair of events when
 // the context's profiler is on.
@@ -234,6 +289,8 @@ struct Level {
   DevBuf u;                    // c128 [n_dirs][n]
   DevBuf W;                    // c128 [n_dirs][nt][3][6] RHS weights
   DevBuf qx;                   // double [3][6*nt] quadrature nodes (component-major)
+  // certificate (opts.certify): norms of the assembled Z, condition estimate, growth factor
+  double z_max = 0, z_fro = 0, z_one = 0, kappa1 = 0, growth = 0;
   const void* lu() const { return precision == FOSB_PREC_FP64 ? Z : Zlow; }
 };
 
@@ -331,6 +388,14 @@ void adjoint_nodes(hipStream_t s, const Mesh& m, const c128* W, const c128* B, i
 int64_t cov_grad_partials(hipStream_t s, const c128* G, int64_t a0, int64_t na, const Level& l1, const Level& l2,
                           const fosb_cov& cov, double scale, double* partial);
 void cov_grad_finish(hipStream_t s, const double* partial, int64_t n, double sigma, double* out);
+
+// out (device, 3 doubles): max |a_ij|, sum |a_ij|^2 and max_j sum_i |a_ij| of an
+// n x n complex matrix, over its upper triangle only when upper is set
+template <typename T>
+void matrix_norms(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, bool upper, double* out);
+// out (n x n) += scale * (T + T^H if both, else T), T n x n (row strides ldt, ldo)
+void herm_accumulate(hipStream_t s, const c128* T, int64_t ldt, int64_t n, double scale, bool both, c128* out,
+                     int64_t ldo);
 
 // level-wide solves (api.cpp helpers)
 // B <- Z^{-1} B, or B <- Z^{-H} B (adjoint)

@@ -75,12 +75,22 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   return m;
 }
 
-// Pivot-search key of a candidate: the bits of float(|re| + |im|) plus one.
-// Non-negative floats order like their bit patterns, so keys order like the
-// moduli; 0 is left for rows that are not candidates.
-template <typename T>
-__device__ __forceinline__ unsigned pivot_key(cplx<T> v) {
-  return (__float_as_uint((float)cabs1(v)) & 0x7fffffffu) + 1u;
+// Pivot-search key of a candidate, a 32-bit value that orders like the
+// modulus |re| + |im|: 1 for an exact zero, at least 2 for any nonzero entry,
+// and 0 is left for rows that are not candidates.  Non-negative floating-point
+// numbers order like their bit patterns.  FP32: the bits of the modulus plus
+// one.  FP64: the upper 32 bits of the modulus (sign, exponent and 20 mantissa
+// bits), so moduli that agree to 2^-20 tie (the lowest row wins, within that
+// relative distance of the largest) and no nonzero modulus, however small or
+// large, falls together with zero.
+__device__ __forceinline__ unsigned pivot_key(cplx<float> v) {
+  return (__float_as_uint(cabs1(v)) & 0x7fffffffu) + 1u;
+}
+__device__ __forceinline__ unsigned pivot_key(cplx<double> v) {
+  const double m = cabs1(v);
+  if (m == 0.0) return 1u;
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(m) >> 32) & 0x7fffffffu;
+  return (hi < 1u ? 1u : hi) + 1u;
 }
 
 // 1/a for the panel's multipliers: FP32 through the hardware reciprocal with
@@ -1188,6 +1198,103 @@ void norms2_c128(hipStream_t s, const c128* x, int64_t ldx, const c128* y, int64
   hipLaunchKernelGGL(k_norms2_finish, dim3(1), dim3(256), 0, s, (const double*)part, blocks, out);
   FOSB_LAUNCH_CHECK();
 }
+
+// ------------------------------------------------------------------ matrix norms (certificates)
+// Partial sums per (row chunk, column): thread = column (consecutive threads
+// read consecutive entries of a row), block y = chunk of rows.  Column sums of
+// |a| go to part1[chunk][col]; each block's sum of |a|^2 and max |a| go to
+// part2 / partmax[chunk][column block].  The finish kernel reduces in a fixed
+// order, so the result does not depend on scheduling.
+template <typename T>
+__global__ __launch_bounds__(256) void k_norm_partials(const cplx<T>* __restrict__ A, int64_t lda, int64_t n,
+                                                       int64_t rows_per_chunk, int upper, double* __restrict__ part1,
+                                                       double* __restrict__ part2, double* __restrict__ partmax) {
+  __shared__ double s2[256], sm[256];
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t r1 = min(n, r0 + rows_per_chunk);
+  double a1 = 0, a2 = 0, am = 0;
+  if (c < n) {
+    const int64_t rend = upper ? min(r1, c + 1) : r1;
+    for (int64_t r = r0; r < rend; ++r) {
+      const cplx<T> v = A[r * lda + c];
+      const double re = (double)v.re, im = (double)v.im;
+      const double m = sqrt(re * re + im * im);
+      a1 += m;
+      a2 += re * re + im * im;
+      am = fmax(am, m);
+    }
+    part1[(int64_t)blockIdx.y * n + c] = a1;
+  }
+  s2[threadIdx.x] = a2;
+  sm[threadIdx.x] = am;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part2[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s2[0];
+    partmax[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sm[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_norm_finish(const double* __restrict__ part1, const double* __restrict__ part2,
+                                                     const double* __restrict__ partmax, int64_t n, int nchunk,
+                                                     int ncb, double* __restrict__ out) {
+  __shared__ double s1[256], s2[256], sm[256];
+  double one = 0, fro = 0, mx = 0;
+  for (int64_t c = threadIdx.x; c < n; c += 256) {
+    double col = 0;
+    for (int k = 0; k < nchunk; ++k) col += part1[(int64_t)k * n + c];
+    one = fmax(one, col);
+  }
+  for (int64_t b = threadIdx.x; b < (int64_t)nchunk * ncb; b += 256) {
+    fro += part2[b];
+    mx = fmax(mx, partmax[b]);
+  }
+  s1[threadIdx.x] = one;
+  s2[threadIdx.x] = fro;
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + o]);
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sm[0];
+    out[1] = s2[0];
+    out[2] = s1[0];
+  }
+}
+
+template <typename T>
+void matrix_norms(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, bool upper, double* out) {
+  if (n <= 0) fail(FOSB_E_INVALID, "matrix_norms: empty matrix");
+  const int ncb = (int)((n + 255) / 256);
+  const int nchunk = (int)std::min<int64_t>(32, n);
+  const int64_t rpc = (n + nchunk - 1) / nchunk;
+  DevBuf part((size_t)(n * nchunk + 2 * (int64_t)nchunk * ncb) * sizeof(double));
+  double* p1 = part.as<double>();
+  double* p2 = p1 + n * nchunk;
+  double* pm = p2 + (int64_t)nchunk * ncb;
+  hipLaunchKernelGGL(k_norm_partials<T>, dim3((unsigned)ncb, (unsigned)nchunk), dim3(256), 0, ctx.stream, A, lda, n,
+                     rpc, upper ? 1 : 0, p1, p2, pm);
+  FOSB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(256), 0, ctx.stream, (const double*)p1, (const double*)p2,
+                     (const double*)pm, n, nchunk, ncb, out);
+  FOSB_LAUNCH_CHECK();
+}
+
+template void matrix_norms<float>(Context&, const c64*, int64_t, int64_t, bool, double*);
+template void matrix_norms<double>(Context&, const c128*, int64_t, int64_t, bool, double*);
 
 // ------------------------------------------------------------------ solves with block inverses
 static_assert(NL == kInvBlock, "inverse block size");

@@ -449,6 +449,35 @@ void row_dot_re_accumulate(hipStream_t s, const c128* P, int64_t ldp, const c128
   FOSB_LAUNCH_CHECK();
 }
 
+// out[i][j] += scale * (T[i][j] + conj T[j][i] when both): the combination of
+// a pair's angular correlation block with that of its transposed pair.
+__global__ __launch_bounds__(256) void k_herm_accumulate(const c128* __restrict__ T, int64_t ldt, int64_t n,
+                                                         double scale, int both, c128* __restrict__ out,
+                                                         int64_t ldo) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j >= n) return;
+  c128 a = T[i * ldt + j];
+  if (both) {
+    const c128 b = T[j * ldt + i];
+    a.re += b.re;
+    a.im -= b.im;
+  }
+  c128 o = out[i * ldo + j];
+  o.re += scale * a.re;
+  o.im += scale * a.im;
+  out[i * ldo + j] = o;
+}
+
+void herm_accumulate(hipStream_t s, const c128* T, int64_t ldt, int64_t n, double scale, bool both, c128* out,
+                     int64_t ldo) {
+  if (n <= 0) return;
+  if (n > 65535) fail(FOSB_E_UNSUPPORTED, "correlation of more than 65535 angles");
+  hipLaunchKernelGGL(k_herm_accumulate, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, T, ldt, n,
+                     scale, both ? 1 : 0, out, ldo);
+  FOSB_LAUNCH_CHECK();
+}
+
 __global__ __launch_bounds__(256) void k_matvec_rows(const c128* __restrict__ FF, int64_t n, const c128* __restrict__ u,
                                                      c128* __restrict__ out) {
   __shared__ double sr[256], si[256];

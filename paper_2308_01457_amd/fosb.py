@@ -35,7 +35,8 @@ class FosbError(RuntimeError):
 
 
 class Opts(C.Structure):
-    _fields_ = [("n_gauss_singular", C.c_int32), ("ir_max_sweeps", C.c_int32), ("ir_tol", C.c_double)]
+    _fields_ = [("n_gauss_singular", C.c_int32), ("ir_max_sweeps", C.c_int32), ("ir_tol", C.c_double),
+                ("certify", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Cov(C.Structure):
@@ -43,7 +44,8 @@ class Cov(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("ir_sweeps", C.c_int32), ("n_solves", C.c_int32), ("ir_rel_correction", C.c_double)]
+    _fields_ = [("ir_sweeps", C.c_int32), ("n_solves", C.c_int32), ("ir_rel_correction", C.c_double),
+                ("backward_error", C.c_double), ("kappa1", C.c_double), ("growth", C.c_double)]
 
 
 class BatchShape(C.Structure):
@@ -62,6 +64,8 @@ _SIGS = {
     "fosb_context_create": (C.c_int, [_I32, _P, C.POINTER(_P)]),
     "fosb_context_destroy": (C.c_int, [_P]),
     "fosb_context_synchronize": (C.c_int, [_P]),
+    "fosb_context_memory": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "fosb_context_trim": (C.c_int, [_P]),
     "fosb_mesh_validate": (C.c_int, [_P, _I64, _P, _I64, C.POINTER(_I64)]),
     "fosb_mesh_create": (C.c_int, [_P, _P, _I64, _P, _I64, C.POINTER(_P)]),
     "fosb_mesh_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
@@ -70,6 +74,8 @@ _SIGS = {
     "fosb_level_create": (C.c_int, [_P, _P, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64, _I32, C.POINTER(Opts),
                                     C.POINTER(_P)]),
     "fosb_level_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
+    "fosb_level_workspace_size": (C.c_int, [_P, _I32, _I64, _I64, C.POINTER(_I64), C.POINTER(_I64)]),
+    "fosb_level_certificate": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_D)]),
     "fosb_level_solve": (C.c_int, [_P, _P, _P, _I64, _I64, C.POINTER(Stats)]),
     "fosb_level_solve_adjoint": (C.c_int, [_P, _P, _P, _I64, _I64, C.POINTER(Stats)]),
     "fosb_level_first_moment": (C.c_int, [_P, _P, _I64, _P]),
@@ -82,7 +88,7 @@ _SIGS = {
                                    C.POINTER(_I64), C.POINTER(Stats)]),
     "fosb_far_field_matrix": (C.c_int, [_P, _P, _P, _I64, _P]),
     "fosb_far_field_moments": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64), _P,
-                                         _I64, _I64, _P, _P]),
+                                         _I64, _I64, _P, _P, _P]),
     "fosb_far_field_moments_backward": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
                                                   _I64, _P, _P, C.POINTER(Stats)]),
     "fosb_second_moment": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, _D, _I32, C.POINTER(_P), C.POINTER(_I64),
@@ -152,6 +158,13 @@ def opts_default(**kw) -> Opts:
     return o
 
 
+def level_workspace_size(mesh: "Mesh", precision: int, n_dirs: int = 1, nrhs: int = 0) -> tuple[int, int]:
+    """fosb_level_workspace_size: (bytes a level keeps, largest work buffer bytes)."""
+    a, b = _I64(), _I64()
+    _check(lib().fosb_level_workspace_size(mesh.h, precision, n_dirs, nrhs, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
 def mesh_validate(V, F) -> int:
     """Host-only validation; returns the number of RWG functions (edges)."""
     V = _host_f64(V)
@@ -183,6 +196,15 @@ class Context:
 
     def synchronize(self):
         _check(lib().fosb_context_synchronize(self.h))
+
+    def memory(self) -> dict:
+        """fosb_context_memory: device allocations made, bytes cached for reuse, bytes in use."""
+        a, c, u = _I64(), _I64(), _I64()
+        _check(lib().fosb_context_memory(self.h, C.byref(a), C.byref(c), C.byref(u)))
+        return {"n_device_allocs": a.value, "bytes_cached": c.value, "bytes_in_use": u.value}
+
+    def trim(self):
+        _check(lib().fosb_context_trim(self.h))
 
     def close(self):
         if getattr(self, "h", None):
@@ -327,6 +349,12 @@ class Level:
                                               B2.shape[1], C.byref(st)))
         return B
 
+    def certificate(self) -> tuple[float, float]:
+        """fosb_level_certificate: (1-norm condition estimate, growth factor); 0 without opts.certify."""
+        k, g = _D(), _D()
+        _check(lib().fosb_level_certificate(self.h, C.byref(k), C.byref(g)))
+        return k.value, g.value
+
     def first_moment(self, dir: int = 0):
         import torch
         u = torch.empty(self.n, dtype=torch.complex128, device=self.ctx.torch_device)
@@ -396,20 +424,28 @@ def far_field_matrix(ctx: Context, level: Level, xhat):
 
 
 def far_field_moments(ctx: Context, levels: list[Level], L0: int, L: int, blocks, xhat, dir: int = 0,
-                      with_mean: bool = False):
-    """CT far-field variance (3, n_a) float64 on device [and the finest level's mean far field (3, n_a)]."""
+                      with_mean: bool = False, with_cor: bool = False):
+    """CT far-field variance (3, n_a) float64 on device, followed, when asked,
+    by the angular correlation (3, n_a, n_a) complex128 and the finest level's
+    mean far field (3, n_a)."""
     import torch
     x = _host_f64(xhat).reshape(-1, 3)
     n_a = x.shape[0]
     var = torch.empty(3 * n_a, dtype=torch.float64, device=ctx.torch_device)
     mean = torch.empty(3 * n_a, dtype=torch.complex128, device=ctx.torch_device) if with_mean else None
+    cor = torch.empty((3, n_a, n_a), dtype=torch.complex128, device=ctx.torch_device) if with_cor else None
     lv = (_P * len(levels))(*[l.h for l in levels])
     bp = (_P * len(blocks))(*[_dev(b, torch.complex128) for b in blocks])
     ld = (_I64 * len(blocks))(*[b.stride(0) for b in blocks])
     _check(lib().fosb_far_field_moments(ctx.h, lv, len(levels), L0, L, bp, ld, x.ctypes.data_as(_P), n_a, dir,
-                                        _dev(var, torch.float64), _dev(mean) if mean is not None else None))
-    var = var.view(3, n_a)
-    return (var, mean.view(3, n_a)) if with_mean else var
+                                        _dev(var, torch.float64), _dev(cor) if cor is not None else None,
+                                        _dev(mean) if mean is not None else None))
+    out = [var.view(3, n_a)]
+    if with_cor:
+        out.append(cor)
+    if with_mean:
+        out.append(mean.view(3, n_a))
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def far_field_moments_backward(ctx: Context, levels: list[Level], L0: int, L: int, cov: Cov, xhat, dvar,

@@ -152,3 +152,33 @@ def test_gradient_full_size_finite_difference(fz):
     print(f"[gpu]   mixed dsigma {g32[0]:.8e} dell {g32[1]:.8e}", flush=True)
     assert abs(g32[0] - dsig) < 1e-5 * abs(dsig)
     assert abs(g32[1] - dell) < 1e-5 * abs(dell)
+
+
+def test_gradient_full_size_against_oracle_golden(fz):
+    """Differentiated workload (s = 1..4, k = 3, L0 = 1, L = 4, 91 angles)
+    against tests/golden/grad_k3_oracle.json, written by
+    make_grad_k3_golden.py from the FP64 oracle alone: S, dS/dsigma and
+    dS/dell to 1e-6 (FP64 path) and 1e-5 (mixed path), and the variance."""
+    fosb, ctx, torch = fz
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_k3_oracle.json")) as f:
+        gold = json.load(f)
+    w = workloads.workload("grad_k3")
+    xh = w.angles
+    Vo = np.asarray(gold["variance"])
+    ones = torch.ones((3, w.n_angles), dtype=torch.float64, device=ctx.torch_device)
+    cov = fosb.make_cov(w.cov_kind, w.sigma, w.ell)
+    for prec, name, tol in ((fosb.FP64, "fp64", 1e-6), (fosb.MIXED, "mixed", 1e-5)):
+        print(f"[gpu] grad_k3 {name} against the oracle golden", flush=True)
+        lv = _levels(fosb, ctx, w.meshes, w.k, prec)
+        blocks = fosb.correlation(ctx, lv, w.L0, w.L, cov)
+        var = fosb.far_field_moments(ctx, lv, w.L0, w.L, blocks, xh).cpu().numpy()
+        del blocks
+        dsig, dell, S = fosb.far_field_moments_backward(ctx, lv, w.L0, w.L, cov, xh, ones).cpu().numpy()
+        ev = float(np.linalg.norm(var - Vo) / np.linalg.norm(Vo))
+        es = abs(S - gold["S"]) / abs(gold["S"])
+        eg = max(abs(dsig - gold["dS_dsigma"]) / abs(gold["dS_dsigma"]), abs(dell - gold["dS_dell"]) / abs(gold["dS_dell"]))
+        print(f"[gpu]   variance {ev:.2e}  S {es:.2e}  gradient {eg:.2e}", flush=True)
+        assert ev < tol and es < tol and eg < tol
+        del lv
