@@ -275,6 +275,30 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
                                    const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir,
                                    double* var, void* cor, void* mean_F);
 
+/* Bytes of the per-GPU work array of fosb_far_field_moments_noalloc. */
+#define FOSB_NOALLOC_SCRATCH_BYTES (64LL << 20)
+
+/* Allocation-free variant of fosb_far_field_moments, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, layouts and results (var, and
+ * mean_F if not NULL; no angular correlation), computed by the same kernels,
+ * except that the complex GEMMs neither split K nor time tile shapes, so the
+ * values may differ from fosb_far_field_moments in the last bits.  The call
+ * makes no device allocation and frees nothing: its far-field maps, products
+ * and the copies of xhat and of the first moment live in a file-scope device
+ * array of FOSB_NOALLOC_SCRATCH_BYTES that each GPU holds from the first
+ * fosb_context_create on it until the process ends.  The angles are processed
+ * in chunks that fit that array; FOSB_E_WORKSPACE when a single angle does not
+ * fit (3 (N_l1 + 2 N_l2) complex128 values of a pair, or 3 N_L + N_L for the
+ * mean field, plus the 3 n_a angle coordinates).  Every call on one GPU uses
+ * the same array and leaves its last contents there; var is cleared by a
+ * kernel before it accumulates.  Calls that overlap on one GPU (other host
+ * threads, other contexts or streams of the same device) race on the array
+ * and must be serialised by the caller.  Synchronises the context's stream. */
+fosb_status fosb_far_field_moments_noalloc(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                                           int32_t L0, int32_t L, void* const* blocks, const int64_t* ldb,
+                                           const double* xhat, int64_t n_a, int64_t dir, double* var, void* mean_F);
+
 /* Adjoint of the combination-technique variance with respect to the
  * covariance parameters.  With upstream weights g = dvar (device, 3 n_a
  * float64, same layout as var) and S = sum_r g_r var_r:

@@ -630,6 +630,7 @@ fosb_status fosb_context_create(int32_t device, void* hip_stream, fosb_context**
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->n_cu = prop.multiProcessorCount;
   c->max_lds = prop.sharedMemPerBlock;
+  noalloc_scratch_init(device);  // once per device: the allocation-free entry point's array
   *out = c.release();
   API_END
 }
@@ -940,6 +941,77 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
   bind(*ctx);
   if (cor) REQUIRE(n_a <= 4096, "the angular correlation takes at most 4096 angles");
   far_field_impl(*ctx, levels, L0, L, blocks, ldb, xhat, n_a, dir, 1, var, mean_F, cor);
+  API_END
+}
+
+fosb_status fosb_far_field_moments_noalloc(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                                           int32_t L0, int32_t L, void* const* blocks, const int64_t* ldb,
+                                           const double* xhat, int64_t n_a, int64_t dir, double* var, void* mean_F) {
+  API_BEGIN
+  REQUIRE(ctx && levels && blocks && ldb && xhat && var, "NULL argument");
+  REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
+  check_far_field_args(xhat, n_a, L0, L, levels, blocks, ldb);
+  bind(*ctx);
+  // scratch layout: [xhat 3 n_a][first moment N_L (mean field only)][work]
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t total = (int64_t)FOSB_NOALLOC_SCRATCH_BYTES;
+  const int64_t nL = levels[n_levels - 1]->n;
+  const int64_t xb = up(3 * n_a * (int64_t)sizeof(double));
+  const int64_t ub = mean_F ? up(nL * (int64_t)sizeof(c128)) : 0;
+  const int64_t work = total - xb - ub;
+  auto v = ct_pairs_vec(L0, L);
+  int64_t per_angle = mean_F ? 3 * nL * (int64_t)sizeof(c128) : 0;
+  for (auto& q : v)
+    per_angle = std::max(per_angle, 3 * (levels[q[0] - L0]->n + 2 * levels[q[1] - L0]->n) * (int64_t)sizeof(c128));
+  if (work < per_angle)
+    fail(FOSB_E_WORKSPACE, "one angle needs %lld bytes of work memory; the allocation-free array leaves %lld",
+         (long long)per_angle, (long long)std::max<int64_t>(work, 0));
+  struct NoAlloc {  // no device allocation and no allocating GEMM mode while this call runs
+    Context& c;
+    explicit NoAlloc(Context& cc) : c(cc) { thread_no_alloc() = true; c.no_alloc = 1; }
+    ~NoAlloc() { thread_no_alloc() = false; c.no_alloc = 0; }
+  } guard(*ctx);
+  hipStream_t s = ctx->stream;
+  unsigned char* base = static_cast<unsigned char*>(noalloc_scratch(ctx->device));
+  double* dx = reinterpret_cast<double*>(base);
+  c128* du = reinterpret_cast<c128*>(base + xb);
+  c128* W = reinterpret_cast<c128*>(base + xb + ub);
+  FOSB_HIP(hipMemcpyAsync(dx, xhat, 3 * n_a * sizeof(double), hipMemcpyHostToDevice, s));
+  const int64_t rows = 3 * n_a;
+  zero_f64(s, var, rows);
+  for (auto& q : v) {
+    const fosb_level& l1 = *levels[q[0] - L0];
+    const fosb_level& l2 = *levels[q[1] - L0];
+    const int64_t n1 = l1.n, n2 = l2.n;
+    const int64_t c = std::min<int64_t>(n_a, work / (3 * (n1 + 2 * n2) * (int64_t)sizeof(c128)));
+    const double scale = (double)(q[2] * q[3]);
+    for (int64_t i0 = 0; i0 < n_a; i0 += c) {
+      const int64_t cn = std::min(c, n_a - i0);
+      c128* F1 = W;                       // 3 cn x n1, row comp * cn + i
+      c128* F2 = F1 + 3 * cn * n1;        // 3 cn x n2
+      c128* P = F2 + 3 * cn * n2;         // 3 cn x n2
+      far_field_matrix_kernel(s, *l1.mesh, l1.k, dx + 3 * i0, cn, F1);
+      far_field_matrix_kernel(s, *l2.mesh, l2.k, dx + 3 * i0, cn, F2);
+      gemm<double>(*ctx, 3 * cn, n2, n1, 1.0, F1, n1, static_cast<const c128*>(blocks[&q - v.data()]),
+                   ldb[&q - v.data()], 0.0, P, n2);
+      for (int cc = 0; cc < 3; ++cc)
+        row_dot_re_accumulate(s, P + cc * cn * n2, n2, F2 + cc * cn * n2, cn, n2, scale, var + cc * n_a + i0);
+    }
+  }
+  if (mean_F) {
+    const fosb_level& lf = *levels[n_levels - 1];
+    copy_c128(s, lf.u.as<c128>() + dir, lf.n_dirs, du, 1, nL, 1);
+    const int64_t c = std::min<int64_t>(n_a, work / (3 * nL * (int64_t)sizeof(c128)));
+    for (int64_t i0 = 0; i0 < n_a; i0 += c) {
+      const int64_t cn = std::min(c, n_a - i0);
+      far_field_matrix_kernel(s, *lf.mesh, lf.k, dx + 3 * i0, cn, W);
+      for (int cc = 0; cc < 3; ++cc)
+        matvec_rows(s, W + cc * cn * nL, cn, nL, du, static_cast<c128*>(mean_F) + cc * n_a + i0);
+    }
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
   API_END
 }
 

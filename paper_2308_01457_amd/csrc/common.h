@@ -67,6 +67,9 @@ struct Pool {
 // The pool used by buffers that are not bound to one: that of the context
 // whose work the calling thread is enqueueing (set by bind_pool).
 std::shared_ptr<Pool>& thread_pool();
+// Set while the calling thread runs the allocation-free entry point: any
+// device buffer allocation then fails instead of reaching a pool or hipMalloc.
+bool& thread_no_alloc();
 
 struct DevBuf {
   void* p = nullptr;
@@ -94,6 +97,7 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) return;
+    if (thread_no_alloc()) fail(FOSB_E_DEVICE, "internal: device buffer of %zu bytes on the allocation-free path", n);
     std::shared_ptr<Pool> pool = home ? home : thread_pool();
     if (pool) {
       p = pool->get(n, cap);
@@ -166,6 +170,9 @@ struct Context {
   // register and LDS footprint instead of the tuned one (set while this
   // context's kernels share the chip with a saturating GEMM on another stream)
   int lean_tiles = 0;
+  // > 0: no GEMM on this context may allocate: split K and tile timing are off
+  // (a tuned size bucket keeps its tile, others take the first tile)
+  int no_alloc = 0;
   // > 0: this context runs the trailing update of a blocked LU; its large
   // complex64 GEMMs take the 64 x 64 tile instead of the tuned one
   int trailing_update = 0;
@@ -396,6 +403,15 @@ void matrix_norms(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, bool u
 // out (n x n) += scale * (T + T^H if both, else T), T n x n (row strides ldt, ldo)
 void herm_accumulate(hipStream_t s, const c128* T, int64_t ldt, int64_t n, double scale, bool both, c128* out,
                      int64_t ldo);
+
+// noalloc.hip: the allocation-free entry point's work memory (a file-scope
+// device array per GPU, FOSB_NOALLOC_SCRATCH_BYTES), its per-device set-up
+// (hipGetSymbolAddress, once per device, with that device current) and its
+// device address; and a zero fill that needs no memset node.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+void noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
+void zero_f64(hipStream_t s, double* p, int64_t n);
 
 // level-wide solves (api.cpp helpers)
 // B <- Z^{-1} B, or B <- Z^{-H} B (adjoint)

@@ -404,6 +404,7 @@ static int pick_variant(Context& ctx, int64_t M, int64_t N, int64_t K, const cpl
     auto it = root.tune.find(key);
     if (it != root.tune.end()) return it->second;
   }
+  if (ctx.no_alloc) return 0;  // no scratch output to time into
   ctx.tune_out.reserve((size_t)M * N * sizeof(cplx<T>));
   if (!ctx.tune_ev[0]) {
     FOSB_HIP(hipEventCreate(&ctx.tune_ev[0]));
@@ -459,7 +460,7 @@ static void gemm_launch(Context& ctx, int64_t M, int64_t N, int64_t K, double al
   const int64_t tiles = ((N + 63) / 64) * ((M + 63) / 64);
   int64_t nz = 1;
   const int64_t want = 2LL * ctx.n_cu;
-  if (tiles < want && Kp >= 512) nz = std::min<int64_t>({(want + tiles - 1) / tiles, Kp / 256, 64});
+  if (tiles < want && Kp >= 512 && !ctx.no_alloc) nz = std::min<int64_t>({(want + tiles - 1) / tiles, Kp / 256, 64});
   int64_t kc = Kp;
   cplx<T>* P = nullptr;
   if (nz > 1) {

@@ -93,6 +93,11 @@ std::shared_ptr<Pool>& thread_pool() {
 
 void bind_pool(Context& ctx) { thread_pool() = ctx.pool; }
 
+bool& thread_no_alloc() {
+  static thread_local bool flag = false;
+  return flag;
+}
+
 Context::Context() {
   for (DevBuf& b : scratch) b.home = pool;
   for (DevBuf& b : ss) b.home = pool;

@@ -89,6 +89,8 @@ _SIGS = {
     "fosb_far_field_matrix": (C.c_int, [_P, _P, _P, _I64, _P]),
     "fosb_far_field_moments": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64), _P,
                                          _I64, _I64, _P, _P, _P]),
+    "fosb_far_field_moments_noalloc": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64),
+                                                 _P, _I64, _I64, _P, _P]),
     "fosb_far_field_moments_backward": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
                                                   _I64, _P, _P, C.POINTER(Stats)]),
     "fosb_second_moment": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, _D, _I32, C.POINTER(_P), C.POINTER(_I64),
@@ -446,6 +448,21 @@ def far_field_moments(ctx: Context, levels: list[Level], L0: int, L: int, blocks
     if with_mean:
         out.append(mean.view(3, n_a))
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def far_field_moments_noalloc(ctx: Context, levels: list[Level], L0: int, L: int, blocks, xhat, var, dir: int = 0,
+                              mean=None):
+    """fosb_far_field_moments_noalloc into caller tensors: var (3 n_a) float64
+    and optionally mean (3 n_a) complex128, both on the device."""
+    import torch
+    x = _host_f64(xhat).reshape(-1, 3)
+    lv = (_P * len(levels))(*[l.h for l in levels])
+    bp = (_P * len(blocks))(*[_dev(b, torch.complex128) for b in blocks])
+    ld = (_I64 * len(blocks))(*[b.stride(0) for b in blocks])
+    _check(lib().fosb_far_field_moments_noalloc(ctx.h, lv, len(levels), L0, L, bp, ld, x.ctypes.data_as(_P),
+                                                x.shape[0], dir, _dev(var, torch.float64),
+                                                _dev(mean, torch.complex128) if mean is not None else None))
+    return var
 
 
 def far_field_moments_backward(ctx: Context, levels: list[Level], L0: int, L: int, cov: Cov, xhat, dvar,
