@@ -275,6 +275,25 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
                                    const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir,
                                    double* var, void* cor, void* mean_F);
 
+/* The same combination-technique variance (and optional mean field) by the
+ * adjoint route, without any Sigma block or pair solve.  The variance is
+ * linear in the right-hand-side correlation C = Wgt_l1 K Wgt_l2^H (FOA
+ * section, second-moment tensor equation; combination-technique
+ * sub-systems), so
+ *   var[r] = sum_{Lambda_H} sign mult Re sum_{q,q'} P_l1[r][q] K(x_q, y_q') conj(P_l2[r][q']),
+ *   P_l = FF_l Z_l^{-1} Wgt_l  (3 n_a x Q_l, Q_l = 6 triangles),
+ * with P_l from one adjoint solve Z_l^{-H} FF_l^H (3 n_a right-hand sides) per
+ * level.  For 3 n_a well below N this replaces the pair solves (N_l2 and N_l1
+ * right-hand sides per pair) by per-level solves; the covariance is formed
+ * in row chunks of at most 2^26 entries and contracted by FP64 GEMMs.
+ * Arguments and layouts as for fosb_far_field_moments_backward (var: device,
+ * 3 n_a float64; mean_F: device, 3 n_a complex128, may be NULL); the levels
+ * must still hold their factors.  Equals fosb_correlation followed by
+ * fosb_far_field_moments up to rounding. */
+fosb_status fosb_far_field_variance_adjoint(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                                            int32_t L0, int32_t L, const fosb_cov* cov, const double* xhat,
+                                            int64_t n_a, int64_t dir, double* var, void* mean_F, fosb_stats* stats);
+
 /* Bytes of the per-GPU work array of fosb_far_field_moments_noalloc. */
 #define FOSB_NOALLOC_SCRATCH_BYTES (64LL << 20)
 

@@ -250,6 +250,20 @@ def adjoint_maps(l: Level, xh: np.ndarray) -> np.ndarray:
     return np.asarray((l.Wgt.T @ R.T).T)
 
 
+def variance_adjoint_route(levels: dict[int, Level], L0: int, L: int, kind: str, sigma: float, ell: float,
+                           xh: np.ndarray) -> np.ndarray:
+    """CT far-field variance (3, n_a) without Sigma blocks: V is linear in
+    C = Wgt1 K Wgt2^H, so with P_l = FF_l Z_l^{-1} Wgt_l
+        V_r = sum_pairs sign*mult*Re (P_l1 K P_l2^H)[r, r]."""
+    P = {s: adjoint_maps(levels[s], xh) for s in levels}
+    V = np.zeros(3 * xh.shape[0])
+    for l1, l2, sgn, mult in ct_pairs(L0, L):
+        a, b = levels[l1], levels[l2]
+        K = covariance(kind, sigma, ell, a.X, a.Nq, b.X, b.Nq)
+        V += sgn * mult * np.real(np.sum((P[l1] @ K) * P[l2].conj(), axis=1))
+    return V.reshape(3, -1)
+
+
 def summed_variance_and_gradient(levels: dict[int, Level], L0: int, L: int, kind: str, sigma: float,
                                  ell: float, xh: np.ndarray, weights: np.ndarray | None = None):
     """S = sum_{c,i} g_{c,i} V_c(x_i) (g = 1 unless weights (3, n_a) are given)

@@ -422,6 +422,22 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
 }
 
 
+// Hn (Q x R, R = 3 n_a) = (FF Z^{-1} Wgt_dir)^T: the rows of the map from the
+// values of the perturbation amplitude at the level's quadrature nodes to the
+// far field of the shape derivative, from one adjoint solve Z^{-H} FF^H with
+// R right-hand sides.  dx: device angles (n_a x 3).
+static void adjoint_node_rows(Context& c, const Level& l, const double* dx, int64_t n_a, int64_t dir, DevBuf& Hn,
+                              fosb_stats* st) {
+  hipStream_t s = c.stream;
+  const int64_t R = 3 * n_a, N = l.n, Q = 6LL * l.mesh->h.nt;
+  DevBuf FF((size_t)R * N * sizeof(c128)), Y((size_t)N * R * sizeof(c128));
+  far_field_matrix_kernel(s, *l.mesh, l.k, dx, n_a, FF.as<c128>());
+  conj_transpose_c128(s, FF.as<c128>(), N, Y.as<c128>(), R, R, N);   // Y = FF^H (N x R)
+  level_solve_inplace(c, l, Y.as<c128>(), R, R, st, true);           // Y = Z^{-H} FF^H
+  Hn.alloc((size_t)Q * R * sizeof(c128));
+  adjoint_nodes(s, *l.mesh, l.W.as<c128>() + dir * l.mesh->h.nt * 18, Y.as<c128>(), R, Hn.as<c128>());
+}
+
 // Device bytes a level keeps for its lifetime.
 static int64_t level_bytes(int64_t n, int64_t nt, int32_t precision, int64_t n_dirs) {
   const int64_t nblk = (n + kPanel - 1) / kPanel;
@@ -944,6 +960,67 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
   API_END
 }
 
+fosb_status fosb_far_field_variance_adjoint(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                                            int32_t L0, int32_t L, const fosb_cov* cov, const double* xhat,
+                                            int64_t n_a, int64_t dir, double* var, void* mean_F, fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && levels && xhat && var, "NULL argument");
+  REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  check_cov(cov);
+  for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
+  for (int64_t i = 0; i < n_a; ++i) {
+    double nn = xhat[3 * i] * xhat[3 * i] + xhat[3 * i + 1] * xhat[3 * i + 1] + xhat[3 * i + 2] * xhat[3 * i + 2];
+    REQUIRE(std::fabs(nn - 1.0) < 1e-9, "xhat[%lld] is not a unit vector", (long long)i);
+  }
+  bind(*ctx);
+  hipStream_t s = ctx->stream;
+  std::vector<double> x(xhat, xhat + 3 * n_a);
+  DevBuf dx;
+  upload(dx, x, s);
+  const int64_t R = 3 * n_a;
+  std::vector<DevBuf> Hn(n_levels), Hc(n_levels);
+  for (int32_t i = 0; i < n_levels; ++i) {
+    const fosb_level& l = *levels[i];
+    const int64_t Q = 6LL * l.mesh->h.nt;
+    adjoint_node_rows(*ctx, l, dx.as<double>(), n_a, dir, Hn[i], stats);   // P_l^T
+    Hc[i].alloc((size_t)Q * R * sizeof(c128));
+    copy_c128(s, Hn[i].as<c128>(), R, Hc[i].as<c128>(), R, Q, R);
+    conj_inplace_c128(s, Hc[i].as<c128>(), Q * R);                          // conj(P_l)^T
+  }
+  zero_f64(s, var, R);
+  // V_r = sum sign mult Re sum_q1 P_l1[r][q1] T[q1][r],  T = K_l1l2 conj(P_l2)^T, in row chunks of K
+  auto v = ct_pairs_vec(L0, L);
+  const int64_t budget = (int64_t)1 << 26;
+  DevBuf Kc, T, part;
+  for (auto& q : v) {
+    const fosb_level& l1 = *levels[q[0] - L0];
+    const fosb_level& l2 = *levels[q[1] - L0];
+    const int64_t Q1 = 6LL * l1.mesh->h.nt, Q2 = 6LL * l2.mesh->h.nt;
+    const int64_t ch = std::min<int64_t>(Q1, std::max<int64_t>(256, budget / Q2) / 256 * 256);
+    Kc.reserve((size_t)ch * Q2 * sizeof(c128));
+    T.reserve((size_t)ch * R * sizeof(c128));
+    part.reserve((size_t)((ch + 255) / 256) * R * sizeof(double));
+    for (int64_t a0 = 0; a0 < Q1; a0 += ch) {
+      const int64_t na = std::min(ch, Q1 - a0);
+      cov_matrix(s, l1, l2, *cov, a0, na, Kc.as<c128>());
+      gemm<double>(*ctx, na, R, Q2, 1.0, Kc.as<c128>(), Q2, Hc[q[1] - L0].as<c128>(), R, 0.0, T.as<c128>(), R);
+      coldot_re_accumulate(s, Hn[q[0] - L0].as<c128>() + a0 * R, T.as<c128>(), na, R, (double)(q[2] * q[3]),
+                           part.as<double>(), var);
+    }
+  }
+  if (mean_F) {
+    const fosb_level& lf = *levels[n_levels - 1];
+    DevBuf FF((size_t)R * lf.n * sizeof(c128)), u((size_t)lf.n * sizeof(c128));
+    far_field_matrix_kernel(s, *lf.mesh, lf.k, dx.as<double>(), n_a, FF.as<c128>());
+    copy_c128(s, lf.u.as<c128>() + dir, lf.n_dirs, u.as<c128>(), 1, lf.n, 1);
+    matvec_rows(s, FF.as<c128>(), R, lf.n, u.as<c128>(), static_cast<c128*>(mean_F));
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
 fosb_status fosb_far_field_moments_noalloc(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
                                            int32_t L0, int32_t L, void* const* blocks, const int64_t* ldb,
                                            const double* xhat, int64_t n_a, int64_t dir, double* var, void* mean_F) {
@@ -1038,23 +1115,14 @@ fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level*
   const int64_t R = 3 * n_a;
   // per level: Hn = (FF Z^{-1} Wgt)^T (Q x R) and Bg = diag(g) conj(FF Z^{-1} Wgt) (R x Q)
   std::vector<DevBuf> Hn(n_levels), Bg(n_levels);
-  {
-    DevBuf FF, Y;
-    for (int32_t i = 0; i < n_levels; ++i) {
-      const fosb_level& l = *levels[i];
-      const int64_t N = l.n, Q = 6LL * l.mesh->h.nt;
-      FF.reserve((size_t)R * N * sizeof(c128));
-      Y.reserve((size_t)N * R * sizeof(c128));
-      far_field_matrix_kernel(s, *l.mesh, l.k, dx.as<double>(), n_a, FF.as<c128>());
-      conj_transpose_c128(s, FF.as<c128>(), N, Y.as<c128>(), R, R, N);           // Y = FF^H (N x R)
-      level_solve_inplace(*ctx, l, Y.as<c128>(), R, R, stats, true);           // Y = Z^{-H} FF^H
-      Hn[i].alloc((size_t)Q * R * sizeof(c128));
-      Bg[i].alloc((size_t)R * Q * sizeof(c128));
-      adjoint_nodes(s, *l.mesh, l.W.as<c128>() + dir * l.mesh->h.nt * 18, Y.as<c128>(), R, Hn[i].as<c128>());
-      conj_transpose_c128(s, Hn[i].as<c128>(), R, Bg[i].as<c128>(), Q, Q, R, dvar);
-    }
-    FOSB_HIP(hipStreamSynchronize(s));
+  for (int32_t i = 0; i < n_levels; ++i) {
+    const fosb_level& l = *levels[i];
+    const int64_t Q = 6LL * l.mesh->h.nt;
+    adjoint_node_rows(*ctx, l, dx.as<double>(), n_a, dir, Hn[i], stats);
+    Bg[i].alloc((size_t)R * Q * sizeof(c128));
+    conj_transpose_c128(s, Hn[i].as<c128>(), R, Bg[i].as<c128>(), Q, Q, R, dvar);
   }
+  FOSB_HIP(hipStreamSynchronize(s));
   // G = Hn_l1 Bg_l2 in row chunks of at most 2^26 entries, reduced against the covariance
   auto v = ct_pairs_vec(L0, L);
   const int64_t budget = (int64_t)1 << 26;

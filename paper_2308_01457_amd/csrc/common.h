@@ -364,6 +364,7 @@ void copy_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t l
 // dst = diag(row_scale) src^H (row_scale: device, one per dst row, or nullptr)
 void conj_transpose_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows,
                          int64_t cols, const double* row_scale = nullptr);
+void conj_inplace_c128(hipStream_t s, c128* x, int64_t n);
 void axpy_c128(hipStream_t s, const c128* x, int64_t ldx, c128* y, int64_t ldy, int64_t rows, int64_t cols);
 // squared Frobenius norms of x and of y (two doubles written to out, device);
 // out has room for 2 + 2 * kNormBlocks doubles (per-block partial sums follow
@@ -395,6 +396,12 @@ void adjoint_nodes(hipStream_t s, const Mesh& m, const c128* W, const c128* B, i
 int64_t cov_grad_partials(hipStream_t s, const c128* G, int64_t a0, int64_t na, const Level& l1, const Level& l2,
                           const fosb_cov& cov, double scale, double* partial);
 void cov_grad_finish(hipStream_t s, const double* partial, int64_t n, double sigma, double* out);
+// rows [a0, a0 + na) of the covariance between the nodes of l1 and l2, as complex (row stride Q2)
+void cov_matrix(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t a0, int64_t na,
+                c128* Kc);
+// out[r] += scale Re sum_{q < n} A[q][r] B[q][r] (row stride R); part: (n/256 + 1) R doubles of scratch
+void coldot_re_accumulate(hipStream_t s, const c128* A, const c128* B, int64_t n, int64_t R, double scale,
+                          double* part, double* out);
 
 // out (device, 3 doubles): max |a_ij|, sum |a_ij|^2 and max_j sum_i |a_ij| of an
 // n x n complex matrix, over its upper triangle only when upper is set

@@ -1133,6 +1133,17 @@ void axpy_c128(hipStream_t s, const c128* x, int64_t ldx, c128* y, int64_t ldy, 
   FOSB_LAUNCH_CHECK();
 }
 
+__global__ void k_conj_inplace(c128* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i].im = -x[i].im;
+}
+
+void conj_inplace_c128(hipStream_t s, c128* x, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_conj_inplace, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+  FOSB_LAUNCH_CHECK();
+}
+
 // Squared Frobenius norms of x and y.  Each block writes its partial sums to
 // its own slot and one block then adds the slots in a fixed order, so the
 // result does not depend on the order in which blocks finish (the refinement

@@ -626,6 +626,84 @@ int64_t cov_grad_partials(hipStream_t s, const c128* G, int64_t a0, int64_t na, 
   return (int64_t)g.x * g.y;
 }
 
+// ------------------------------------------------------------------ variance through the adjoint maps
+// Kc[rr][c] = K(x1[a0 + rr], x2[c]) + 0i for rr < na (row stride Q2): a row
+// chunk of the covariance between the quadrature nodes of two levels.
+__global__ __launch_bounds__(256) void k_cov_matrix(int64_t a0, int64_t na, int64_t Q2, const double* __restrict__ x1,
+                                                    int64_t Q1, const double* __restrict__ n1, int nt1,
+                                                    const double* __restrict__ x2, const double* __restrict__ n2,
+                                                    int nt2, CovParams cp, c128* __restrict__ Kc) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= Q2) return;
+  const double y0 = x2[c], y1 = x2[Q2 + c], y2 = x2[2 * Q2 + c];
+  const int t2 = (int)(c / 6);
+  const double m0 = n2[t2], m1 = n2[nt2 + t2], m2 = n2[2 * nt2 + t2];
+  for (int64_t rr = blockIdx.y; rr < na; rr += gridDim.y) {
+    const int64_t q1 = a0 + rr;
+    const double d0 = x1[q1] - y0, d1 = x1[Q1 + q1] - y1, d2 = x1[2 * Q1 + q1] - y2;
+    const int t1 = (int)(q1 / 6);
+    const double nd = n1[t1] * m0 + n1[nt1 + t1] * m1 + n1[2 * nt1 + t1] * m2;
+    Kc[rr * Q2 + c] = c128{cov_eval(cp, d0 * d0 + d1 * d1 + d2 * d2, nd), 0.0};
+  }
+}
+
+void cov_matrix(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t a0, int64_t na,
+                c128* Kc) {
+  const Mesh& m1 = *l1.mesh;
+  const Mesh& m2 = *l2.mesh;
+  const int64_t Q1 = 6LL * m1.h.nt, Q2 = 6LL * m2.h.nt;
+  CovParams cp;
+  cp.kind = cov.kind;
+  cp.s2 = cov.sigma * cov.sigma;
+  cp.inv2l2 = cov.ell > 0 ? 1.0 / (2.0 * cov.ell * cov.ell) : 0.0;
+  cp.s3l = cov.ell > 0 ? std::sqrt(3.0) / cov.ell : 0.0;
+  dim3 g((unsigned)((Q2 + 255) / 256), (unsigned)std::min<int64_t>(na, 65535));
+  hipLaunchKernelGGL(k_cov_matrix, g, dim3(256), 0, s, a0, na, Q2, l1.qx.as<double>(), Q1, m1.nrm.as<double>(),
+                     (int)m1.h.nt, l2.qx.as<double>(), m2.nrm.as<double>(), (int)m2.h.nt, cp, Kc);
+  FOSB_LAUNCH_CHECK();
+}
+
+// part[b][r] = Re sum over rows q of block b (256 rows of [0, n)) of A[q][r] B[q][r]
+// (row stride R for both): 64 columns x 4 row lanes per block.
+__global__ __launch_bounds__(256) void k_coldot_partials(const c128* __restrict__ A, const c128* __restrict__ B,
+                                                         int64_t n, int64_t R, double* __restrict__ part) {
+  __shared__ double sm[4][64];
+  const int cl = threadIdx.x & 63, lane = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 64 + cl;
+  const int64_t q0 = (int64_t)blockIdx.y * 256;
+  double acc = 0;
+  if (r < R)
+    for (int64_t q = q0 + lane; q < min(n, q0 + 256); q += 4) {
+      const c128 a = A[q * R + r], b = B[q * R + r];
+      acc += a.re * b.re - a.im * b.im;
+    }
+  sm[lane][cl] = acc;
+  __syncthreads();
+  if (lane == 0 && r < R) part[(int64_t)blockIdx.y * R + r] = ((sm[0][cl] + sm[1][cl]) + sm[2][cl]) + sm[3][cl];
+}
+
+__global__ __launch_bounds__(256) void k_coldot_finish(const double* __restrict__ part, int nb, int64_t R, double scale,
+                                                       double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  double acc = 0;
+  for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * R + r];
+  out[r] += scale * acc;
+}
+
+void coldot_re_accumulate(hipStream_t s, const c128* A, const c128* B, int64_t n, int64_t R, double scale,
+                          double* part, double* out) {
+  if (n <= 0 || R <= 0) return;
+  const int nb = (int)((n + 255) / 256);
+  if (nb > 65535) fail(FOSB_E_UNSUPPORTED, "column dot over %lld rows", (long long)n);
+  hipLaunchKernelGGL(k_coldot_partials, dim3((unsigned)((R + 63) / 64), (unsigned)nb), dim3(256), 0, s, A, B, n, R,
+                     part);
+  FOSB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_coldot_finish, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, (const double*)part, nb, R,
+                     scale, out);
+  FOSB_LAUNCH_CHECK();
+}
+
 // out[0] = 2 sigma A, out[1] = sigma^2 B, out[2] = sigma^2 A with (A, B) the
 // partial pairs summed in order (one block, fixed reduction tree).
 __global__ __launch_bounds__(256) void k_cov_grad_finish(const double* __restrict__ partial, int64_t n, double sigma,

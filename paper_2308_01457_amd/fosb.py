@@ -89,6 +89,8 @@ _SIGS = {
     "fosb_far_field_matrix": (C.c_int, [_P, _P, _P, _I64, _P]),
     "fosb_far_field_moments": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64), _P,
                                          _I64, _I64, _P, _P, _P]),
+    "fosb_far_field_variance_adjoint": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
+                                                  _I64, _P, _P, C.POINTER(Stats)]),
     "fosb_far_field_moments_noalloc": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64),
                                                  _P, _I64, _I64, _P, _P]),
     "fosb_far_field_moments_backward": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
@@ -448,6 +450,24 @@ def far_field_moments(ctx: Context, levels: list[Level], L0: int, L: int, blocks
     if with_mean:
         out.append(mean.view(3, n_a))
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def far_field_variance_adjoint(ctx: Context, levels: list[Level], L0: int, L: int, cov: Cov, xhat, dir: int = 0,
+                               with_mean: bool = False, stats: Stats | None = None):
+    """fosb_far_field_variance_adjoint: the CT variance (3, n_a) without Sigma
+    blocks [and the finest level's mean far field (3, n_a)]."""
+    import torch
+    x = _host_f64(xhat).reshape(-1, 3)
+    n_a = x.shape[0]
+    var = torch.empty(3 * n_a, dtype=torch.float64, device=ctx.torch_device)
+    mean = torch.empty(3 * n_a, dtype=torch.complex128, device=ctx.torch_device) if with_mean else None
+    st = stats if stats is not None else Stats()
+    lv = (_P * len(levels))(*[l.h for l in levels])
+    _check(lib().fosb_far_field_variance_adjoint(ctx.h, lv, len(levels), L0, L, C.byref(cov), x.ctypes.data_as(_P),
+                                                 n_a, dir, _dev(var, torch.float64),
+                                                 _dev(mean) if mean is not None else None, C.byref(st)))
+    var = var.view(3, n_a)
+    return (var, mean.view(3, n_a)) if with_mean else var
 
 
 def far_field_moments_noalloc(ctx: Context, levels: list[Level], L0: int, L: int, blocks, xhat, var, dir: int = 0,

@@ -238,3 +238,14 @@ def test_rcs_db_values():
     assert abs(db[0]) < 1e-13 and abs(db[1] - 10.0) < 1e-13 and abs(db[2] + 30.0) < 1e-12
     assert np.isfinite(db[3]) and db[3] < -2900.0
     assert abs(uq.rcs_db(V[:1], pol_norm2=2.0)[0] + 10.0 * np.log10(2.0)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "matern32"])
+def test_variance_adjoint_route_equals_sigma_route(oracle_levels, kind):
+    """The variance-only route V_r = sum sign mult Re (P1 K P2^H)_rr with
+    P_l = FF_l Z_l^{-1} Wgt_l equals the Sigma route angle by angle."""
+    xh = workloads.angles_xz(23)
+    levels = {s: oracle_levels(s) for s in (0, 1, 2)}
+    V, _, _, _, _ = uq.second_moment(None, 1.0, 0, 2, kind, 0.01, 0.5, xh, levels=levels)
+    Va = uq.variance_adjoint_route(levels, 0, 2, kind, 0.01, 0.5, xh)
+    assert np.abs(Va - V).max() < 1e-11 * np.abs(V).max()
