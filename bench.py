@@ -93,6 +93,9 @@ def parse():
     ap.add_argument("--tune-load", default=None, metavar="JSON",
                     help="load a GEMM tile table ({bucket key: variant}, from --tune-dump) before the warmup")
     ap.add_argument("--tune-dump", default=None, metavar="JSON", help="write the GEMM tile table after the run")
+    ap.add_argument("--certify", action="store_true",
+                    help="after the timed steps, one untimed step per precision with opts.certify and refinement to "
+                         "1e-13: backward error, 1-norm condition estimate and growth factor in the line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -254,6 +257,20 @@ def run_gpu(args, W):
             prof = fosb.profile_read(ctx)
             fosb.profile_enable(ctx, False)
             rec["profile"] = prof
+        if args.certify:
+            log(f"[bench] {pname}: certified step")
+            copts = fosb.opts_default(ir_tol=1e-13, ir_max_sweeps=20, certify=1)
+            if args.schedule == "concurrent":
+                _, cst = one_step_concurrent(fosb, ctx, W, meshes, Z, Zlow, prec, cov, copts, blocks)
+            else:
+                _, blk, lvs, cst = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, copts)
+                for lv in lvs:
+                    kap, gro = lv.certificate()
+                    cst.kappa1, cst.growth = max(cst.kappa1, kap), max(cst.growth, gro)
+                del blk, lvs
+            rec["certificate"] = {"ir_tol": 1e-13, "ir_sweeps": int(cst.ir_sweeps),
+                                  "backward_error": cst.backward_error if prec == fosb.MIXED else None,
+                                  "kappa1": cst.kappa1, "growth": cst.growth}
         out[pname] = rec
     if args.tune_dump:
         with open(args.tune_dump, "w") as f:
@@ -343,21 +360,38 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(W):
-    """The oracle on a bounded sample of the same workload: levels s = 2, 3 of
-    the ladder (480 and 1920 RWG) timed stage by stage on the host, then
-    extrapolated to the full ladder with the stages' cost laws (regular
-    assembly ~ T^2, LU ~ N^3, pair solve ~ N1 N2 (N1 + N2), RHS correlation
-    ~ N1 N2, far field ~ N1 N2 n_a)."""
+    """The oracle on a bounded sample of the same workload, timed stage by stage
+    on the host, then extrapolated to the full ladder:
+    * levels s = 2, 3 (480 and 1920 RWG): assembly, LU + first moment, the
+      (3,2) RHS correlation, two-sided solve and far-field contraction;
+    * the oracle's LU routine (scipy.linalg.lu_factor, LAPACK getrf) on a
+      seeded random complex matrix of the s = 4 size (7680): the LU stage
+      dominates the full ladder, and this anchors its N^3 law at a size
+      where the BLAS runs at its large-matrix rate.
+    Cost laws: assembly ~ T^2 (from s = 3), LU ~ N^3 (from N = 7680), pair
+    solve ~ N1 N2 (N1 + N2), RHS correlation and far field ~ N1 N2."""
     import scipy.linalg as sla
 
     import workloads
-    from oracle import uq
+    from oracle import efie, mesh, uq
+    blas = []
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        blas = [{k: p.get(k) for k in ("internal_api", "num_threads", "version")} for p in threadpool_info()]
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
+    cores = max([b.get("num_threads") or 1 for b in blas] + [1]) if blas else (os.cpu_count() or 1)
     w = W.w
     xh = W.xh
     t = {}
@@ -365,7 +399,6 @@ def cpu_baseline(W):
     for s in (2, 3):
         V, F = workloads.icosphere(s)
         t0 = time.perf_counter()
-        from oracle import efie, mesh
         m = mesh.build(V, F)
         Z = efie.assemble(m, w.k)
         t[("asm", s)] = time.perf_counter() - t0
@@ -383,13 +416,19 @@ def cpu_baseline(W):
     FF2 = uq.far_field_matrix(lv[2], xh)
     uq.pair_variance(FF3, S, FF2)
     t_f = time.perf_counter() - t0
-    sample_s = sum(t.values()) + t_c + t_s + t_f
-    # extrapolation to the full ladder
+    n4 = 30 * 4 ** 4
+    rng = np.random.Generator(np.random.PCG64(4))
+    A = rng.standard_normal((n4, n4)) + 1j * rng.standard_normal((n4, n4))
+    t0 = time.perf_counter()
+    sla.lu_factor(A, overwrite_a=True, check_finite=False)
+    t_lu4 = time.perf_counter() - t0
+    del A
+    sample_s = sum(t.values()) + t_c + t_s + t_f + t_lu4
     N = {s: 30 * 4 ** s for s in w.levels}
     T = {s: 20 * 4 ** s for s in w.levels}
     proj = 0.0
     for s in w.levels:
-        proj += t[("asm", 3)] * (T[s] / T[3]) ** 2 + t[("lu", 3)] * (N[s] / N[3]) ** 3
+        proj += t[("asm", 3)] * (T[s] / T[3]) ** 2 + t_lu4 * (N[s] / n4) ** 3
     from paper_2308_01457_amd import fosb
     pairs = fosb.ct_pairs(w.L0, w.L)
     base_s = 8.0 * N[3] * N[2] * (N[3] + N[2])
@@ -397,11 +436,16 @@ def cpu_baseline(W):
         proj += t_s * 8.0 * N[a] * N[b] * (N[a] + N[b]) / base_s
         proj += (t_c + t_f) * N[a] * N[b] / (N[3] * N[2])
     return {"value": len(pairs) / proj, "unit": "level-pair solves/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "blas": blas,
             "sample": (f"oracle (numpy/scipy FP64) timed on levels s=2,3 of the ladder (assembly, LU + first moment, "
-                       f"the (3,2) RHS correlation, two-sided solve and far-field contraction; {sample_s:.1f} s), "
-                       f"extrapolated to s=2..5 by T^2 (assembly), N^3 (LU), N1 N2 (N1+N2) (pair solve); "
-                       f"projected {proj:.0f} s per step"),
-            "projected_seconds_per_step": proj}
+                       f"the (3,2) RHS correlation, two-sided solve and far-field contraction) and its LU routine "
+                       f"on a random complex {n4} x {n4} matrix ({t_lu4:.1f} s, {8.0 / 3.0 * n4 ** 3 / t_lu4 / 1e9:.0f}"
+                       f" GFLOP/s); {sample_s:.1f} s in all; extrapolated to s=2..5 by T^2 (assembly, from s=3), "
+                       f"N^3 (LU, from N={n4}), N1 N2 (N1+N2) (pair solve); projected {proj:.0f} s per step"),
+            "projected_seconds_per_step": proj,
+            "stage_seconds_sample": {"assembly_s3": t[("asm", 3)], "lu_first_moment_s3": t[("lu", 3)],
+                                     "lu_n7680": t_lu4, "rhs_correlation_32": t_c, "two_sided_32": t_s,
+                                     "far_field_32": t_f}}
 
 
 def calibrate_copy():
@@ -456,6 +500,12 @@ def main():
     }
     for pname, rec in gpu.items():
         line[pname] = {k: v for k, v in rec.items() if k not in ("var", "profile")}
+    mie_file = os.path.join(ROOT, "tests", "golden", "mie_shape_oracle.json")
+    if W.name == "mixed_k5" and W.w.levels[-1] == 5 and os.path.exists(mie_file):
+        with open(mie_file) as f:
+            mie = np.asarray(json.load(f)["variance"]["5.0"])
+        for pname, rec in gpu.items():   # discretisation + CT error against the mesh-free value
+            line[pname]["vs_mie_shape_rel_err"] = float(np.linalg.norm(rec["var"] - mie) / np.linalg.norm(mie))
     if "mixed" in gpu and "fp64" in gpu:
         v64, v32 = gpu["fp64"]["var"], gpu["mixed"]["var"]
         line["mixed_speedup_vs_fp64"] = gpu["fp64"]["seconds_per_step"] / gpu["mixed"]["seconds_per_step"]
@@ -475,6 +525,18 @@ def main():
                             "algorithmic_bytes_per_launch": by / max(n, 1)}
         line["kernel_profile"] = {k: {"launches": v[0], "seconds": v[1], "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
                                       "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof.items()}
+    prof64 = gpu.get("fp64", {}).get("profile") if head == "mixed" else None
+    if prof64:   # the FP64 path's dominant kernel, for the mixed-versus-FP64 comparison
+        n, sec, fl, by = prof64["gemm_f64"]
+        ach = fl / sec / 1e12 if sec > 0 else 0.0
+        line["roofline_fp64"] = {"kernel": "k_gemm<double>", "bound": "mfma", "achieved": ach, "peak": PEAK["fp64"],
+                                 "unit": "TFLOP/s", "frac": ach / PEAK["fp64"], "traffic": None,
+                                 "launches": n, "avg_launch_us": sec / max(n, 1) * 1e6,
+                                 "algorithmic_flop_per_launch": fl / max(n, 1),
+                                 "algorithmic_bytes_per_launch": by / max(n, 1)}
+        line["kernel_profile_fp64"] = {k: {"launches": v[0], "seconds": v[1],
+                                           "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
+                                           "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof64.items()}
     if not args.no_cpu_baseline and W.name == "mixed_k5":
         log("[bench] cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(W)

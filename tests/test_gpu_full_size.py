@@ -10,6 +10,9 @@ L0 = 2, L = 5, 181 angles), in the launch configuration bench.py times.
   the oracle alone.  FP64 path: 1e-9; mixed path (bench tolerance: refined
   solves to an estimated 1e-8): 1e-6 on the variance, 1e-5 on sampled entries (C is
   built from the first moments, so it carries their accuracy).
+* The CT variance against the mesh-free spectral Mie shape derivative
+  (tests/golden/mie_shape_oracle.json): within 0.2%, the discretisation and
+  combination-technique error at L = 5.
 * Properties at full size: the two-sided backward error of the (5,2) block
   and the Hermitian symmetry of C(3,3)."""
 
@@ -139,6 +142,12 @@ def test_full_size_against_oracle_golden(fz, golden, precision):
     e = _rel(var, np.asarray(golden["variance"]))
     print(f"[gpu]   CT variance {e:.2e} (refinement sweeps {st.ir_sweeps})", flush=True)
     assert e < tol_v
+    # the mesh-free spectral Mie value of the same variance (discretisation + CT error at L = 5)
+    with open(os.path.join(HERE, "golden", "mie_shape_oracle.json")) as f:
+        mie = np.asarray(json.load(f)["variance"]["5.0"])
+    e_m = _rel(var, mie)
+    print(f"[gpu]   CT variance vs the spectral Mie shape derivative {e_m:.2e}", flush=True)
+    assert e_m < 2e-3
 
 
 def test_full_size_properties(fz):

@@ -102,3 +102,21 @@ def test_discretised_gaussian_variance_converges_to_the_spectral_reference(oracl
         FF = uq.far_field_matrix(lv, xh)
         errs.append(_rel(uq.pair_variance(FF, uq.two_sided_solve(lv, lv, C), FF), Vr))
     assert errs[-1] < 1e-2 and errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def test_stored_spectral_values_and_the_mixed_workload_golden():
+    """tests/golden/mie_shape_oracle.json holds what oracle/mie_shape.py
+    computes (k = 1 recomputed here), and the oracle's CT variance of the
+    mixed workload (s = 2..5, k = 5; tests/golden/mixed_k5_oracle.json) is
+    within 0.2% of the mesh-free k = 5 value."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(here, "mie_shape_oracle.json")) as f:
+        ms_gold = json.load(f)
+    xh = workloads.angles_xz(181)
+    V1 = ms.variance_gaussian(1.0, ms_gold["sigma"], ms_gold["ell"], xh)
+    assert np.abs(V1 - np.asarray(ms_gold["variance"]["1.0"])).max() < 1e-12 * np.abs(V1).max()
+    with open(os.path.join(here, "mixed_k5_oracle.json")) as f:
+        ct = np.asarray(json.load(f)["variance"])
+    assert _rel(ct, np.asarray(ms_gold["variance"]["5.0"])) < 2e-3
