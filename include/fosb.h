@@ -52,6 +52,7 @@ extern "C" {
 typedef struct fosb_context fosb_context;
 typedef struct fosb_mesh fosb_mesh;
 typedef struct fosb_level fosb_level;
+typedef struct fosb_lowrank fosb_lowrank;
 
 typedef enum fosb_status {
   FOSB_OK = 0,
@@ -293,6 +294,41 @@ fosb_status fosb_far_field_moments(fosb_context* ctx, const fosb_level* const* l
 fosb_status fosb_far_field_variance_adjoint(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
                                             int32_t L0, int32_t L, const fosb_cov* cov, const double* xhat,
                                             int64_t n_a, int64_t dir, double* var, void* mean_F, fosb_stats* stats);
+
+/* ---------------------------------------------------------------- low-rank covariance */
+/* Low-rank factor K ~ L L^T of the covariance on the quadrature nodes of a
+ * level ladder (levels[i] = level L0 + i, coarse to fine; the nodes of all
+ * levels, in that order, are the candidate points), for a second moment
+ * whose right-hand-side correlation factors as C_l1l2 = (Wgt_l1 L_l1)
+ * (Wgt_l2 L_l2)^H, so that Sigma_l1l2 = Y_l1 Y_l2^H with Y_l = Z_l^{-1} Wgt_l L_l:
+ * one solve with rank right-hand sides per level instead of N_l2 + N_l1 per
+ * pair (the paper's future-work remarks on low-rank covariance
+ * representations; the Fichera experiment's covariance is separable).
+ * Greedy pivoted Cholesky: starting from d = diag K, each step takes as pivot
+ * p the lowest candidate index with d_p >= (1 - 1e-9) max d, forms the column
+ * L[:, j] = (K(X, x_p) - L[:, :j] L[p, :j]^T) / sqrt(d_p), subtracts its
+ * squares from d and sets d_p = 0; it stops once max d <= tol max(diag K) or
+ * at max_rank columns.  The factor is exact on the pivots and bounded by the
+ * remaining diagonal elsewhere.  FP64 throughout; device memory about
+ * 8 max_rank (number of nodes) bytes.  The levels must outlive the handle.
+ * E_INVALID for bad arguments (max_rank 1..min(8192, nodes), 0 <= tol < 1). */
+fosb_status fosb_lowrank_create(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                                const fosb_cov* cov, int32_t max_rank, double tol, fosb_lowrank** out);
+/* rank reached, residual (largest remaining diagonal entry / largest initial
+ * one) and the pivots (host, rank int64 candidate indices; may be NULL). */
+fosb_status fosb_lowrank_info(const fosb_lowrank* lr, int32_t* rank, double* residual, int64_t* pivots);
+/* Y (device, N x rank complex128, row stride ldy >= rank) = Z^{-1} Wgt_dir L_l
+ * for ladder level level_index (refined in FP64 on MIXED levels). */
+fosb_status fosb_lowrank_factor(fosb_context* ctx, const fosb_lowrank* lr, int32_t level_index, int64_t dir, void* Y,
+                                int64_t ldy, fosb_stats* stats);
+/* CT far-field variance with the low-rank covariance (var: device, 3 n_a
+ * float64, layout as fosb_far_field_moments):
+ *   var[r] = sum_{Lambda_H} sign mult Re sum_k G_l1[r][k] conj(G_l2[r][k]),  G_l = FF_l Y_l.
+ * L - L0 + 1 must equal the ladder's length. */
+fosb_status fosb_far_field_moments_lowrank(fosb_context* ctx, const fosb_lowrank* lr, int32_t L0, int32_t L,
+                                           const double* xhat, int64_t n_a, int64_t dir, double* var,
+                                           fosb_stats* stats);
+fosb_status fosb_lowrank_destroy(fosb_lowrank* lr);
 
 /* Bytes of the per-GPU work array of fosb_far_field_moments_noalloc. */
 #define FOSB_NOALLOC_SCRATCH_BYTES (64LL << 20)

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfosb.so")
-SOURCES = ["mesh.cpp", "api.cpp", "prof.cpp", "assemble.hip", "gemm.hip", "lu.hip", "uq.hip", "noalloc.hip"]
+SOURCES = ["mesh.cpp", "api.cpp", "prof.cpp", "assemble.hip", "gemm.hip", "lu.hip", "uq.hip", "noalloc.hip", "lowrank.hip"]
 ARCH = os.environ.get("FOSB_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

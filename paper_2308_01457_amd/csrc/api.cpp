@@ -247,6 +247,19 @@ struct PoolRelease {
 
 
 struct fosb_context : fosb::Context {};
+
+// Low-rank covariance factor of a level ladder (fosb_lowrank_*).
+struct fosb_lowrank {
+  fosb::Context* ctx = nullptr;
+  std::vector<const fosb::Level*> levels;   // the ladder, coarse to fine
+  std::vector<int64_t> off;                 // first candidate row of each level
+  fosb_cov cov{};
+  int64_t nc = 0;
+  int32_t rank = 0;
+  double residual = 1.0;
+  std::vector<int64_t> pivots;
+  fosb::DevBuf L;                           // factor, column-major nc x rank (double)
+};
 struct fosb_mesh : fosb::Mesh {};
 struct fosb_level : fosb::Level {};
 
@@ -1017,6 +1030,163 @@ fosb_status fosb_far_field_variance_adjoint(fosb_context* ctx, const fosb_level*
     copy_c128(s, lf.u.as<c128>() + dir, lf.n_dirs, u.as<c128>(), 1, lf.n, 1);
     matvec_rows(s, FF.as<c128>(), R, lf.n, u.as<c128>(), static_cast<c128*>(mean_F));
   }
+  FOSB_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+fosb_status fosb_lowrank_create(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
+                                const fosb_cov* cov, int32_t max_rank, double tol, fosb_lowrank** out) {
+  API_BEGIN
+  REQUIRE(ctx && levels && out, "NULL argument");
+  *out = nullptr;
+  REQUIRE(n_levels >= 1 && n_levels <= 64, "n_levels must be 1..64");
+  check_cov(cov);
+  for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  REQUIRE(std::isfinite(tol) && tol >= 0.0 && tol < 1.0, "tol must be in [0, 1)");
+  std::unique_ptr<fosb_lowrank> lr(new fosb_lowrank());
+  lr->ctx = ctx;
+  lr->cov = *cov;
+  int64_t nc = 0;
+  for (int32_t i = 0; i < n_levels; ++i) {
+    lr->levels.push_back(levels[i]);
+    lr->off.push_back(nc);
+    nc += 6LL * levels[i]->mesh->h.nt;
+  }
+  lr->nc = nc;
+  REQUIRE(max_rank >= 1 && max_rank <= 8192 && max_rank <= nc, "max_rank must be 1..min(8192, nodes)");
+  bind(*ctx);
+  check_device_memory(*ctx, (int64_t)max_rank * nc * 8 + 7 * nc * 8, "the low-rank factor");
+  hipStream_t s = ctx->stream;
+  DevBuf X((size_t)3 * nc * sizeof(double)), Nn((size_t)3 * nc * sizeof(double)), d((size_t)nc * sizeof(double));
+  DevBuf pv(2 * sizeof(double));
+  lr->L.alloc((size_t)max_rank * nc * sizeof(double));
+  for (int32_t i = 0; i < n_levels; ++i)
+    lr_candidates(s, *levels[i], lr->off[i], nc, X.as<double>(), Nn.as<double>());
+  lr_diag(s, Nn.as<double>(), nc, *cov, d.as<double>());
+  // Greedy pivoted Cholesky: the host reads each pivot (its remaining diagonal
+  // entry decides termination) and launches the column update.
+  constexpr double kTie = 1e-9;
+  double dmax0 = -1.0, last = 0.0;
+  for (int32_t j = 0; j < max_rank; ++j) {
+    double h[2];
+    lr_pivot(s, d.as<double>(), nc, kTie, pv.as<double>());
+    FOSB_HIP(hipMemcpyAsync(h, pv.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+    if (j == 0) dmax0 = h[0];
+    last = h[0];
+    if (!(h[0] > tol * dmax0) || !(h[0] > 0.0)) break;
+    const int64_t p = (int64_t)h[1];
+    lr_column(s, X.as<double>(), Nn.as<double>(), nc, *cov, lr->L.as<double>(), j, p, h[0], d.as<double>());
+    lr->pivots.push_back(p);
+    lr->rank = j + 1;
+  }
+  if (lr->rank == max_rank) {  // the largest remaining diagonal entry after the last column
+    double h[2];
+    lr_pivot(s, d.as<double>(), nc, kTie, pv.as<double>());
+    FOSB_HIP(hipMemcpyAsync(h, pv.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    FOSB_HIP(hipStreamSynchronize(s));
+    last = h[0];
+  }
+  lr->residual = dmax0 > 0 ? last / dmax0 : 0.0;
+  FOSB_HIP(hipStreamSynchronize(s));
+  *out = lr.release();
+  API_END
+}
+
+fosb_status fosb_lowrank_info(const fosb_lowrank* lr, int32_t* rank, double* residual, int64_t* pivots) {
+  API_BEGIN
+  REQUIRE(lr, "lowrank is NULL");
+  if (rank) *rank = lr->rank;
+  if (residual) *residual = lr->residual;
+  if (pivots) std::copy(lr->pivots.begin(), lr->pivots.end(), pivots);
+  API_END
+}
+
+fosb_status fosb_lowrank_destroy(fosb_lowrank* lr) {
+  API_BEGIN
+  if (!lr) return FOSB_OK;
+  if (lr->ctx) {
+    (void)hipSetDevice(lr->ctx->device);
+    (void)hipStreamSynchronize(lr->ctx->stream);
+  }
+  delete lr;
+  API_END
+}
+
+// Y (N x rank, row stride ldy) = Z^{-1} Wgt_dir L_l for ladder level i.
+static void lowrank_factor_impl(Context& c, const fosb_lowrank& lr, int32_t i, int64_t dir, c128* Y, int64_t ldy,
+                                fosb_stats* st) {
+  const Level& l = *lr.levels[i];
+  const int r = lr.rank;
+  DevBuf Lr((size_t)6 * l.mesh->h.nt * r * sizeof(double));
+  if (ldy == r) {
+    lr_rhs(c.stream, l, dir, lr.L.as<double>(), lr.nc, lr.off[i], r, Lr.as<double>(), Y);
+    level_solve_inplace(c, l, Y, ldy, r, st);
+  } else {
+    DevBuf M((size_t)l.n * r * sizeof(c128));
+    lr_rhs(c.stream, l, dir, lr.L.as<double>(), lr.nc, lr.off[i], r, Lr.as<double>(), M.as<c128>());
+    level_solve_inplace(c, l, M.as<c128>(), r, r, st);
+    copy_c128(c.stream, M.as<c128>(), r, Y, ldy, l.n, r);
+  }
+}
+
+static void check_lowrank(const fosb_context* ctx, const fosb_lowrank* lr) {
+  REQUIRE(lr, "lowrank is NULL");
+  REQUIRE(lr->ctx == ctx, "lowrank belongs to another context");
+  REQUIRE(lr->rank >= 1, "the low-rank factor is empty (rank 0)");
+  for (const Level* l : lr->levels) REQUIRE(l->ctx == ctx, "a level of the low-rank factor was detached");
+}
+
+fosb_status fosb_lowrank_factor(fosb_context* ctx, const fosb_lowrank* lr, int32_t level_index, int64_t dir, void* Y,
+                                int64_t ldy, fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && Y, "NULL argument");
+  check_lowrank(ctx, lr);
+  REQUIRE(level_index >= 0 && level_index < (int32_t)lr->levels.size(), "level_index out of range");
+  REQUIRE(dir >= 0 && dir < lr->levels[0]->n_dirs, "dir out of range");
+  if (ldy < lr->rank) fail(FOSB_E_WORKSPACE, "ldy < rank");
+  bind(*ctx);
+  lowrank_factor_impl(*ctx, *lr, level_index, dir, static_cast<c128*>(Y), ldy, stats);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  API_END
+}
+
+fosb_status fosb_far_field_moments_lowrank(fosb_context* ctx, const fosb_lowrank* lr, int32_t L0, int32_t L,
+                                           const double* xhat, int64_t n_a, int64_t dir, double* var,
+                                           fosb_stats* stats) {
+  API_BEGIN
+  REQUIRE(ctx && xhat && var, "NULL argument");
+  check_lowrank(ctx, lr);
+  REQUIRE(L0 >= 0 && L >= L0 && L - L0 + 1 == (int32_t)lr->levels.size(),
+          "L - L0 + 1 must equal the low-rank factor's number of levels");
+  REQUIRE(dir >= 0 && dir < lr->levels[0]->n_dirs, "dir out of range");
+  REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
+  for (int64_t i = 0; i < n_a; ++i) {
+    double nn = xhat[3 * i] * xhat[3 * i] + xhat[3 * i + 1] * xhat[3 * i + 1] + xhat[3 * i + 2] * xhat[3 * i + 2];
+    REQUIRE(std::fabs(nn - 1.0) < 1e-9, "xhat[%lld] is not a unit vector", (long long)i);
+  }
+  bind(*ctx);
+  hipStream_t s = ctx->stream;
+  std::vector<double> x(xhat, xhat + 3 * n_a);
+  DevBuf dx;
+  upload(dx, x, s);
+  const int64_t R = 3 * n_a;
+  const int r = lr->rank;
+  const int n_levels = (int)lr->levels.size();
+  // per level: G_l = FF_l Z_l^{-1} Wgt_l L_l  (R x rank)
+  std::vector<DevBuf> G(n_levels);
+  for (int i = 0; i < n_levels; ++i) {
+    const Level& l = *lr->levels[i];
+    DevBuf Y((size_t)l.n * r * sizeof(c128)), FF((size_t)R * l.n * sizeof(c128));
+    lowrank_factor_impl(*ctx, *lr, i, dir, Y.as<c128>(), r, stats);
+    far_field_matrix_kernel(s, *l.mesh, l.k, dx.as<double>(), n_a, FF.as<c128>());
+    G[i].alloc((size_t)R * r * sizeof(c128));
+    gemm<double>(*ctx, R, r, l.n, 1.0, FF.as<c128>(), l.n, Y.as<c128>(), r, 0.0, G[i].as<c128>(), r);
+  }
+  // Sigma_l1l2 = Y_l1 Y_l2^H, so (FF_l1 Sigma FF_l2^H)_rr = sum_k G_l1[r][k] conj(G_l2[r][k])
+  zero_f64(s, var, R);
+  for (auto& q : ct_pairs_vec(L0, L))
+    row_dot_re_accumulate(s, G[q[0] - L0].as<c128>(), r, G[q[1] - L0].as<c128>(), R, r, (double)(q[2] * q[3]), var);
   FOSB_HIP(hipStreamSynchronize(s));
   API_END
 }

@@ -420,6 +420,18 @@ void noalloc_scratch_init(int device);
 void* noalloc_scratch(int device);
 void zero_f64(hipStream_t s, double* p, int64_t n);
 
+// lowrank.hip: pivoted Cholesky of the covariance on a ladder's quadrature nodes
+// (candidates Xc, Nc: [3][nc]; factor L column-major, L[k * nc + i]).
+void lr_candidates(hipStream_t s, const Level& l, int64_t off, int64_t nc, double* Xc, double* Nc);
+void lr_diag(hipStream_t s, const double* Nc, int64_t nc, const fosb_cov& cov, double* d);
+// out (device, 2 doubles) = {d[p], p}: p the lowest index with d[p] >= (1 - tie) max d
+void lr_pivot(hipStream_t s, const double* d, int64_t nc, double tie, double* out);
+void lr_column(hipStream_t s, const double* Xc, const double* Nc, int64_t nc, const fosb_cov& cov, double* L, int j,
+               int64_t p, double dp, double* d);
+// M (N x rank) = Wgt_dir L_l with L_l the factor's rows [off, off + 6 nt) (Lr: scratch, 6 nt x rank doubles)
+void lr_rhs(hipStream_t s, const Level& l, int64_t dir, const double* L, int64_t nc, int64_t off, int rank,
+            double* Lr, c128* M);
+
 // level-wide solves (api.cpp helpers)
 // B <- Z^{-1} B, or B <- Z^{-H} B (adjoint)
 void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st,

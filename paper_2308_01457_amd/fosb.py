@@ -91,6 +91,11 @@ _SIGS = {
                                          _I64, _I64, _P, _P, _P]),
     "fosb_far_field_variance_adjoint": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
                                                   _I64, _P, _P, C.POINTER(Stats)]),
+    "fosb_lowrank_create": (C.c_int, [_P, C.POINTER(_P), _I32, C.POINTER(Cov), _I32, _D, C.POINTER(_P)]),
+    "fosb_lowrank_info": (C.c_int, [_P, C.POINTER(_I32), C.POINTER(_D), C.POINTER(_I64)]),
+    "fosb_lowrank_factor": (C.c_int, [_P, _P, _I32, _I64, _P, _I64, C.POINTER(Stats)]),
+    "fosb_far_field_moments_lowrank": (C.c_int, [_P, _P, _I32, _I32, _P, _I64, _I64, _P, C.POINTER(Stats)]),
+    "fosb_lowrank_destroy": (C.c_int, [_P]),
     "fosb_far_field_moments_noalloc": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64),
                                                  _P, _I64, _I64, _P, _P]),
     "fosb_far_field_moments_backward": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
@@ -468,6 +473,56 @@ def far_field_variance_adjoint(ctx: Context, levels: list[Level], L0: int, L: in
                                                  _dev(mean) if mean is not None else None, C.byref(st)))
     var = var.view(3, n_a)
     return (var, mean.view(3, n_a)) if with_mean else var
+
+
+class LowRank:
+    """fosb_lowrank_create: pivoted Cholesky factor of the covariance on the
+    quadrature nodes of the ladder `levels` (coarse to fine)."""
+
+    def __init__(self, ctx: Context, levels: list[Level], cov: Cov, max_rank: int, tol: float):
+        self.ctx, self.levels = ctx, list(levels)
+        lv = (_P * len(levels))(*[l.h for l in levels])
+        h = _P()
+        _check(lib().fosb_lowrank_create(ctx.h, lv, len(levels), C.byref(cov), int(max_rank), float(tol), C.byref(h)))
+        self.h = h
+        r, res = _I32(), _D()
+        _check(lib().fosb_lowrank_info(h, C.byref(r), C.byref(res), None))
+        self.rank, self.residual = r.value, res.value
+        piv = (_I64 * max(self.rank, 1))()
+        _check(lib().fosb_lowrank_info(h, None, None, piv))
+        self.pivots = np.array([piv[i] for i in range(self.rank)], dtype=np.int64)
+
+    def factor(self, level_index: int, dir: int = 0, stats: Stats | None = None):
+        """Y = Z^{-1} Wgt L_l (N x rank, complex128 on the device)."""
+        import torch
+        n = self.levels[level_index].n
+        Y = torch.empty((n, self.rank), dtype=torch.complex128, device=self.ctx.torch_device)
+        st = stats if stats is not None else Stats()
+        _check(lib().fosb_lowrank_factor(self.ctx.h, self.h, level_index, dir, _dev(Y, torch.complex128), Y.stride(0),
+                                         C.byref(st)))
+        return Y
+
+    def far_field_moments(self, L0: int, L: int, xhat, dir: int = 0, stats: Stats | None = None):
+        import torch
+        x = _host_f64(xhat).reshape(-1, 3)
+        var = torch.empty(3 * x.shape[0], dtype=torch.float64, device=self.ctx.torch_device)
+        st = stats if stats is not None else Stats()
+        _check(lib().fosb_far_field_moments_lowrank(self.ctx.h, self.h, L0, L, x.ctypes.data_as(_P), x.shape[0], dir,
+                                                    _dev(var, torch.float64), C.byref(st)))
+        return var.view(3, -1)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fosb_lowrank_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def far_field_moments_noalloc(ctx: Context, levels: list[Level], L0: int, L: int, blocks, xhat, var, dir: int = 0,
