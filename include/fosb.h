@@ -354,6 +354,27 @@ fosb_status fosb_far_field_moments_noalloc(fosb_context* ctx, const fosb_level* 
                                            int32_t L0, int32_t L, void* const* blocks, const int64_t* ldb,
                                            const double* xhat, int64_t n_a, int64_t dir, double* var, void* mean_F);
 
+/* ---------------------------------------------------------------- near field */
+/* Scattered field at field points off the surface (FOA section: the field's
+ * shape derivative is E' = -E_k dj', the electric potential applied to the
+ * trace's shape derivative; problem setting: E^sc = -E_k j):
+ *   E^sc_c(x_p) = sum_m NF[c*n_p + p][m] u_m,
+ *   E_k phi(x) = i k int G(x,y) phi(y) dy + (i/k) grad_x int G(x,y) div phi(y) dy,
+ * 6-point rule on every triangle (accurate for points farther from the
+ * surface than a few triangle sizes; points on the surface are singular).
+ * points: host, n_p x 3 (1..65535).  NF: device, (3 n_p) x N complex128. */
+fosb_status fosb_near_field_matrix(fosb_context* ctx, const fosb_level* level, const double* points, int64_t n_p,
+                                   void* NF);
+/* Combination-technique second moment of the field's shape derivative at the
+ * field points:
+ *   var[c*n_p + p] = sum_{Lambda_H} sign mult Re (NF_l1 Sigma NF_l2^H)[(c,p),(c,p)]
+ * (device, 3 n_p float64), from the blocks of fosb_correlation, and mean_E
+ * (device, 3 n_p complex128, may be NULL) the finest level's scattered field
+ * there (the first moment).  Arguments otherwise as for fosb_far_field_moments. */
+fosb_status fosb_near_field_moments(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels, int32_t L0,
+                                    int32_t L, void* const* blocks, const int64_t* ldb, const double* points,
+                                    int64_t n_p, int64_t dir, double* var, void* mean_E);
+
 /* Adjoint of the combination-technique variance with respect to the
  * covariance parameters.  With upstream weights g = dvar (device, 3 n_a
  * float64, same layout as var) and S = sum_r g_r var_r:

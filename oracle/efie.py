@@ -204,6 +204,28 @@ def far_field_matrix(m: meshmod.RWGMesh, k: float, xh: np.ndarray) -> np.ndarray
     return (Jt.reshape(3 * n_a, 3 * m.nt) @ S.T).reshape(3, n_a, m.ne)
 
 
+def near_field_matrix(m: meshmod.RWGMesh, k: float, P: np.ndarray) -> np.ndarray:
+    """NF (3, n_p, ne): the scattered field E^sc_c(P_p) = sum_m NF[c, p, m] u_m
+    of the current j = sum u_m phi_m at field points P (n_p, 3) off the
+    surface, E^sc = -E_k j with the electric potential
+        E_k phi(x) = i k int G(x, y) phi(y) dy + (i/k) grad_x int G(x, y) div phi(y) dy
+    (the form whose Galerkin pairing is the EFIE matrix above, and whose far
+    zone gives far_field_matrix), 6-point rule on every triangle,
+    grad_x G = (i k - 1/R) G (x - y)/R."""
+    X, W, Phi, D = basis_at_points(m)
+    P = np.asarray(P, dtype=np.float64)
+    d = P[:, None, None, :] - X[None]                                   # (n_p, nt, 6, 3)
+    R = np.sqrt(np.sum(d * d, axis=-1))
+    G = green(k, R) * W[None]                                           # (n_p, nt, 6)
+    gG = ((1j * k - 1.0 / R) * G / R)[..., None] * d                    # (n_p, nt, 6, 3)
+    t1 = np.einsum("ptq,taqc->ptac", G, Phi)
+    t2 = np.einsum("ptqc,ta->ptac", gG, D)
+    E = -(1j * k * t1 + (1j / k) * t2)                                  # (n_p, nt, 3 local, 3 comp)
+    n_p = P.shape[0]
+    Et = np.transpose(E, (3, 0, 1, 2)).reshape(3 * n_p, 3 * m.nt)
+    return (Et @ incidence(m).T).reshape(3, n_p, m.ne)
+
+
 def far_field(m: meshmod.RWGMesh, k: float, u: np.ndarray, xh: np.ndarray) -> np.ndarray:
     """Far field F (n_a, 3) of the current with RWG coefficients u."""
     FF = far_field_matrix(m, k, xh)

@@ -219,6 +219,20 @@ def far_field_moments(levels: dict[int, Level], blocks: dict[tuple[int, int], np
     return V, per
 
 
+def near_field_moments(levels: dict[int, Level], blocks: dict[tuple[int, int], np.ndarray],
+                       L0: int, L: int, P: np.ndarray):
+    """CT variance of the shape derivative of the scattered field at field
+    points P (n_p, 3): Var[E'_c](P_p) = sum_pairs sign*mult*Re (NF1 Sigma NF2^H)
+    at ((c,p),(c,p)) (3, n_p), and the finest level's mean field E^sc (3, n_p).
+    Same combination as far_field_moments, with the near-field map."""
+    NF = {s: efie.near_field_matrix(levels[s].mesh, levels[s].k, P) for s in levels}
+    V = np.zeros((3, P.shape[0]))
+    for l1, l2, sgn, mult in ct_pairs(L0, L):
+        V += sgn * mult * pair_variance(NF[l1], blocks[(l1, l2)], NF[l2])
+    mean = np.einsum("cpm,m->cp", NF[L], levels[L].u)
+    return V, mean
+
+
 def rcs_db(V: np.ndarray, pol_norm2: float = 1.0) -> np.ndarray:
     """Display transform of a (non-negative) far-field power: 10 log10(4 pi V/|p|^2)
     (the paper's RCS definition applied literally; negative CT values clamp)."""

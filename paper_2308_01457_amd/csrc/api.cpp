@@ -526,7 +526,7 @@ static void check_far_field_args(const double* xhat, int64_t n_a, int32_t L0, in
 // maps are formed once.  Synchronises c's stream.
 static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t L0, int32_t L, void* const* blocks,
                            const int64_t* ldb, const double* xhat, int64_t n_a, int64_t dir0, int64_t nd, double* var,
-                           void* mean_F, void* cor = nullptr) {
+                           void* mean_F, void* cor = nullptr, bool near = false) {
   const int32_t n_levels = L - L0 + 1;
   hipStream_t s = c.stream;
   std::vector<double> x(xhat, xhat + 3 * n_a);
@@ -537,7 +537,10 @@ static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t 
   std::vector<DevBuf> FF(n_levels);
   for (int32_t i = 0; i < n_levels; ++i) {
     FF[i].alloc((size_t)rows * levels[i]->n * sizeof(c128));
-    far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
+    if (near)  // scattered field at field points instead of the far field at directions
+      near_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
+    else
+      far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
   }
   FOSB_HIP(hipMemsetAsync(var, 0, nd * rows * sizeof(double), s));
   if (cor) {
@@ -1259,6 +1262,46 @@ fosb_status fosb_far_field_moments_noalloc(fosb_context* ctx, const fosb_level* 
     }
   }
   FOSB_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+static void check_field_points(const double* xp, int64_t n_p) {
+  REQUIRE(xp, "points is NULL");
+  REQUIRE(n_p >= 1 && n_p <= 65535, "n_p must be 1..65535");
+  for (int64_t i = 0; i < 3 * n_p; ++i) REQUIRE(std::isfinite(xp[i]), "non-finite field point coordinate");
+}
+
+fosb_status fosb_near_field_matrix(fosb_context* ctx, const fosb_level* level, const double* points, int64_t n_p,
+                                   void* NF) {
+  API_BEGIN
+  REQUIRE(ctx && level && NF, "NULL argument");
+  REQUIRE(level->ctx == ctx, "level belongs to another context");
+  check_field_points(points, n_p);
+  bind(*ctx);
+  std::vector<double> x(points, points + 3 * n_p);
+  DevBuf dx;
+  upload(dx, x, ctx->stream);
+  near_field_matrix_kernel(ctx->stream, *level->mesh, level->k, dx.as<double>(), n_p, static_cast<c128*>(NF));
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
+  API_END
+}
+
+fosb_status fosb_near_field_moments(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels, int32_t L0,
+                                    int32_t L, void* const* blocks, const int64_t* ldb, const double* points,
+                                    int64_t n_p, int64_t dir, double* var, void* mean_E) {
+  API_BEGIN
+  REQUIRE(ctx && levels && blocks && ldb && var, "NULL argument");
+  REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
+  check_field_points(points, n_p);
+  auto v = ct_pairs_vec(L0, L);
+  for (size_t p = 0; p < v.size(); ++p) {
+    REQUIRE(blocks[p], "block %zu is NULL", p);
+    if (ldb[p] < levels[v[p][1] - L0]->n) fail(FOSB_E_WORKSPACE, "ldb[%zu] < N_l2", p);
+  }
+  bind(*ctx);
+  far_field_impl(*ctx, levels, L0, L, blocks, ldb, points, n_p, dir, 1, var, mean_E, nullptr, true);
   API_END
 }
 

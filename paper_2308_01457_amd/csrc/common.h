@@ -386,6 +386,8 @@ void rhs_correlation_multi(hipStream_t s, const Level& l1, const Level& l2, cons
                            int64_t nd, c128* C, int64_t ldc, int64_t dstride);
 void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a,
                              c128* FF);
+// NF[(c*n_p + p)][m]: scattered field at the field points x_p (device, n_p x 3) of each RWG
+void near_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xp_dev, int64_t n_p, c128* NF);
 void row_dot_re_accumulate(hipStream_t s, const c128* P, int64_t ldp, const c128* FF2, int64_t rows, int64_t n,
                            double scale, double* var);
 void matvec_rows(hipStream_t s, const c128* FF, int64_t rows, int64_t n, const c128* u, c128* out);

@@ -422,6 +422,64 @@ void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const doubl
   FOSB_LAUNCH_CHECK();
 }
 
+// NF[(c*n_p + p)][m] = E^sc_c(x_p) of phi_m, E^sc = -E_k phi with
+//   E_k phi(x) = i k int G phi + (i/k) grad_x int G div phi,
+//   grad_x G(x, y) = (i k - 1/R) G (x - y)/R,  G = e^{ikR}/(4 pi R),
+// 6-point rule on both triangles of the RWG (field points off the surface).
+__global__ void k_near_field_matrix(MeshDev md, Rule6Q R, double k, const double* __restrict__ xp, int n_p,
+                                    c128* __restrict__ NF) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ip = blockIdx.y;
+  if (m >= md.ne || ip >= n_p) return;
+  const double x[3] = {xp[3 * ip], xp[3 * ip + 1], xp[3 * ip + 2]};
+  double Ar[3] = {0, 0, 0}, Ai[3] = {0, 0, 0};   // int G phi
+  double Br[3] = {0, 0, 0}, Bi[3] = {0, 0, 0};   // int grad_x G div phi
+  const double inv4pi = 0.25 / M_PI;
+  for (int side = 0; side < 2; ++side) {
+    const int t = md.edge_tri[side * md.ne + m];
+    const int a = md.edge_loc[side * md.ne + m];
+    double P[3][3];
+    tri_vertices(md, t, P);
+    const double al = md.alpha[a * md.nt + t];
+    const double ha = 0.5 * al * md.area[t];
+    const double dv = al * md.area[t];
+    for (int q = 0; q < 6; ++q) {
+      double y[3], dx[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        y[c] = R.l[q][0] * P[0][c] + R.l[q][1] * P[1][c] + R.l[q][2] * P[2][c];
+        dx[c] = x[c] - y[c];
+      }
+      const double r = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      const double g0 = inv4pi / r;                      // G = g0 (cs + i sn)
+      const double gr = g0 * cs, gi = g0 * sn;
+      // (i k - 1/r) G / r = ((-1/r) gr - k gi + i (k gr - (1/r) gi)) / r
+      const double hr = (-gr / r - k * gi) / r, hi = (k * gr - gi / r) / r;
+      const double f = R.w[q] * ha, fd = R.w[q] * dv;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double ph = f * (y[c] - P[a][c]);
+        Ar[c] += ph * gr;
+        Ai[c] += ph * gi;
+        Br[c] += fd * hr * dx[c];
+        Bi[c] += fd * hi * dx[c];
+      }
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    // -(i k A + (i/k) B) = (k Ai + Bi/k) - i (k Ar + Br/k)
+    NF[((int64_t)c * n_p + ip) * md.ne + m] = c128{k * Ai[c] + Bi[c] / k, -(k * Ar[c] + Br[c] / k)};
+  }
+}
+
+void near_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xp_dev, int64_t n_p, c128* NF) {
+  dim3 g((unsigned)((m.h.ne + 255) / 256), (unsigned)n_p);
+  hipLaunchKernelGGL(k_near_field_matrix, g, dim3(256), 0, s, m.dev(), make_rule(), k, xp_dev, (int)n_p, NF);
+  FOSB_LAUNCH_CHECK();
+}
+
 // var[r] += scale * Re sum_n P[r][n] conj(F2[r][n]) (P row stride ldp); one
 // block per row, fixed order.
 __global__ __launch_bounds__(256) void k_row_dot_re(const c128* __restrict__ P, int64_t ldp,

@@ -96,6 +96,9 @@ _SIGS = {
     "fosb_lowrank_factor": (C.c_int, [_P, _P, _I32, _I64, _P, _I64, C.POINTER(Stats)]),
     "fosb_far_field_moments_lowrank": (C.c_int, [_P, _P, _I32, _I32, _P, _I64, _I64, _P, C.POINTER(Stats)]),
     "fosb_lowrank_destroy": (C.c_int, [_P]),
+    "fosb_near_field_matrix": (C.c_int, [_P, _P, _P, _I64, _P]),
+    "fosb_near_field_moments": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64), _P,
+                                          _I64, _I64, _P, _P]),
     "fosb_far_field_moments_noalloc": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(_P), C.POINTER(_I64),
                                                  _P, _I64, _I64, _P, _P]),
     "fosb_far_field_moments_backward": (C.c_int, [_P, C.POINTER(_P), _I32, _I32, _I32, C.POINTER(Cov), _P, _I64,
@@ -523,6 +526,30 @@ class LowRank:
             self.close()
         except Exception:
             pass
+
+
+def near_field_matrix(ctx: Context, level: Level, points):
+    import torch
+    x = _host_f64(points).reshape(-1, 3)
+    NF = torch.empty((3 * x.shape[0], level.n), dtype=torch.complex128, device=ctx.torch_device)
+    _check(lib().fosb_near_field_matrix(ctx.h, level.h, x.ctypes.data_as(_P), x.shape[0], _dev(NF)))
+    return NF
+
+
+def near_field_moments(ctx: Context, levels: list[Level], L0: int, L: int, blocks, points, dir: int = 0):
+    """CT variance of the field's shape derivative at field points (3, n_p)
+    float64 and the finest level's scattered field there (3, n_p) complex128."""
+    import torch
+    x = _host_f64(points).reshape(-1, 3)
+    n_p = x.shape[0]
+    var = torch.empty(3 * n_p, dtype=torch.float64, device=ctx.torch_device)
+    mean = torch.empty(3 * n_p, dtype=torch.complex128, device=ctx.torch_device)
+    lv = (_P * len(levels))(*[l.h for l in levels])
+    bp = (_P * len(blocks))(*[_dev(b, torch.complex128) for b in blocks])
+    ld = (_I64 * len(blocks))(*[b.stride(0) for b in blocks])
+    _check(lib().fosb_near_field_moments(ctx.h, lv, len(levels), L0, L, bp, ld, x.ctypes.data_as(_P), n_p, dir,
+                                         _dev(var, torch.float64), _dev(mean)))
+    return var.view(3, n_p), mean.view(3, n_p)
 
 
 def far_field_moments_noalloc(ctx: Context, levels: list[Level], L0: int, L: int, blocks, xhat, var, dir: int = 0,

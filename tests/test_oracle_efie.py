@@ -226,3 +226,34 @@ def test_sauter_schwab_entries_converge_in_order():
     d35, d57, d79 = (np.abs(z[a] - z[b]).max() / scale for a, b in ((3, 5), (5, 7), (7, 9)))
     assert d57 < d35 and d79 < d57, (d35, d57, d79)
     assert d57 < 1e-5, d57   # measured 1.6e-6 (n = 7 vs 9: 1.1e-8)
+
+
+def test_near_field_far_zone_limit():
+    """4 pi r e^{-ikr} NF(r x) tends to the far-field map FF(x) with an O(1/r)
+    error (halves when r doubles)."""
+    from oracle import uq
+    k = 1.0
+    lv = uq.make_level(*workloads.icosphere(2), k)
+    xh = workloads.angles_xz(7)
+    FF = efie.far_field_matrix(lv.mesh, k, xh)
+    errs = []
+    for r in (1e3, 2e3, 4e3):
+        NF = efie.near_field_matrix(lv.mesh, k, r * xh) * 4 * np.pi * r / np.exp(1j * k * r)
+        errs.append(np.abs(NF - FF).max() / np.abs(FF).max())
+    assert errs[-1] < 1e-3 and all(1.9 < errs[i] / errs[i + 1] < 2.1 for i in range(2)), errs
+
+
+def test_near_field_converges_to_mie(oracle_levels):
+    """The scattered field of the Galerkin solution at 20 points on the sphere
+    of radius 2 against the Mie series (k = 1): O(h^2) on s = 1, 2, 3."""
+    from oracle import mie_shape
+    g = np.random.default_rng(0).standard_normal((20, 3))
+    P = 2.0 * g / np.linalg.norm(g, axis=1, keepdims=True)
+    th, ph = np.arccos(P[:, 2] / 2.0), np.arctan2(P[:, 1], P[:, 0])
+    Em = mie_shape.mie_fields(1.0, 2.0, th, ph, part="scattered")
+    errs = []
+    for s in (1, 2, 3):
+        lv = oracle_levels(s)
+        E = np.einsum("cpm,m->pc", efie.near_field_matrix(lv.mesh, 1.0, P), lv.u)
+        errs.append(np.linalg.norm(E - Em) / np.linalg.norm(Em))
+    assert errs[-1] < 1e-2 and errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs

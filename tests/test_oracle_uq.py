@@ -249,3 +249,39 @@ def test_variance_adjoint_route_equals_sigma_route(oracle_levels, kind):
     V, _, _, _, _ = uq.second_moment(None, 1.0, 0, 2, kind, 0.01, 0.5, xh, levels=levels)
     Va = uq.variance_adjoint_route(levels, 0, 2, kind, 0.01, 0.5, xh)
     assert np.abs(Va - V).max() < 1e-11 * np.abs(V).max()
+
+
+def test_near_field_translation_identity(oracle_levels):
+    """Rigid translation c ~ N(0, sigma^2 I) of the sphere: the scattered
+    field moves with it, E_c(x) = e^{i k d.c} E(x - c), so
+    Var[E'_comp](x) = sigma^2 sum_j |i k d_j E_comp(x) - d_j E_comp(x)|^2
+    (d_j: partial derivative, from central differences of the Mie series).
+    The discretised near-field variance (K = sigma^2 n(x).n(y), v_n = v_r)
+    converges to it at second order (s = 1, 2, 3, k = 1, points at r = 2)."""
+    from oracle import mie_shape
+    k, d = 1.0, np.array([0.0, 0.0, 1.0])
+    g = np.random.default_rng(1).standard_normal((12, 3))
+    P = 2.0 * g / np.linalg.norm(g, axis=1, keepdims=True)
+
+    def mie_at(X):
+        r = np.linalg.norm(X, axis=1)
+        return np.stack([mie_shape.mie_fields(k, ri, np.array([np.arccos(x[2] / ri)]),
+                                              np.array([np.arctan2(x[1], x[0])]), part="scattered")[0]
+                         for ri, x in zip(r, X)])
+
+    E = mie_at(P)
+    h = 1e-4
+    ref = np.zeros((len(P), 3))
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        dE = (mie_at(P + e) - mie_at(P - e)) / (2 * h)
+        ref += np.abs(1j * k * d[j] * E - dE) ** 2
+    errs = []
+    for s in (1, 2, 3):
+        lv = oracle_levels(s, k, "normal")
+        C = uq.rhs_correlation(lv, lv, "normal_dot", 1.0, 1.0)
+        NF = efie.near_field_matrix(lv.mesh, k, P)
+        V = uq.pair_variance(NF, uq.two_sided_solve(lv, lv, C), NF)
+        errs.append(_rel(V.T, ref))
+    assert errs[-1] < 2e-2 and errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
