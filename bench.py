@@ -93,6 +93,11 @@ def parse():
     ap.add_argument("--tune-load", default=None, metavar="JSON",
                     help="load a GEMM tile table ({bucket key: variant}, from --tune-dump) before the warmup")
     ap.add_argument("--tune-dump", default=None, metavar="JSON", help="write the GEMM tile table after the run")
+    ap.add_argument("--reassemble", action="store_true",
+                    help="mixed path: the finest level keeps no complex128 copy of Z (Zlow assembled in FP64 bands, "
+                         "refinement residuals with Z re-assembled band by band); needed for superquad_k8 at s=6")
+    ap.add_argument("--save-var", default=None, metavar="NPZ",
+                    help="write each path's variance of the last timed step to this .npz file")
     ap.add_argument("--certify", action="store_true",
                     help="after the timed steps, one untimed step per precision with opts.certify and refinement to "
                          "1e-13: backward error, 1-norm condition estimate and growth factor in the line")
@@ -116,9 +121,11 @@ class Workload:
                 f"{w.n_angles} angles")
 
 
-def gpu_setup(fosb, torch, ctx, W):
+def gpu_setup(fosb, torch, ctx, W, reassemble=False):
     meshes = [fosb.Mesh(ctx, V, F) for V, F in W.w.meshes]
-    Z = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex128, device=ctx.torch_device) for m in meshes]
+    Z = [None if (reassemble and i == len(meshes) - 1) else
+         torch.empty((m.n_edges, m.n_edges), dtype=torch.complex128, device=ctx.torch_device)
+         for i, m in enumerate(meshes)]
     return meshes, Z
 
 
@@ -138,8 +145,9 @@ def one_step(fosb, torch, ctx, W, meshes, Z, Zlow, precision, cov, opts, stage_e
     if ev:
         ev[0].record()
     for s, m, z in zip(w.levels, meshes, Z):
-        fosb.assemble(ctx, m, k, opts, Z=z)
-        _progress(f"assembled s={s}")
+        if z is not None:
+            fosb.assemble(ctx, m, k, opts, Z=z)
+            _progress(f"assembled s={s}")
     if ev:
         ev[1].record()
     levels = []
@@ -196,8 +204,10 @@ def run_gpu(args, W):
             fosb.autotune_load(ctx, {int(k): v for k, v in json.load(f).items()})
     cov = fosb.make_cov(W.w.cov_kind, W.w.sigma, W.w.ell)
     opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
-    meshes, Z = gpu_setup(fosb, torch, ctx, W)
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    if args.reassemble and precs != ["mixed"]:
+        raise SystemExit("--reassemble applies to the mixed path only (use --precision mixed)")
+    meshes, Z = gpu_setup(fosb, torch, ctx, W, args.reassemble)
     Zlow = [None] * len(meshes)
     if "mixed" in precs:
         Zlow = [torch.empty((m.n_edges, m.n_edges), dtype=torch.complex64, device=ctx.torch_device) for m in meshes]
@@ -495,11 +505,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.describe(npairs),
                    "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol, "autotune": args.autotune,
+                   "finest_level_reassembled": bool(args.reassemble),
                    "profile_mode": args.profile_mode},
         "algorithmic_flop_per_step": {"lu": lu_f, "pair_solves": solve_f, "far_field": ff_f},
     }
     for pname, rec in gpu.items():
         line[pname] = {k: v for k, v in rec.items() if k not in ("var", "profile")}
+    if args.save_var:
+        np.savez(args.save_var, **{p: r["var"] for p, r in gpu.items()})
     mie_file = os.path.join(ROOT, "tests", "golden", "mie_shape_oracle.json")
     if W.name == "mixed_k5" and W.w.levels[-1] == 5 and os.path.exists(mie_file):
         with open(mie_file) as f:

@@ -195,6 +195,15 @@ fosb_status fosb_assemble(fosb_context* ctx, const fosb_mesh* mesh, double k, co
  *                    ldzlow) receives the FP32 LU factors, which the level's
  *                    solves apply through the inverses of their 256 x 256
  *                    diagonal blocks (kept by the level).
+ *                    Z may be NULL: the level then assembles the matrix in FP64
+ *                    column bands straight into Zlow (rounded to complex64) and
+ *                    re-assembles FP64 bands of Z for every refinement residual
+ *                    (R -= Z X band by band, each band discarded), so no
+ *                    complex128 copy of Z is ever stored: about 2x the
+ *                    assembly and 2x the residual product per residual, and
+ *                    half the device memory.  Such a level supports no adjoint
+ *                    solve (FOSB_E_UNSUPPORTED); its certificate normalises
+ *                    by the norms of the complex64 rounding of Z.
  * dirs, pols: host, n_dirs x 3 float64 (unit incidence direction, real
  * polarisation).  field: fosb_field.  On an exactly zero pivot returns
  * FOSB_E_SINGULAR. */
@@ -399,7 +408,8 @@ fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level*
 /* ---------------------------------------------------------------- whole pipeline */
 /* One pass of the hot path over a level ladder L0..L (levels[i] = level L0 + i,
  * coarse to fine): EFIE assembly into Z[i] (device, N_i x N_i complex128, row
- * stride ldz[i]; MIXED also needs Zlow[i], complex64, stride ldzlow[i]),
+ * stride ldz[i]; MIXED also needs Zlow[i], complex64, stride ldzlow[i], and
+ * may pass Z[i] = NULL for levels that re-assemble, as for fosb_level_create),
  * factorisation, first moments and RHS weights of every level, the RHS
  * correlation and two-sided solve of every pair of fosb_ct_pairs(L0, L) into
  * blocks[p] (as fosb_correlation), and the far-field variance var (device,

@@ -73,7 +73,7 @@ static void merge_level_certificate(fosb_stats* dst, const Level& L) {
 // B <- Z^{-1} B (or Z^{-H} B) for a factorised level; MIXED levels refine in FP64.
 // With P Z = L U:  Z^{-1} = U^{-1} L^{-1} P  and  Z^{-H} = P^T L^{-H} U^{-H}.
 void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st,
-                         bool adjoint) {
+                         bool adjoint, int max_sweeps) {
   hipStream_t s = ctx.stream;
   const int64_t n = L.n;
   if (nrhs <= 0) return;
@@ -97,7 +97,11 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     if (st) st->ir_sweeps = std::max(st->ir_sweeps, 0);
     return;
   }
-  // mixed: FP32 LU solves + FP64 residuals against the kept complex128 Z
+  // mixed: FP32 LU solves + FP64 residuals against the kept complex128 Z, or
+  // against Z re-assembled band by band when the level keeps no FP64 copy
+  const int sweep_limit = max_sweeps >= 0 ? max_sweeps : L.opts.ir_max_sweeps;
+  if (!L.Z && adjoint && sweep_limit > 0)
+    fail(FOSB_E_UNSUPPORTED, "adjoint solves need the level's stored FP64 matrix (this level re-assembles it)");
   ctx.scratch[2].reserve(bytes128);
   ctx.scratch[3].reserve(bytes128);
   ctx.scratch[4].reserve((size_t)n * nrhs * sizeof(c64));
@@ -149,11 +153,13 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     rel = nn[1] > 0 ? std::sqrt(nn[0] / nn[1]) : 0.0;
     est = it == 0 ? 1.0 : rel * rel / prev;
     if (it > 0) sweeps = it;
-    if (est <= L.opts.ir_tol || it >= L.opts.ir_max_sweeps || (it > 1 && rel >= prev)) break;
+    if (est <= L.opts.ir_tol || it >= sweep_limit || (it > 1 && rel >= prev)) break;
     prev = rel;
     // residual R = Bo - op(Z64) X in FP64 (scratch[5])
     copy_c128(s, Bo, nrhs, Rw, nrhs, n, nrhs);
-    if (!adjoint)
+    if (!Z64)
+      efie_residual(ctx, *L.mesh, L.k, L.opts.n_gauss_singular, X, nrhs, nrhs, Rw, nrhs);
+    else if (!adjoint)
       gemm<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
     else
       gemm_ch<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
@@ -163,7 +169,9 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
   if (st && L.opts.certify && L.z_fro > 0) {
     // normwise backward error of the returned iterate: ||Bo - op(Z64) X|| / (||Z|| ||X|| + ||Bo||)
     copy_c128(s, Bo, nrhs, Rw, nrhs, n, nrhs);
-    if (!adjoint)
+    if (!Z64)
+      efie_residual(ctx, *L.mesh, L.k, L.opts.n_gauss_singular, X, nrhs, nrhs, Rw, nrhs);
+    else if (!adjoint)
       gemm<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
     else
       gemm_ch<double>(ctx, n, nrhs, n, -1.0, Z64, L.ldz, X, nrhs, 1.0, Rw, nrhs);
@@ -181,7 +189,7 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     st->ir_sweeps = std::max(st->ir_sweeps, sweeps);
     st->ir_rel_correction = std::max(st->ir_rel_correction, rel);
   }
-  if (est > L.opts.ir_tol && L.opts.ir_max_sweeps > 0) {
+  if (est > L.opts.ir_tol && sweep_limit > 0) {
     FOSB_HIP(hipStreamSynchronize(s));
     fail(FOSB_E_NOCONV, "refinement stopped at estimated relative error %.3e after %d sweeps (tol %.1e)", est, sweeps,
          L.opts.ir_tol);
@@ -286,9 +294,9 @@ static void check_physics(double k, int32_t precision, const double* dirs, const
 static void check_level_args(const fosb_mesh* mesh, double k, int32_t precision, void* Z, int64_t ldz, void* Zlow,
                              int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs, int32_t field) {
   check_physics(k, precision, dirs, pols, n_dirs, field);
-  REQUIRE(Z, "Z is NULL");
+  REQUIRE(Z || precision == FOSB_PREC_MIXED, "Z is NULL (only a MIXED level may re-assemble its FP64 matrix)");
   const int64_t n = mesh->h.ne;
-  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz < N");
+  if (Z && ldz < n) fail(FOSB_E_WORKSPACE, "ldz < N");
   if (precision == FOSB_PREC_MIXED) {
     REQUIRE(Zlow, "MIXED precision needs the complex64 buffer Zlow");
     if (ldzlow < n) fail(FOSB_E_WORKSPACE, "ldzlow < N");
@@ -309,9 +317,11 @@ static double inverse_norm1_estimate(Context& c, const Level& L) {
   hipStream_t s = c.stream;
   std::vector<c128> h(n);
   DevBuf v((size_t)n * sizeof(c128));
+  // a level without a stored FP64 matrix estimates with its unrefined FP32 factors
+  const int sweeps = L.Z ? -1 : 0;
   auto solve = [&](bool adjoint) {
     FOSB_HIP(hipMemcpyAsync(v.p, h.data(), n * sizeof(c128), hipMemcpyHostToDevice, s));
-    level_solve_inplace(c, L, v.as<c128>(), 1, 1, nullptr, adjoint);
+    level_solve_inplace(c, L, v.as<c128>(), 1, 1, nullptr, adjoint, sweeps);
     FOSB_HIP(hipMemcpyAsync(h.data(), v.p, n * sizeof(c128), hipMemcpyDeviceToHost, s));
     FOSB_HIP(hipStreamSynchronize(s));
   };
@@ -376,16 +386,23 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
   const int64_t nblk = (n + kPanel - 1) / kPanel;
   int64_t info = 0;
   DevBuf cert;
-  if (o.certify) {  // norms of the assembled matrix, before an FP64 factorisation overwrites it
+  // norms of the assembled matrix (certificates), taken before the factorisation
+  // overwrites it: of Z, or of its complex64 rounding for a level that keeps no
+  // FP64 copy (within 1e-7 of the FP64 norms)
+  auto matrix_certificate = [&](bool fp32) {
     cert.alloc(6 * sizeof(double));
-    matrix_norms<double>(c, static_cast<const c128*>(Z), n, ldz, false, cert.as<double>());
+    if (fp32)
+      matrix_norms<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, false, cert.as<double>());
+    else
+      matrix_norms<double>(c, static_cast<const c128*>(Z), n, ldz, false, cert.as<double>());
     double zn[3];
     FOSB_HIP(hipMemcpyAsync(zn, cert.p, sizeof(zn), hipMemcpyDeviceToHost, s));
     FOSB_HIP(hipStreamSynchronize(s));
     L->z_max = zn[0];
     L->z_fro = std::sqrt(zn[1]);
     L->z_one = zn[2];
-  }
+  };
+  if (o.certify && Z) matrix_certificate(false);
   if (precision == FOSB_PREC_FP64) {
     L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
     L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c128));
@@ -393,7 +410,12 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
   } else {
     L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
     L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
-    copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
+    if (Z) {
+      copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
+    } else {  // no FP64 copy: assemble in FP64 column bands straight into complex64
+      assemble_efie_c64(c, *mesh, k, o.n_gauss_singular, static_cast<c64*>(Zlow), ldzlow);
+      if (o.certify) matrix_certificate(true);
+    }
     // the refined solves apply the factors through their diagonal-block inverses
     const size_t bytes = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(c64);
     L->inv_L.alloc(bytes);
@@ -1380,6 +1402,8 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
                                const fosb_opts* opts, fosb_level** levels_out, fosb_stats* stats) {
   API_BEGIN
   REQUIRE(ctx && meshes && Z && ldz && blocks && ldb && xhat && var, "NULL argument");
+  for (int32_t i = 0; i < n_levels; ++i)
+    REQUIRE(Z[i] || precision == FOSB_PREC_MIXED, "Z[%d] is NULL (only MIXED levels may re-assemble)", i);
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
   REQUIRE(precision == FOSB_PREC_FP64 || (Zlow && ldzlow), "MIXED precision needs Zlow and ldzlow");
   for (int32_t i = 0; i < n_levels; ++i) {
@@ -1402,7 +1426,10 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   bind(*ctx);
   {
     int64_t need = (int64_t)1 << 30;  // assembly band
-    for (int32_t i = 0; i < n_levels; ++i) need += level_bytes(meshes[i]->h.ne, meshes[i]->h.nt, precision, n_dirs);
+    for (int32_t i = 0; i < n_levels; ++i) {
+      need += level_bytes(meshes[i]->h.ne, meshes[i]->h.nt, precision, n_dirs);
+      if (!Z[i]) need += (int64_t)8 << 30;  // bands of the re-assembled residual
+    }
     int64_t pair_max = 0;
     for (auto& q : v) {
       const int64_t n1 = meshes[q[0] - L0]->h.ne, n2 = meshes[q[1] - L0]->h.ne;
@@ -1417,7 +1444,7 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   fosb_stats st_main{}, st_aux{};
 
   auto build = [&](Context& c, int i) {
-    {
+    if (Z[i]) {  // a MIXED level without Z assembles its complex64 copy itself
       const double ne = (double)meshes[i]->h.ne;
       ProfScope prof(c, FOSB_K_ASSEMBLE, 0.0, 16.0 * ne * ne);
       assemble_efie(c, *meshes[i], k, o.n_gauss_singular, static_cast<c128*>(Z[i]), ldz[i]);

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <functional>
+
 #include "common.h"
 
 namespace fosb {
@@ -326,7 +328,78 @@ static void ensure_ss_table(Context& ctx, int n) {
   FOSB_HIP(hipStreamSynchronize(ctx.stream));
 }
 
-void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz) {
+// Row-gathered band: Zr[m][c] = Zc[r+(m)][c] + Zc[r-(m)][c] for the 3w local
+// columns of the band (the edge rows of Z restricted to the band's triangle
+// columns; each RWG row is the sum of its two triangles' local rows).
+__global__ __launch_bounds__(256) void k_band_rows(int ne, const int32_t* __restrict__ edge_tri,
+                                                   const int32_t* __restrict__ edge_loc, int ncol,
+                                                   const c128* __restrict__ Zc, int64_t ldc, c128* __restrict__ Zr) {
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (c >= ncol || m >= ne) return;
+  const int64_t rp = 3 * (int64_t)edge_tri[m] + edge_loc[m];
+  const int64_t rm = 3 * (int64_t)edge_tri[ne + m] + edge_loc[ne + m];
+  const c128 u = Zc[rp * ldc + c], v = Zc[rm * ldc + c];
+  Zr[(int64_t)m * ncol + c] = c128{u.re + v.re, u.im + v.im};
+}
+
+// Xt[3 (t - j0) + a][:] = X[edge(t, a)][:] for the band's triangles.
+__global__ __launch_bounds__(256) void k_band_gather_x(int nt, const int32_t* __restrict__ tri_edge, int j0, int w,
+                                                       const c128* __restrict__ X, int64_t ldx, int64_t nrhs,
+                                                       c128* __restrict__ Xt) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y;   // 0 .. 3w-1
+  if (c >= nrhs || r >= 3 * w) return;
+  const int t = j0 + r / 3, a = r % 3;
+  const int e = tri_edge[a * nt + t];
+  Xt[(int64_t)r * nrhs + c] = X[(int64_t)e * ldx + c];
+}
+
+// As k_assemble_gather, into a complex64 matrix: the first part of a column is
+// rounded and stored, the second added to it in FP64 and rounded again.
+__global__ __launch_bounds__(256) void k_assemble_gather_c64(int ne, const int32_t* __restrict__ edge_tri,
+                                                             const int32_t* __restrict__ edge_loc, int j0, int j1,
+                                                             const int32_t* __restrict__ cols, int ncols,
+                                                             const c128* __restrict__ Zc, int64_t ldc,
+                                                             c64* __restrict__ Z, int64_t ldz) {
+  const int ci = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (ci >= ncols || m >= ne) return;
+  const int n = cols[ci];
+  const int tp = edge_tri[n], tm = edge_tri[ne + n];
+  const int64_t rp = 3 * (int64_t)edge_tri[m] + edge_loc[m];
+  const int64_t rm = 3 * (int64_t)edge_tri[ne + m] + edge_loc[ne + m];
+  double sr = 0.0, si = 0.0;
+  const bool has_p = tp >= j0 && tp < j1;
+  if (has_p) {
+    const int64_t c = 3 * (int64_t)(tp - j0) + edge_loc[n];
+    const c128 u = Zc[rp * ldc + c], v = Zc[rm * ldc + c];
+    sr += u.re + v.re;
+    si += u.im + v.im;
+  }
+  if (tm >= j0 && tm < j1) {
+    const int64_t c = 3 * (int64_t)(tm - j0) + edge_loc[ne + n];
+    const c128 u = Zc[rp * ldc + c], v = Zc[rm * ldc + c];
+    sr += u.re + v.re;
+    si += u.im + v.im;
+  }
+  c64* z = Z + (int64_t)m * ldz + n;
+  if (has_p) {
+    *z = c64{(float)sr, (float)si};
+  } else {
+    const c64 o = *z;
+    *z = c64{(float)((double)o.re + sr), (float)((double)o.im + si)};
+  }
+}
+
+namespace {
+// Triangle-column bands of the local EFIE blocks.  For each band [j0, j1) of
+// column triangles, the regular and touching-pair kernels fill Zc (3 nt x 3 w
+// local blocks, row stride ldc) and sink(j0, j1, Zc, ldc, cols, ncols) consumes
+// it; cols lists the RWG columns whose T+ or T- lies in the band.  The band
+// buffer holds about `budget` bytes.
+template <typename Sink>
+void assemble_bands(Context& ctx, const Mesh& m, double k, int n_gauss, int64_t budget, Sink&& sink) {
   hipStream_t s = ctx.stream;
   const MeshHost& h = m.h;
   const int nt = (int)h.nt, ne = (int)h.ne;
@@ -345,16 +418,12 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
   ensure_ss_table(ctx, n_gauss);
   Rule6 R;
   rule6(R.l, R.w);
-  // band width: scratch Zc of 3nt x 3jc complex128 limited to ~1 GiB (wider
-  // bands mean fewer launches with longer gathers; at nt = 20480 a 1 GiB band
-  // assembled faster than 256 and 512 MiB ones, and about as fast as 2 GiB)
-  const int64_t budget = (int64_t)1024 << 20;
   int jc = (int)std::max<int64_t>(1, std::min<int64_t>(nt, budget / (9LL * nt * (int64_t)sizeof(c128))));
   if (jc < nt) jc = std::max(64, jc / 64 * 64);
   jc = std::min(jc, nt);
   const int64_t ldc = 3LL * jc;
-  ctx.scratch[0].reserve((size_t)(3LL * nt) * ldc * sizeof(c128));
-  c128* Zc = ctx.scratch[0].as<c128>();
+  DevBuf band((size_t)(3LL * nt) * ldc * sizeof(c128));
+  c128* Zc = band.as<c128>();
   // column lists per band (host): edges whose T+ or T- lies in the band
   std::vector<int32_t> cols;
   std::vector<int64_t> cbeg;
@@ -370,8 +439,8 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
   DevBuf dcols;
   upload(dcols, cols, s);
   const MeshDev md = m.dev();
-  int band = 0;
-  for (int j0 = 0; j0 < nt; j0 += jc, ++band) {
+  int bi = 0;
+  for (int j0 = 0; j0 < nt; j0 += jc, ++bi) {
     const int j1 = std::min(nt, j0 + jc);
     const int w = j1 - j0;
     dim3 g1((w + 63) / 64, (nt + 3) / 4);
@@ -387,16 +456,64 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
                          ctx.ss_cnt[n_gauss][0], ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], k, j0, Zc, ldc);
       FOSB_LAUNCH_CHECK();
     }
-    const int nc = (int)(cbeg[band + 1] - cbeg[band]);
-    if (nc > 0) {
-      dim3 g3((nc + 63) / 64, (ne + 3) / 4);
-      hipLaunchKernelGGL(k_assemble_gather, g3, dim3(256), 0, s, ne, md.edge_tri, md.edge_loc, j0, j1,
-                         dcols.as<int32_t>() + cbeg[band], nc, Zc, ldc, Z, ldz);
-      FOSB_LAUNCH_CHECK();
-    }
+    sink(j0, j1, (const c128*)Zc, ldc, dcols.as<int32_t>() + cbeg[bi], (int)(cbeg[bi + 1] - cbeg[bi]));
   }
-  // dcols must live until the kernels ran
+  // the band buffer and the column lists must live until the kernels ran
   FOSB_HIP(hipStreamSynchronize(s));
+}
+}  // namespace
+
+void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz) {
+  // 1 GiB bands: at nt = 20480 these assembled faster than 256 and 512 MiB ones, and about as fast as 2 GiB
+  const int ne = (int)m.h.ne;
+  const MeshDev md = m.dev();
+  assemble_bands(ctx, m, k, n_gauss, (int64_t)1024 << 20,
+                 [&](int j0, int j1, const c128* Zc, int64_t ldc, const int32_t* cols, int nc) {
+                   if (nc <= 0) return;
+                   dim3 g3((nc + 63) / 64, (ne + 3) / 4);
+                   hipLaunchKernelGGL(k_assemble_gather, g3, dim3(256), 0, ctx.stream, ne, md.edge_tri,
+                                      md.edge_loc, j0, j1, cols, nc, Zc, ldc, Z, ldz);
+                   FOSB_LAUNCH_CHECK();
+                 });
+}
+
+void assemble_efie_c64(Context& ctx, const Mesh& m, double k, int n_gauss, c64* Z, int64_t ldz) {
+  const int ne = (int)m.h.ne;
+  const MeshDev md = m.dev();
+  assemble_bands(ctx, m, k, n_gauss, (int64_t)1024 << 20,
+                 [&](int j0, int j1, const c128* Zc, int64_t ldc, const int32_t* cols, int nc) {
+                   if (nc <= 0) return;
+                   dim3 g3((nc + 63) / 64, (ne + 3) / 4);
+                   hipLaunchKernelGGL(k_assemble_gather_c64, g3, dim3(256), 0, ctx.stream, ne, md.edge_tri,
+                                      md.edge_loc, j0, j1, cols, nc, Zc, ldc, Z, ldz);
+                   FOSB_LAUNCH_CHECK();
+                 });
+}
+
+void efie_residual(Context& ctx, const Mesh& m, double k, int n_gauss, const c128* X, int64_t ldx, int64_t nrhs,
+                   c128* R, int64_t ldr) {
+  if (nrhs <= 0) return;
+  const int ne = (int)m.h.ne, nt = (int)m.h.nt;
+  const MeshDev md = m.dev();
+  // R -= sum over bands (rows of Z on the band's local columns) x (X at the band's local columns)
+  const int64_t budget = (int64_t)4096 << 20;
+  int jc = (int)std::max<int64_t>(1, std::min<int64_t>(nt, budget / (9LL * nt * (int64_t)sizeof(c128))));
+  if (jc < nt) jc = std::max(64, jc / 64 * 64);
+  jc = std::min(jc, nt);
+  DevBuf zr((size_t)ne * 3 * jc * sizeof(c128)), xt((size_t)3 * jc * nrhs * sizeof(c128));
+  assemble_bands(ctx, m, k, n_gauss, budget,
+                 [&](int j0, int j1, const c128* Zc, int64_t ldc, const int32_t*, int) {
+                   const int w = j1 - j0, ncol = 3 * w;
+                   dim3 g1((ncol + 63) / 64, (ne + 3) / 4);
+                   hipLaunchKernelGGL(k_band_rows, g1, dim3(256), 0, ctx.stream, ne, md.edge_tri, md.edge_loc,
+                                      ncol, Zc, ldc, zr.as<c128>());
+                   FOSB_LAUNCH_CHECK();
+                   dim3 g2((unsigned)((nrhs + 255) / 256), (unsigned)ncol);
+                   hipLaunchKernelGGL(k_band_gather_x, g2, dim3(256), 0, ctx.stream, nt, md.tri_edge, j0, w, X, ldx,
+                                      nrhs, xt.as<c128>());
+                   FOSB_LAUNCH_CHECK();
+                   gemm<double>(ctx, ne, nrhs, ncol, -1.0, zr.as<c128>(), ncol, xt.as<c128>(), nrhs, 1.0, R, ldr);
+                 });
 }
 
 }  // namespace fosb

@@ -306,6 +306,11 @@ constexpr int kPanel = 32;   // LU panel width / TRSM diagonal block size
 // ------------------------------------------------------------------ kernels (host launchers)
 // assemble.hip
 void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz);
+// the same matrix assembled in FP64 and stored rounded to complex64 (no complex128 copy)
+void assemble_efie_c64(Context& ctx, const Mesh& m, double k, int n_gauss, c64* Z, int64_t ldz);
+// R (N x nrhs) -= Z X in FP64 with Z re-assembled band by band and discarded
+void efie_residual(Context& ctx, const Mesh& m, double k, int n_gauss, const c128* X, int64_t ldx, int64_t nrhs,
+                   c128* R, int64_t ldr);
 // gemm.hip: C = beta*C + alpha*A*B, complex, row-major.
 template <typename T>
 void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
@@ -435,8 +440,9 @@ void lr_rhs(hipStream_t s, const Level& l, int64_t dir, const double* L, int64_t
             double* Lr, c128* M);
 
 // level-wide solves (api.cpp helpers)
-// B <- Z^{-1} B, or B <- Z^{-H} B (adjoint)
+// B <- Z^{-1} B, or B <- Z^{-H} B (adjoint); max_sweeps >= 0 overrides the
+// level's refinement sweep limit (0: the factors' solve alone)
 void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int64_t nrhs, fosb_stats* st,
-                         bool adjoint = false);
+                         bool adjoint = false, int max_sweeps = -1);
 
 }  // namespace fosb

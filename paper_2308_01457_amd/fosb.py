@@ -327,7 +327,9 @@ class Level:
         p = _host_f64(pols).reshape(-1, 3)
         fld = FIELDS[field] if isinstance(field, str) else int(field)
         h = _P()
-        _check(lib().fosb_level_create(ctx.h, mesh.h, self.k, precision, _dev(Z, torch.complex128), Z.stride(0),
+        _check(lib().fosb_level_create(ctx.h, mesh.h, self.k, precision,
+                                       _dev(Z, torch.complex128) if Z is not None else None,
+                                       Z.stride(0) if Z is not None else 0,
                                        _dev(Zlow, torch.complex64) if Zlow is not None else None,
                                        Zlow.stride(0) if Zlow is not None else 0, d.ctypes.data_as(_P),
                                        p.ctypes.data_as(_P), d.shape[0], fld, C.byref(opts) if opts else None,
@@ -652,8 +654,8 @@ def second_moment(ctx: Context, meshes: list[Mesh], L0: int, L: int, k: float, p
     var = torch.empty(nd * 3 * x.shape[0], dtype=torch.float64, device=dev)
     st = stats if stats is not None else Stats()
     ms = (_P * n)(*[m.h for m in meshes])
-    zp = (_P * n)(*[_dev(z, torch.complex128) for z in Z])
-    zl = (_I64 * n)(*[z.stride(0) for z in Z])
+    zp = (_P * n)(*[_dev(z, torch.complex128) if z is not None else None for z in Z])
+    zl = (_I64 * n)(*[z.stride(0) if z is not None else 0 for z in Z])
     if precision == MIXED:
         lp = (_P * n)(*[_dev(z, torch.complex64) for z in Zlow])
         ll = (_I64 * n)(*[z.stride(0) for z in Zlow])
