@@ -350,6 +350,12 @@ def run_batched(args):
         t = float(np.mean(times))
         out[pname] = {"seconds_per_step": t, "pair_solves_per_s": npairs / t, "ir_sweeps": int(st.ir_sweeps),
                       "var": torch.stack([r.reshape(-1) for r in [x.reshape(-1) for x in res]]).cpu().numpy()}
+        if not args.no_profile:
+            log(f"[bench] ellipsoids {pname}: profiled step")
+            fosb.profile_enable(ctx, True)
+            step(prec)
+            out[pname]["profile"] = fosb.profile_read(ctx)
+            fosb.profile_enable(ctx, False)
     head = "mixed" if "mixed" in out else "fp64"
     line = {"metric": "Cor[u'] level-pair solves/sec + MFMA TFLOP/s, mixed vs FP64 at 1e-6 rel err",
             "value": out[head]["pair_solves_per_s"], "unit": "level-pair solves/s", "n_gpus": 1,
@@ -362,7 +368,23 @@ def run_batched(args):
                        "precision": head, "ir_tol": args.ir_tol, "level_pair_solves": npairs,
                        "shapes_in_flight": args.workers}}
     for pname, rec in out.items():
-        line[pname] = {k: v for k, v in rec.items() if k != "var"}
+        line[pname] = {k: v for k, v in rec.items() if k not in ("var", "profile")}
+    for pname, rec in out.items():   # dominant kernel of each path: its complex GEMM
+        prof = rec.get("profile")
+        if not prof:
+            continue
+        kname = "gemm_f32" if pname == "mixed" else "gemm_f64"
+        n, sec, fl, by = prof[kname]
+        ach = fl / sec / 1e12 if sec > 0 else 0.0
+        key = "roofline" if pname == head else f"roofline_{pname}"
+        line[key] = {"kernel": f"k_gemm<{'float' if pname == 'mixed' else 'double'}>", "bound": "mfma",
+                     "achieved": ach, "peak": PEAK[pname], "unit": "TFLOP/s", "frac": ach / PEAK[pname],
+                     "traffic": None, "launches": n, "avg_launch_us": sec / max(n, 1) * 1e6,
+                     "algorithmic_flop_per_launch": fl / max(n, 1), "algorithmic_bytes_per_launch": by / max(n, 1),
+                     "concurrent_streams": args.workers}
+        line[f"kernel_profile_{pname}"] = {k: {"launches": v[0], "seconds": v[1],
+                                               "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
+                                               "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof.items()}
     if "mixed" in out and "fp64" in out:
         a, b = out["mixed"]["var"], out["fp64"]["var"]
         line["mixed_speedup_vs_fp64"] = out["fp64"]["seconds_per_step"] / out["mixed"]["seconds_per_step"]
