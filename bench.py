@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--reassemble", action="store_true",
                     help="mixed path: the finest level keeps no complex128 copy of Z (Zlow assembled in FP64 bands, "
                          "refinement residuals with Z re-assembled band by band); needed for superquad_k8 at s=6")
+    ap.add_argument("--no-stages", action="store_true",
+                    help="skip the extra step through the step-by-step calls that times each stage")
     ap.add_argument("--save-var", default=None, metavar="NPZ",
                     help="write each path's variance of the last timed step to this .npz file")
     ap.add_argument("--certify", action="store_true",
@@ -193,6 +195,48 @@ def algorithmic_flops(W):
     return lu, solve, ff, len(pairs)
 
 
+def assembly_point_pairs(W, n_gauss=5):
+    """Point pairs the assembly integrates per step: 36 (6 x 6 points) per
+    ordered non-touching triangle pair, and the Sauter-Schwab points of the
+    touching ones (6, 5, 2 regions of n^4 points for identical, edge- and
+    vertex-adjacent pairs)."""
+    import scipy.sparse as sp
+    reg = sing = 0
+    for V, F in W.w.meshes:
+        nt, nv = F.shape[0], V.shape[0]
+        inc = sp.csr_matrix((np.ones(3 * nt), (np.repeat(np.arange(nt), 3), F.reshape(-1))), shape=(nt, nv))
+        shared = (inc @ inc.T).tocoo()   # vertices shared by each ordered pair
+        cnt = np.bincount(shared.data.astype(np.int64), minlength=4)
+        touching = cnt[1] + cnt[2] + cnt[3]
+        reg += 36 * (nt * nt - touching)
+        sing += n_gauss ** 4 * (6 * cnt[3] + 5 * cnt[2] + 2 * cnt[1])
+    return int(reg), int(sing)
+
+
+def stage_report(t, lu_f, solve_f, pname, sweeps):
+    """Seconds per stage of one step through the step-by-step calls, and each
+    compute stage against its MFMA bound.  LU: (8/3) N^3 per level at the
+    factor's precision.  Pairs: the two-sided solves, 8 N1 N2 (N1 + N2) per pair;
+    on the mixed path each refinement sweep adds one FP64 residual product and
+    one FP32 correction solve of the same flop count, so the stage executes
+    (1 + sweeps) x that in FP32 and sweeps x that in FP64."""
+    asm, lu, pairs, ff = t
+    p32, p64 = PEAK["mixed"] * 1e12, PEAK["fp64"] * 1e12
+    if pname == "mixed":
+        f32, f64 = solve_f * (1 + sweeps), solve_f * sweeps
+        lu_peak = p32
+    else:
+        f32, f64 = 0.0, solve_f
+        lu_peak = p64
+    bound = f32 / p32 + f64 / p64
+    return {"assemble_s": asm, "far_field_s": ff,
+            "lu_first_moment": {"seconds": lu, "algorithmic_flop": lu_f, "achieved_tflops": lu_f / lu / 1e12,
+                                "peak_tflops": lu_peak / 1e12, "frac": lu_f / lu_peak / lu},
+            "pairs": {"seconds": pairs, "algorithmic_flop": solve_f, "refinement_sweeps": sweeps,
+                      "executed_flop_fp32": f32, "executed_flop_fp64": f64, "bound_seconds_at_peaks": bound,
+                      "frac": bound / pairs}}
+
+
 def run_gpu(args, W):
     import torch
     from paper_2308_01457_amd import fosb
@@ -267,6 +311,15 @@ def run_gpu(args, W):
             prof = fosb.profile_read(ctx)
             fosb.profile_enable(ctx, False)
             rec["profile"] = prof
+        if not args.no_stages and args.schedule == "concurrent":
+            log(f"[bench] {pname}: staged step")
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            torch.cuda.synchronize()
+            _, blk, lvs, sst = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts, ev)
+            torch.cuda.synchronize()
+            del blk, lvs
+            rec["stages"] = stage_report([ev[j].elapsed_time(ev[j + 1]) * 1e-3 for j in range(4)], lu_f, solve_f,
+                                         pname, int(sst.ir_sweeps))
         if args.certify:
             log(f"[bench] {pname}: certified step")
             copts = fosb.opts_default(ir_tol=1e-13, ir_max_sweeps=20, certify=1)
@@ -560,6 +613,11 @@ def main():
                             "algorithmic_bytes_per_launch": by / max(n, 1)}
         line["kernel_profile"] = {k: {"launches": v[0], "seconds": v[1], "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
                                       "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof.items()}
+        reg, sing = assembly_point_pairs(W)
+        asec = prof["assemble"][1]
+        line["assembly"] = {"regular_point_pairs": reg, "singular_point_pairs": sing, "seconds": asec,
+                            "point_pairs_per_s": (reg + sing) / asec if asec > 0 else None,
+                            "note": "all assembly kernels of one step (regular, touching, gather), FP64"}
     prof64 = gpu.get("fp64", {}).get("profile") if head == "mixed" else None
     if prof64:   # the FP64 path's dominant kernel, for the mixed-versus-FP64 comparison
         n, sec, fl, by = prof64["gemm_f64"]
