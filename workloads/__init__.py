@@ -153,6 +153,13 @@ def angles_xz(n: int) -> np.ndarray:
     return np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], axis=1)
 
 
+def angles_xy(n: int) -> np.ndarray:
+    """n unit observation directions in the plane z = 0, theta_i = 2 pi i / n
+    (the angles of the experiments section), x_hat = (cos theta, sin theta, 0)."""
+    th = 2.0 * np.pi * np.arange(n) / n
+    return np.stack([np.cos(th), np.sin(th), np.zeros_like(th)], axis=1)
+
+
 def kite_field(X: np.ndarray) -> np.ndarray:
     """Deterministic perturbation field of the FOA-versus-ZOA experiment
     (kite experiment of the paper), evaluated at points X (..., 3):
