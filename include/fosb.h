@@ -85,6 +85,12 @@ typedef enum fosb_field {
   FOSB_FIELD_NORMAL = 1    /* v_n = v_r                                            */
 } fosb_field;
 
+/* Boundary integral equation of a level. */
+typedef enum fosb_formulation {
+  FOSB_FORM_EFIE = 0,    /* PEC: EFIE on RWG, N = number of edges                 */
+  FOSB_FORM_PMCHWT = 1   /* dielectric: PMCHWT on RWG, N = 2 x edges, [J; M]      */
+} fosb_formulation;
+
 typedef struct fosb_cov {
   int32_t kind;   /* fosb_cov_kind                                                */
   int32_t pad;
@@ -181,6 +187,23 @@ fosb_status fosb_mesh_destroy(fosb_mesh* mesh);
 fosb_status fosb_assemble(fosb_context* ctx, const fosb_mesh* mesh, double k, const fosb_opts* opts,
                           void* Z, int64_t ldz);
 
+/* Galerkin PMCHWT matrix of the dielectric problem (problem setting: the
+ * transmission problem, the MFIO K_k, the multitrace operators A_k and their
+ * eta-scaled interior form, the PMCHWT equation; Galerkin section, first
+ * moments), for the exterior total traces J = n x H~ (H~ = eta0 H, eta0 = 1)
+ * and M = -n x E on RWG, tested with RWG:
+ *   Z = [ T0 + eta T1     K0 + K1        ]   (2N x 2N, N = number of edges)
+ *       [ -(K0 + K1)      T0 + T1 / eta  ]
+ *   T_i  the EFIE matrix of fosb_assemble at k_i,
+ *   K_i[m][n] = int int phi_m(x) . (grad_x G_ki(x,y) x phi_n(y)) dx dy (principal value),
+ *   k1 = k0 sqrt(eps_r mu_r), eta = sqrt(mu_r / eps_r).
+ * Same quadrature as fosb_assemble (the MFIO blocks of identical flat
+ * triangles vanish).  FP64 throughout.  Z: device, 2N x 2N complex128, row
+ * stride ldz >= 2N.  eps_r, mu_r real and > 0; k0 > 0 with k1 times the mesh's
+ * bounding-box diagonal at most 1e5, else FOSB_E_INVALID.  opts may be NULL. */
+fosb_status fosb_assemble_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, double k0, double eps_r, double mu_r,
+                                 const fosb_opts* opts, void* Z, int64_t ldz);
+
 /* ---------------------------------------------------------------- level */
 /* A mesh level ready for the tensor solves: LU factorisation with partial
  * pivoting (tournament pivoting per 32-column panel), the first moment
@@ -211,6 +234,27 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
                               void* Z, int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs,
                               const double* pols, int64_t n_dirs, int32_t field,
                               const fosb_opts* opts, fosb_level** out);
+/* A dielectric level: the PMCHWT matrix Z of fosb_assemble_pmchwt (2N x 2N)
+ * factored as for fosb_level_create (FP64, or MIXED with Zlow 2N x 2N
+ * complex64; Z may not be NULL), and the first moments u = Z^{-1} b for each
+ * plane wave E^inc = p exp(i k0 d.x), H~^inc = (d x p) exp(i k0 d.x):
+ *   b = [e; h],  e[m] = int phi_m . E^inc,  h[m] = int phi_m . H~^inc.
+ * The level keeps b: fosb_rhs_correlation and fosb_correlation on dielectric
+ * levels take cov = NULL and form the rank-one right-hand side
+ * C = b_l1 b_l2^H of the paper's sphere validation (a second moment with
+ * M2[f] = f (x) f, whose solution is u_l1 u_l2^H).  fosb_level_solve,
+ * fosb_level_solve_adjoint, fosb_level_first_moment, fosb_two_sided_solve,
+ * fosb_far_field_matrix and fosb_far_field_moments accept dielectric levels;
+ * the entry points that need the shape-derivative weights of the PEC
+ * problem (low-rank, adjoint-route and backward variance, near field,
+ * whole-pass and batch entry points) return FOSB_E_UNSUPPORTED for them. */
+fosb_status fosb_level_create_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, double k0, double eps_r,
+                                     double mu_r, int32_t precision, void* Z, int64_t ldz, void* Zlow,
+                                     int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs,
+                                     const fosb_opts* opts, fosb_level** out);
+/* The level's formulation (fosb_formulation) and, for FOSB_FORM_PMCHWT, its
+ * eps_r and mu_r (1 for EFIE levels).  Any output pointer may be NULL. */
+fosb_status fosb_level_formulation(const fosb_level* level, int32_t* form, double* eps_r, double* mu_r);
 fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precision, int64_t* n_dirs);
 /* Device bytes a level built on mesh with this precision and n_dirs
  * incidences keeps for its lifetime (permutation, diagonal-block inverses,
@@ -242,7 +286,9 @@ fosb_status fosb_level_destroy(fosb_level* level);
  * second-moment tensor equation; combination-technique sub-systems), with K
  * the covariance of the amplitude at the quadrature nodes of both levels.
  * C: device, N1 x N2 complex128, row stride ldc >= N2.  dir selects the
- * incidence (first moment) of both levels. */
+ * incidence (first moment) of both levels.  Dielectric levels (cov = NULL):
+ * the rank-one C = b_l1 b_l2^H of their right-hand sides (sphere validation
+ * of the DE second moment, M2[f] = f (x) f). */
 fosb_status fosb_rhs_correlation(fosb_context* ctx, const fosb_level* l1, const fosb_level* l2,
                                  const fosb_cov* cov, int64_t dir, void* C, int64_t ldc);
 /* In place: C (N1 x N2) <- Sigma with Z1 Sigma Z2^H = C, i.e. the sub-system
@@ -258,14 +304,17 @@ fosb_status fosb_ct_pairs(int32_t L0, int32_t L, int32_t* l1, int32_t* l2, int32
                           int32_t* mult, int32_t* n_pairs);
 /* All Sigma blocks of Lambda_H for direction dir.  levels[i] is level L0 + i
  * (n_levels = L - L0 + 1); blocks[p] (device, N_l1 x N_l2 complex128, row
- * stride ldb[p]) receives the block of pair p in fosb_ct_pairs order. */
+ * stride ldb[p]) receives the block of pair p in fosb_ct_pairs order.
+ * Dielectric levels take cov = NULL (rank-one right-hand sides). */
 fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
                              int32_t L0, int32_t L, const fosb_cov* cov, int64_t dir,
                              void* const* blocks, const int64_t* ldb, fosb_stats* stats);
 
 /* ---------------------------------------------------------------- far field */
 /* Far-field map of a level (problem setting, far-field expansion):
- *   F_c(x) = sum_m FF[c*n_a + i][m] u_m,  FF = -i k (I - x x^T) int phi_m(y) exp(-i k x.y) dy.
+ *   F_c(x) = sum_m FF[c*n_a + i][m] u_m,  FF = -i k (I - x x^T) int phi_m(y) exp(-i k x.y) dy;
+ * for a dielectric level (u = [J; M], exterior field E_k0 J - H_k0 M)
+ *   FF = [ i k0 (I - x x^T) A_m  |  -i k0 x x A_m ],  A_m = int phi_m(y) exp(-i k0 x.y) dy.
  * xhat: host, n_a x 3 unit vectors.  FF: device, (3 n_a) x N complex128. */
 fosb_status fosb_far_field_matrix(fosb_context* ctx, const fosb_level* level, const double* xhat,
                                   int64_t n_a, void* FF);

@@ -367,10 +367,15 @@ static double inverse_norm1_estimate(Context& c, const Level& L) {
 static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh, double k, int32_t precision,
                                                void* Z, int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs,
                                                const double* pols, int64_t n_dirs, int32_t field,
-                                               const fosb_opts& o) {
+                                               const fosb_opts& o, int32_t form = FOSB_FORM_EFIE,
+                                               double eps_r = 1.0, double mu_r = 1.0) {
   hipStream_t s = c.stream;
-  const int64_t n = mesh->h.ne;
+  const bool pm = form == FOSB_FORM_PMCHWT;
+  const int64_t n = pm ? 2 * mesh->h.ne : mesh->h.ne;
   std::unique_ptr<fosb_level> L(new fosb_level());
+  L->form = form;
+  L->eps_r = eps_r;
+  L->mu_r = mu_r;
   L->ctx = &c;
   L->mesh = mesh;
   L->k = k;
@@ -438,14 +443,23 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     FOSB_HIP(hipStreamSynchronize(s));
     L->growth = L->z_max > 0 ? un[0] / L->z_max : 0.0;
   }
-  // quadrature nodes, first moments and RHS weights
-  L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));
-  quad_nodes(s, *mesh, L->qx.as<double>());
   std::vector<double> dp(dirs, dirs + 3 * n_dirs), pp(pols, pols + 3 * n_dirs);
   DevBuf ddir, dpol;
   upload(ddir, dp, s);
   upload(dpol, pp, s);
   L->u.alloc((size_t)n * n_dirs * sizeof(c128));
+  if (pm) {  // dielectric: keep the right-hand sides b = [e; h], first moments u = Z^{-1} b
+    L->b.alloc((size_t)n * n_dirs * sizeof(c128));
+    incident_rhs_pmchwt(s, *mesh, k, ddir.as<double>(), dpol.as<double>(), (int)n_dirs, L->b.as<c128>());
+    copy_c128(s, L->b.as<c128>(), n_dirs, L->u.as<c128>(), n_dirs, n, n_dirs);
+    level_solve_inplace(c, *L, L->u.as<c128>(), n_dirs, n_dirs, nullptr);
+    if (o.certify) L->kappa1 = L->z_one * inverse_norm1_estimate(c, *L);
+    FOSB_HIP(hipStreamSynchronize(s));
+    return L;
+  }
+  // quadrature nodes, first moments and RHS weights
+  L->qx.alloc((size_t)3 * 6 * mesh->h.nt * sizeof(double));
+  quad_nodes(s, *mesh, L->qx.as<double>());
   incident_rhs(s, *mesh, k, ddir.as<double>(), dpol.as<double>(), (int)n_dirs, L->u.as<c128>());
   level_solve_inplace(c, *L, L->u.as<c128>(), n_dirs, n_dirs, nullptr);
   L->W.alloc((size_t)n_dirs * mesh->h.nt * 18 * sizeof(c128));
@@ -506,7 +520,37 @@ static void check_pair(const fosb_context* ctx, const fosb_level* a, const fosb_
   REQUIRE(a->k == b->k, "levels have different wavenumbers");
   REQUIRE(a->n_dirs == b->n_dirs, "levels have different incidence sets");
   REQUIRE(a->field == b->field, "levels use different perturbation fields");
+  REQUIRE(a->form == b->form && a->eps_r == b->eps_r && a->mu_r == b->mu_r,
+          "levels use different formulations or materials");
 }
+
+// Entry points built on the PEC shape-derivative weights take EFIE levels only.
+static void require_efie(const fosb_level* const* levels, int32_t n) {
+  for (int32_t i = 0; i < n; ++i)
+    if (levels[i] && levels[i]->form != FOSB_FORM_EFIE)
+      fail(FOSB_E_UNSUPPORTED, "this entry point needs EFIE levels (the dielectric shape-derivative right-hand "
+                               "side is not built)");
+}
+
+// Far-field map of a level of either formulation (rows 3 n_a, N columns).
+static void level_far_field(hipStream_t s, const Level& l, const double* dx, int64_t n_a, c128* FF) {
+  if (l.form == FOSB_FORM_PMCHWT)
+    far_field_matrix_pmchwt(s, *l.mesh, l.k, dx, n_a, FF);
+  else
+    far_field_matrix_kernel(s, *l.mesh, l.k, dx, n_a, FF);
+}
+
+// RHS correlation of a pair: the covariance form (EFIE) or the rank-one
+// b_l1 b_l2^H (PMCHWT, cov NULL).
+static void pair_rhs(hipStream_t s, const Level& a, const Level& b, const fosb_cov* cov, int64_t dir, c128* C,
+                     int64_t ldc) {
+  if (a.form == FOSB_FORM_PMCHWT)
+    rank_one_correlation(s, a.b.as<c128>(), a.n, b.b.as<c128>(), b.n, a.n_dirs, dir, C, ldc);
+  else
+    rhs_correlation_kernel(s, a, b, *cov, dir, C, ldc);
+}
+
+static void check_cov_for(const fosb_level* l, const fosb_cov* cov);
 
 static void check_cov(const fosb_cov* cov) {
   REQUIRE(cov, "cov is NULL");
@@ -514,6 +558,13 @@ static void check_cov(const fosb_cov* cov) {
   REQUIRE(std::isfinite(cov->sigma) && cov->sigma >= 0, "sigma must be >= 0");
   if (cov->kind == FOSB_COV_GAUSSIAN || cov->kind == FOSB_COV_MATERN32)
     REQUIRE(std::isfinite(cov->ell) && cov->ell > 0, "ell must be > 0");
+}
+
+static void check_cov_for(const fosb_level* l, const fosb_cov* cov) {
+  if (l->form == FOSB_FORM_PMCHWT)
+    REQUIRE(!cov, "dielectric levels take cov = NULL (rank-one right-hand side)");
+  else
+    check_cov(cov);
 }
 
 static std::vector<std::array<int32_t, 4>> ct_pairs_vec(int32_t L0, int32_t L) {
@@ -562,7 +613,7 @@ static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t 
     if (near)  // scattered field at field points instead of the far field at directions
       near_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
     else
-      far_field_matrix_kernel(s, *levels[i]->mesh, levels[i]->k, dx.as<double>(), n_a, FF[i].as<c128>());
+      level_far_field(s, *levels[i], dx.as<double>(), n_a, FF[i].as<c128>());
   }
   FOSB_HIP(hipMemsetAsync(var, 0, nd * rows * sizeof(double), s));
   if (cor) {
@@ -824,6 +875,83 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
   API_END
 }
 
+static void check_material(double k0, double eps_r, double mu_r, const fosb_mesh* mesh) {
+  REQUIRE(std::isfinite(k0) && k0 > 0, "wavenumber must be positive and finite");
+  REQUIRE(std::isfinite(eps_r) && eps_r > 0 && std::isfinite(mu_r) && mu_r > 0, "eps_r and mu_r must be > 0");
+  const MeshHost& h = mesh->h;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < h.nv; ++v)
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = std::min(lo[q], h.V[3 * v + q]);
+      hi[q] = std::max(hi[q], h.V[3 * v + q]);
+    }
+  const double diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  const double k1 = k0 * std::sqrt(eps_r * mu_r);
+  REQUIRE(std::max(k0, k1) * diag <= 1e5, "max(k0, k1) * (mesh bounding-box diagonal) = %g exceeds 1e5",
+          std::max(k0, k1) * diag);
+}
+
+fosb_status fosb_assemble_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, double k0, double eps_r, double mu_r,
+                                 const fosb_opts* opts, void* Z, int64_t ldz) {
+  API_BEGIN
+  REQUIRE(ctx && mesh, "ctx/mesh is NULL");
+  REQUIRE(mesh->ctx == ctx, "mesh belongs to another context");
+  check_material(k0, eps_r, mu_r, mesh);
+  REQUIRE(Z, "Z is NULL");
+  const int64_t n = 2 * mesh->h.ne;
+  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz (%lld) < 2N (%lld)", (long long)ldz, (long long)n);
+  fosb_opts o = opts_or_default(opts);
+  bind(*ctx);
+  {
+    ProfScope prof(*ctx, FOSB_K_ASSEMBLE, 0.0, 2.0 * 16.0 * (double)n * (double)n);
+    assemble_pmchwt(*ctx, *mesh, k0, eps_r, mu_r, o.n_gauss_singular, static_cast<c128*>(Z), ldz);
+  }
+  API_END
+}
+
+fosb_status fosb_level_create_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, double k0, double eps_r,
+                                     double mu_r, int32_t precision, void* Z, int64_t ldz, void* Zlow,
+                                     int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs,
+                                     const fosb_opts* opts, fosb_level** out) {
+  API_BEGIN
+  REQUIRE(ctx && mesh && out, "ctx/mesh/out is NULL");
+  *out = nullptr;
+  REQUIRE(mesh->ctx == ctx, "mesh belongs to another context");
+  check_material(k0, eps_r, mu_r, mesh);
+  check_physics(k0, precision, dirs, pols, n_dirs, FOSB_FIELD_NORMAL);
+  REQUIRE(Z, "Z is NULL (a dielectric level keeps its FP64 matrix)");
+  const int64_t n = 2 * mesh->h.ne;
+  if (ldz < n) fail(FOSB_E_WORKSPACE, "ldz < 2N");
+  if (precision == FOSB_PREC_MIXED) {
+    REQUIRE(Zlow, "MIXED precision needs the complex64 buffer Zlow");
+    if (ldzlow < n) fail(FOSB_E_WORKSPACE, "ldzlow < 2N");
+  } else {
+    REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
+  }
+  fosb_opts o = opts_or_default(opts);
+  bind(*ctx);
+  check_device_memory(*ctx, level_bytes(n, 0, precision, n_dirs) + solve_work_bytes(n, precision, n_dirs),
+                      "the level");
+  auto L = level_build(*ctx, mesh, k0, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, FOSB_FIELD_NORMAL, o,
+                       FOSB_FORM_PMCHWT, eps_r, mu_r);
+  {
+    std::lock_guard<std::mutex> lock(ctx->reg_mu);
+    ctx->live_levels.insert(L.get());
+  }
+  *out = L.release();
+  API_END
+}
+
+fosb_status fosb_level_formulation(const fosb_level* level, int32_t* form, double* eps_r, double* mu_r) {
+  API_BEGIN
+  REQUIRE(level, "level is NULL");
+  if (form) *form = level->form;
+  if (eps_r) *eps_r = level->eps_r;
+  if (mu_r) *mu_r = level->mu_r;
+  API_END
+}
+
 fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precision, int64_t* n_dirs) {
   API_BEGIN
   REQUIRE(level, "level is NULL");
@@ -905,11 +1033,11 @@ fosb_status fosb_rhs_correlation(fosb_context* ctx, const fosb_level* l1, const 
   API_BEGIN
   REQUIRE(ctx && C, "ctx/C is NULL");
   check_pair(ctx, l1, l2);
-  check_cov(cov);
+  check_cov_for(l1, cov);
   REQUIRE(dir >= 0 && dir < l1->n_dirs, "dir out of range");
   if (ldc < l2->n) fail(FOSB_E_WORKSPACE, "ldc < N2");
   bind(*ctx);
-  rhs_correlation_kernel(ctx->stream, *l1, *l2, *cov, dir, static_cast<c128*>(C), ldc);
+  pair_rhs(ctx->stream, *l1, *l2, cov, dir, static_cast<c128*>(C), ldc);
   API_END
 }
 
@@ -946,8 +1074,8 @@ fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels,
   API_BEGIN
   REQUIRE(ctx && levels && blocks && ldb, "NULL argument");
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
-  check_cov(cov);
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
+  check_cov_for(levels[0], cov);
   REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
   auto v = ct_pairs_vec(L0, L);
   for (size_t p = 0; p < v.size(); ++p) {
@@ -961,7 +1089,7 @@ fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels,
     c128* C = static_cast<c128*>(blocks[p]);
     {
       ProfScope prof(*ctx, FOSB_K_RHS, 0.0, 16.0 * (double)a->n * (double)b->n);
-      rhs_correlation_kernel(ctx->stream, *a, *b, *cov, dir, C, ldb[p]);
+      pair_rhs(ctx->stream, *a, *b, cov, dir, C, ldb[p]);
     }
     two_sided(*ctx, *a, *b, C, ldb[p], stats);
   }
@@ -978,7 +1106,7 @@ fosb_status fosb_far_field_matrix(fosb_context* ctx, const fosb_level* level, co
   std::vector<double> x(xhat, xhat + 3 * n_a);
   DevBuf dx;
   upload(dx, x, ctx->stream);
-  far_field_matrix_kernel(ctx->stream, *level->mesh, level->k, dx.as<double>(), n_a, static_cast<c128*>(FF));
+  level_far_field(ctx->stream, *level, dx.as<double>(), n_a, static_cast<c128*>(FF));
   FOSB_HIP(hipStreamSynchronize(ctx->stream));
   API_END
 }
@@ -1004,6 +1132,7 @@ fosb_status fosb_far_field_variance_adjoint(fosb_context* ctx, const fosb_level*
   API_BEGIN
   REQUIRE(ctx && levels && xhat && var, "NULL argument");
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  require_efie(levels, n_levels);
   REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
   check_cov(cov);
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
@@ -1065,6 +1194,7 @@ fosb_status fosb_lowrank_create(fosb_context* ctx, const fosb_level* const* leve
   REQUIRE(ctx && levels && out, "NULL argument");
   *out = nullptr;
   REQUIRE(n_levels >= 1 && n_levels <= 64, "n_levels must be 1..64");
+  require_efie(levels, n_levels);
   check_cov(cov);
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
   REQUIRE(std::isfinite(tol) && tol >= 0.0 && tol < 1.0, "tol must be in [0, 1)");
@@ -1222,6 +1352,7 @@ fosb_status fosb_far_field_moments_noalloc(fosb_context* ctx, const fosb_level* 
   API_BEGIN
   REQUIRE(ctx && levels && blocks && ldb && xhat && var, "NULL argument");
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  require_efie(levels, n_levels);
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
   REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
   check_far_field_args(xhat, n_a, L0, L, levels, blocks, ldb);
@@ -1298,6 +1429,7 @@ fosb_status fosb_near_field_matrix(fosb_context* ctx, const fosb_level* level, c
   API_BEGIN
   REQUIRE(ctx && level && NF, "NULL argument");
   REQUIRE(level->ctx == ctx, "level belongs to another context");
+  require_efie(&level, 1);
   check_field_points(points, n_p);
   bind(*ctx);
   std::vector<double> x(points, points + 3 * n_p);
@@ -1314,6 +1446,7 @@ fosb_status fosb_near_field_moments(fosb_context* ctx, const fosb_level* const* 
   API_BEGIN
   REQUIRE(ctx && levels && blocks && ldb && var, "NULL argument");
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  require_efie(levels, n_levels);
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
   REQUIRE(dir >= 0 && dir < levels[0]->n_dirs, "dir out of range");
   check_field_points(points, n_p);
@@ -1334,6 +1467,7 @@ fosb_status fosb_far_field_moments_backward(fosb_context* ctx, const fosb_level*
   API_BEGIN
   REQUIRE(ctx && levels && xhat && dvar && out, "NULL argument");
   REQUIRE(L0 >= 0 && L >= L0 && n_levels == L - L0 + 1, "n_levels must be L - L0 + 1");
+  require_efie(levels, n_levels);
   REQUIRE(n_a >= 1 && n_a <= 65535, "n_a must be 1..65535");
   check_cov(cov);
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);

@@ -490,6 +490,400 @@ void assemble_efie_c64(Context& ctx, const Mesh& m, double k, int n_gauss, c64* 
                  });
 }
 
+// ------------------------------------------------------------------ PMCHWT (dielectric) blocks
+//
+// The MFIO pairing of two RWG functions,
+//   K[m][n] = int int phi_m(x) . (grad_x G_k(x, y) x phi_n(y)) dx dy,
+//   grad_x G_k = g (x - y),  g = (i k R - 1) exp(i k R) / (4 pi R^3),
+// reduces per triangle pair to ten moments.  With phi_a(x) = (alpha_a / 2)(x - P_a),
+// phi_b(y) = (beta_b / 2)(y - Q_b) and x - y = (x - P_a) - (y - Q_b) + (P_a - Q_b),
+// the triple product (x - P_a) . ((x - y) x (y - Q_b)) equals
+// (P_a - Q_b) . ((y - Q_b) x (x - P_a)); relative to the centroids
+// (x = c + x~, y = c' + y~) it is linear in
+//   K0 = sum g,  Kx = sum g x~,  Ky = sum g y~,  Kyx = sum g (y~ x x~):
+//   blk[a][b] = (alpha_a beta_b / 4) (dc + P~_a - Q~_b) . (Kyx - Ky x P~_a - Q~_b x Kx + (Q~_b x P~_a) K0).
+// On identical (flat) triangles all three vectors lie in the plane and the
+// integrand vanishes, so those blocks are zero.
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ void write_local_block_k(const MeshDev& md, int i, int j, int jj, const double Li[3][3],
+                                                    const double Lj[3][3], const double dc[3], double K0r, double K0i,
+                                                    const double Kxr[3], const double Kxi[3], const double Kyr[3],
+                                                    const double Kyi[3], const double Kyxr[3], const double Kyxi[3],
+                                                    c128* __restrict__ Kc, int64_t ldc) {
+  const int nt = md.nt;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double al = md.alpha[a * nt + i];
+    const double Pa[3] = {Li[a][0], Li[a][1], Li[a][2]};
+    double KyPr[3], KyPi[3];
+    cross3(Kyr, Pa, KyPr);
+    cross3(Kyi, Pa, KyPi);
+    c128* row = Kc + (int64_t)(3 * i + a) * ldc + 3 * jj;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double be = md.alpha[b * nt + j];
+      const double Qb[3] = {Lj[b][0], Lj[b][1], Lj[b][2]};
+      double QKxr[3], QKxi[3], QP[3];
+      cross3(Qb, Kxr, QKxr);
+      cross3(Qb, Kxi, QKxi);
+      cross3(Qb, Pa, QP);
+      double vr = 0, vi = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double cab = dc[c] + Pa[c] - Qb[c];
+        vr += cab * (Kyxr[c] - KyPr[c] - QKxr[c] + QP[c] * K0r);
+        vi += cab * (Kyxi[c] - KyPi[c] - QKxi[c] + QP[c] * K0i);
+      }
+      const double sc = 0.25 * al * be;
+      row[b] = c128{vr * sc, vi * sc};
+    }
+  }
+}
+
+// One thread per ordered non-touching triangle pair (i, j0 + jj): the EFIE
+// block into Tc and the MFIO block into Kc, from the same point pairs.
+__global__ __launch_bounds__(256) void k_pm_regular(MeshDev md, Rule6 R, double k, int j0, int jc,
+                                                    c128* __restrict__ Tc, c128* __restrict__ Kc, int64_t ldc) {
+  const int jj = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (jj >= jc || i >= md.nt) return;
+  const int j = j0 + jj;
+  const int nt = md.nt;
+  {
+    const int a0 = md.fv[i], a1 = md.fv[nt + i], a2 = md.fv[2 * nt + i];
+    const int b0 = md.fv[j], b1 = md.fv[nt + j], b2 = md.fv[2 * nt + j];
+    if (a0 == b0 || a0 == b1 || a0 == b2 || a1 == b0 || a1 == b1 || a1 == b2 || a2 == b0 || a2 == b1 ||
+        a2 == b2)
+      return;  // touching pair: integrated by k_pm_singular
+  }
+  double Pi[3][3], Pj[3][3], ci[3], cj[3];
+  load_tri(md, i, Pi, ci);
+  load_tri(md, j, Pj, cj);
+  double Li[3][3], Lj[3][3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      Li[v][q] = Pi[v][q] - ci[q];
+      Lj[v][q] = Pj[v][q] - cj[q];
+    }
+  const double Ai = md.area[i], Aj = md.area[j];
+  double yq[6][3], wq[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) yq[q][c] = R.l[q][0] * Lj[0][c] + R.l[q][1] * Lj[1][c] + R.l[q][2] * Lj[2][c];
+    wq[q] = R.w[q] * Aj * kInv4Pi;
+  }
+  const double dc[3] = {ci[0] - cj[0], ci[1] - cj[1], ci[2] - cj[2]};
+  double I0r = 0, I0i = 0, Ixyr = 0, Ixyi = 0;
+  double Ixr[3] = {0, 0, 0}, Ixi[3] = {0, 0, 0}, Iyr[3] = {0, 0, 0}, Iyi[3] = {0, 0, 0};
+  double K0r = 0, K0i = 0;
+  double Kxr[3] = {0, 0, 0}, Kxi[3] = {0, 0, 0}, Kyr[3] = {0, 0, 0}, Kyi[3] = {0, 0, 0};
+  double Kyxr[3] = {0, 0, 0}, Kyxi[3] = {0, 0, 0};
+  for (int p = 0; p < 6; ++p) {
+    double xp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xp[c] = R.l[p][0] * Li[0][c] + R.l[p][1] * Li[1][c] + R.l[p][2] * Li[2][c];
+    const double wp = R.w[p] * Ai;
+    const double e0 = xp[0] + dc[0], e1 = xp[1] + dc[1], e2 = xp[2] + dc[2];
+    double Sr = 0, Si = 0, Syr[3] = {0, 0, 0}, Syi[3] = {0, 0, 0};
+    double Tr = 0, Ti = 0, Tyr[3] = {0, 0, 0}, Tyi[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double d0 = e0 - yq[q][0], d1 = e1 - yq[q][1], d2 = e2 - yq[q][2];
+      const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const double ir = rsqrt(r2);
+      const double r = r2 * ir;
+      double sn, cs;
+      sincos_phase(k * r, &sn, &cs);
+      const double g = wq[q] * ir;
+      const double gr = cs * g, gi = sn * g;
+      // (i k R - 1) / R^2 times G
+      const double ir2 = ir * ir, kr = k * r;
+      const double hr = (-gr - gi * kr) * ir2, hi = (gr * kr - gi) * ir2;
+      Sr += gr;
+      Si += gi;
+      Tr += hr;
+      Ti += hi;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Syr[c] += gr * yq[q][c];
+        Syi[c] += gi * yq[q][c];
+        Tyr[c] += hr * yq[q][c];
+        Tyi[c] += hi * yq[q][c];
+      }
+    }
+    I0r += wp * Sr;
+    I0i += wp * Si;
+    K0r += wp * Tr;
+    K0i += wp * Ti;
+    double cyr[3], cyi[3];
+    cross3(Tyr, xp, cyr);
+    cross3(Tyi, xp, cyi);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Ixr[c] += wp * Sr * xp[c];
+      Ixi[c] += wp * Si * xp[c];
+      Iyr[c] += wp * Syr[c];
+      Iyi[c] += wp * Syi[c];
+      Kxr[c] += wp * Tr * xp[c];
+      Kxi[c] += wp * Ti * xp[c];
+      Kyr[c] += wp * Tyr[c];
+      Kyi[c] += wp * Tyi[c];
+      Kyxr[c] += wp * cyr[c];
+      Kyxi[c] += wp * cyi[c];
+    }
+    Ixyr += wp * (xp[0] * Syr[0] + xp[1] * Syr[1] + xp[2] * Syr[2]);
+    Ixyi += wp * (xp[0] * Syi[0] + xp[1] * Syi[1] + xp[2] * Syi[2]);
+  }
+  write_local_block(md, i, j, jj, k, Li, Lj, I0r, I0i, Ixr, Ixi, Iyr, Iyi, Ixyr, Ixyi, Tc, ldc);
+  write_local_block_k(md, i, j, jj, Li, Lj, dc, K0r, K0i, Kxr, Kxi, Kyr, Kyi, Kyxr, Kyxi, Kc, ldc);
+}
+
+// One wavefront per touching ordered pair (Sauter-Schwab points over the lanes):
+// EFIE block into Tc, MFIO block into Kc (zero for identical triangles).
+__global__ __launch_bounds__(256) void k_pm_singular(MeshDev md, const int32_t* __restrict__ tp_i,
+                                                     const int32_t* __restrict__ tp_j,
+                                                     const int32_t* __restrict__ tp_kind,
+                                                     const int32_t* __restrict__ tp_ord, int pbeg, int pend,
+                                                     const double* __restrict__ ss, int off0, int off1, int off2,
+                                                     int cnt0, int cnt1, int cnt2, double k, int j0,
+                                                     c128* __restrict__ Tc, c128* __restrict__ Kc, int64_t ldc) {
+  const int p = pbeg + blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= pend) return;
+  const int i = tp_i[p], j = tp_j[p], kind = tp_kind[p];
+  const int* ord = tp_ord + 6 * p;
+  double Pi[3][3], Pj[3][3], ci[3], cj[3];
+  load_tri(md, i, Pi, ci);
+  load_tri(md, j, Pj, cj);
+  double Li[3][3], Lj[3][3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      Li[v][q] = Pi[v][q] - ci[q];
+      Lj[v][q] = Pj[v][q] - cj[q];
+    }
+  double S0[3], S1[3], S2[3], T0[3], T1[3], T2[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    S0[q] = Li[ord[0]][q]; S1[q] = Li[ord[1]][q] - Li[ord[0]][q]; S2[q] = Li[ord[2]][q] - Li[ord[1]][q];
+    T0[q] = Lj[ord[3]][q]; T1[q] = Lj[ord[4]][q] - Lj[ord[3]][q]; T2[q] = Lj[ord[5]][q] - Lj[ord[4]][q];
+  }
+  const double jac = 4.0 * md.area[i] * md.area[j] * kInv4Pi;
+  const double dc[3] = {ci[0] - cj[0], ci[1] - cj[1], ci[2] - cj[2]};
+  const int off = kind == 0 ? off0 : (kind == 1 ? off1 : off2);
+  const int cnt = kind == 0 ? cnt0 : (kind == 1 ? cnt1 : cnt2);
+  const bool with_k = kind != 0;
+  double I0r = 0, I0i = 0, Ixyr = 0, Ixyi = 0;
+  double Ixr[3] = {0, 0, 0}, Ixi[3] = {0, 0, 0}, Iyr[3] = {0, 0, 0}, Iyi[3] = {0, 0, 0};
+  double K0r = 0, K0i = 0;
+  double Kxr[3] = {0, 0, 0}, Kxi[3] = {0, 0, 0}, Kyr[3] = {0, 0, 0}, Kyi[3] = {0, 0, 0};
+  double Kyxr[3] = {0, 0, 0}, Kyxi[3] = {0, 0, 0};
+  for (int m = lane; m < cnt; m += 64) {
+    const double* pt = ss + 5 * (int64_t)(off + m);
+    const double x1 = pt[0], x2 = pt[1], y1 = pt[2], y2 = pt[3], w = pt[4];
+    double x[3], y[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      x[q] = S0[q] + x1 * S1[q] + x2 * S2[q];
+      y[q] = T0[q] + y1 * T1[q] + y2 * T2[q];
+    }
+    const double d0 = x[0] - y[0] + dc[0], d1 = x[1] - y[1] + dc[1], d2 = x[2] - y[2] + dc[2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    double sn, cs;
+    sincos(k * r, &sn, &cs);
+    const double g = w * jac * ir;
+    const double gr = cs * g, gi = sn * g;
+    I0r += gr;
+    I0i += gi;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      Ixr[q] += gr * x[q];
+      Ixi[q] += gi * x[q];
+      Iyr[q] += gr * y[q];
+      Iyi[q] += gi * y[q];
+    }
+    const double xy = x[0] * y[0] + x[1] * y[1] + x[2] * y[2];
+    Ixyr += gr * xy;
+    Ixyi += gi * xy;
+    if (with_k) {
+      const double ir2 = ir * ir, kr = k * r;
+      const double hr = (-gr - gi * kr) * ir2, hi = (gr * kr - gi) * ir2;
+      double yx[3];
+      cross3(y, x, yx);
+      K0r += hr;
+      K0i += hi;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        Kxr[q] += hr * x[q];
+        Kxi[q] += hi * x[q];
+        Kyr[q] += hr * y[q];
+        Kyi[q] += hi * y[q];
+        Kyxr[q] += hr * yx[q];
+        Kyxi[q] += hi * yx[q];
+      }
+    }
+  }
+  I0r = wave_sum(I0r);
+  I0i = wave_sum(I0i);
+  Ixyr = wave_sum(Ixyr);
+  Ixyi = wave_sum(Ixyi);
+  K0r = wave_sum(K0r);
+  K0i = wave_sum(K0i);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    Ixr[q] = wave_sum(Ixr[q]);
+    Ixi[q] = wave_sum(Ixi[q]);
+    Iyr[q] = wave_sum(Iyr[q]);
+    Iyi[q] = wave_sum(Iyi[q]);
+    Kxr[q] = wave_sum(Kxr[q]);
+    Kxi[q] = wave_sum(Kxi[q]);
+    Kyr[q] = wave_sum(Kyr[q]);
+    Kyi[q] = wave_sum(Kyi[q]);
+    Kyxr[q] = wave_sum(Kyxr[q]);
+    Kyxi[q] = wave_sum(Kyxi[q]);
+  }
+  if (lane == 0) {
+    write_local_block(md, i, j, j - j0, k, Li, Lj, I0r, I0i, Ixr, Ixi, Iyr, Iyi, Ixyr, Ixyi, Tc, ldc);
+    write_local_block_k(md, i, j, j - j0, Li, Lj, dc, K0r, K0i, Kxr, Kxi, Kyr, Kyi, Kyxr, Kyxi, Kc, ldc);
+  }
+}
+
+// The 2N x 2N PMCHWT matrix from one band of EFIE (Tc) and MFIO (Kc) local
+// blocks at one wavenumber:  Z[m][n] (+)= cT1 T,  Z[m][N+n] (+)= K,
+// Z[N+m][n] (+)= -K,  Z[N+m][N+n] (+)= cT2 T, with T and K the sums of the
+// (up to) four local blocks of the band.  Stored where `first` is set and the
+// band holds T+ of n, added otherwise, so every entry is a fixed-order sum.
+__global__ __launch_bounds__(256) void k_pm_gather(int ne, const int32_t* __restrict__ edge_tri,
+                                                   const int32_t* __restrict__ edge_loc, int j0, int j1,
+                                                   const int32_t* __restrict__ cols, int ncols,
+                                                   const c128* __restrict__ Tc, const c128* __restrict__ Kc,
+                                                   int64_t ldc, double cT1, double cT2, int first,
+                                                   c128* __restrict__ Z, int64_t ldz) {
+  const int ci = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (ci >= ncols || m >= ne) return;
+  const int n = cols[ci];
+  const int tp = edge_tri[n], tm = edge_tri[ne + n];
+  const int64_t rp = 3 * (int64_t)edge_tri[m] + edge_loc[m];
+  const int64_t rm = 3 * (int64_t)edge_tri[ne + m] + edge_loc[ne + m];
+  double tr = 0.0, ti = 0.0, kr = 0.0, ki = 0.0;
+  const bool has_p = tp >= j0 && tp < j1;
+  if (has_p) {
+    const int64_t c = 3 * (int64_t)(tp - j0) + edge_loc[n];
+    const c128 u = Tc[rp * ldc + c], v = Tc[rm * ldc + c];
+    const c128 x = Kc[rp * ldc + c], y = Kc[rm * ldc + c];
+    tr += u.re + v.re;
+    ti += u.im + v.im;
+    kr += x.re + y.re;
+    ki += x.im + y.im;
+  }
+  if (tm >= j0 && tm < j1) {
+    const int64_t c = 3 * (int64_t)(tm - j0) + edge_loc[ne + n];
+    const c128 u = Tc[rp * ldc + c], v = Tc[rm * ldc + c];
+    const c128 x = Kc[rp * ldc + c], y = Kc[rm * ldc + c];
+    tr += u.re + v.re;
+    ti += u.im + v.im;
+    kr += x.re + y.re;
+    ki += x.im + y.im;
+  }
+  c128* z00 = Z + (int64_t)m * ldz + n;
+  c128* z01 = z00 + ne;
+  c128* z10 = Z + (int64_t)(ne + m) * ldz + n;
+  c128* z11 = z10 + ne;
+  const c128 v00{cT1 * tr, cT1 * ti}, v01{kr, ki}, v10{-kr, -ki}, v11{cT2 * tr, cT2 * ti};
+  if (first && has_p) {
+    *z00 = v00;
+    *z01 = v01;
+    *z10 = v10;
+    *z11 = v11;
+  } else {
+    c128 o = *z00;
+    *z00 = c128{o.re + v00.re, o.im + v00.im};
+    o = *z01;
+    *z01 = c128{o.re + v01.re, o.im + v01.im};
+    o = *z10;
+    *z10 = c128{o.re + v10.re, o.im + v10.im};
+    o = *z11;
+    *z11 = c128{o.re + v11.re, o.im + v11.im};
+  }
+}
+
+void assemble_pmchwt(Context& ctx, const Mesh& m, double k0, double eps_r, double mu_r, int n_gauss, c128* Z,
+                     int64_t ldz) {
+  hipStream_t s = ctx.stream;
+  const MeshHost& h = m.h;
+  const int nt = (int)h.nt, ne = (int)h.ne;
+  const double k1 = k0 * std::sqrt(eps_r * mu_r), eta = std::sqrt(mu_r / eps_r);
+  ensure_ss_table(ctx, n_gauss);
+  Rule6 R;
+  rule6(R.l, R.w);
+  // two band buffers (EFIE and MFIO blocks) of up to 512 MiB each
+  const int64_t budget = (int64_t)512 << 20;
+  int jc = (int)std::max<int64_t>(1, std::min<int64_t>(nt, budget / (9LL * nt * (int64_t)sizeof(c128))));
+  if (jc < nt) jc = std::max(64, jc / 64 * 64);
+  jc = std::min(jc, nt);
+  const int64_t ldc = 3LL * jc;
+  DevBuf tband((size_t)(3LL * nt) * ldc * sizeof(c128)), kband((size_t)(3LL * nt) * ldc * sizeof(c128));
+  std::vector<int32_t> cols;
+  std::vector<int64_t> cbeg;
+  for (int j0 = 0; j0 < nt; j0 += jc) {
+    const int j1 = std::min(nt, j0 + jc);
+    cbeg.push_back((int64_t)cols.size());
+    for (int e = 0; e < ne; ++e) {
+      const int tp = h.edge_tri[2 * e], tm = h.edge_tri[2 * e + 1];
+      if ((tp >= j0 && tp < j1) || (tm >= j0 && tm < j1)) cols.push_back(e);
+    }
+  }
+  cbeg.push_back((int64_t)cols.size());
+  DevBuf dcols;
+  upload(dcols, cols, s);
+  const MeshDev md = m.dev();
+  const double kk[2] = {k0, k1}, c1[2] = {1.0, eta}, c2[2] = {1.0, 1.0 / eta};
+  for (int pass = 0; pass < 2; ++pass) {
+    int bi = 0;
+    for (int j0 = 0; j0 < nt; j0 += jc, ++bi) {
+      const int j1 = std::min(nt, j0 + jc);
+      const int w = j1 - j0;
+      dim3 g1((w + 63) / 64, (nt + 3) / 4);
+      hipLaunchKernelGGL(k_pm_regular, g1, dim3(256), 0, s, md, R, kk[pass], j0, w, tband.as<c128>(),
+                         kband.as<c128>(), ldc);
+      FOSB_LAUNCH_CHECK();
+      const int pb = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j0) - h.tp_j.begin());
+      const int pe = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j1) - h.tp_j.begin());
+      if (pe > pb) {
+        dim3 g2((pe - pb + 3) / 4);
+        hipLaunchKernelGGL(k_pm_singular, g2, dim3(256), 0, s, md, m.tp_i.as<int32_t>(), m.tp_j.as<int32_t>(),
+                           m.tp_kind.as<int32_t>(), m.tp_ord.as<int32_t>(), pb, pe, ctx.ss[n_gauss].as<double>(),
+                           ctx.ss_off[n_gauss][0], ctx.ss_off[n_gauss][1], ctx.ss_off[n_gauss][2],
+                           ctx.ss_cnt[n_gauss][0], ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], kk[pass], j0,
+                           tband.as<c128>(), kband.as<c128>(), ldc);
+        FOSB_LAUNCH_CHECK();
+      }
+      const int nc = (int)(cbeg[bi + 1] - cbeg[bi]);
+      if (nc > 0) {
+        dim3 g3((nc + 63) / 64, (ne + 3) / 4);
+        hipLaunchKernelGGL(k_pm_gather, g3, dim3(256), 0, s, ne, md.edge_tri, md.edge_loc, j0, j1,
+                           dcols.as<int32_t>() + cbeg[bi], nc, tband.as<c128>(), kband.as<c128>(), ldc, c1[pass],
+                           c2[pass], pass == 0 ? 1 : 0, Z, ldz);
+        FOSB_LAUNCH_CHECK();
+      }
+    }
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
+}
+
 void efie_residual(Context& ctx, const Mesh& m, double k, int n_gauss, const c128* X, int64_t ldx, int64_t nrhs,
                    c128* R, int64_t ldr) {
   if (nrhs <= 0) return;

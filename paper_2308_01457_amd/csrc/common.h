@@ -298,6 +298,11 @@ struct Level {
   DevBuf qx;                   // double [3][6*nt] quadrature nodes (component-major)
   // certificate (opts.certify): norms of the assembled Z, condition estimate, growth factor
   double z_max = 0, z_fro = 0, z_one = 0, kappa1 = 0, growth = 0;
+  // formulation: FOSB_FORM_EFIE (N = edges) or FOSB_FORM_PMCHWT (N = 2 edges,
+  // unknowns [J; M], interior eps_r, mu_r; b keeps the right-hand sides)
+  int form = FOSB_FORM_EFIE;
+  double eps_r = 1.0, mu_r = 1.0;
+  DevBuf b;                    // PMCHWT: c128 [n][n_dirs]
   const void* lu() const { return precision == FOSB_PREC_FP64 ? Z : Zlow; }
 };
 
@@ -311,6 +316,10 @@ void assemble_efie_c64(Context& ctx, const Mesh& m, double k, int n_gauss, c64* 
 // R (N x nrhs) -= Z X in FP64 with Z re-assembled band by band and discarded
 void efie_residual(Context& ctx, const Mesh& m, double k, int n_gauss, const c128* X, int64_t ldx, int64_t nrhs,
                    c128* R, int64_t ldr);
+// the 2N x 2N PMCHWT matrix [[T0 + eta T1, K0 + K1], [-(K0 + K1), T0 + T1/eta]] (EFIE blocks T, MFIO
+// blocks K at k0 and k1 = k0 sqrt(eps_r mu_r), eta = sqrt(mu_r / eps_r)); synchronises the stream
+void assemble_pmchwt(Context& ctx, const Mesh& m, double k0, double eps_r, double mu_r, int n_gauss, c128* Z,
+                     int64_t ldz);
 // gemm.hip: C = beta*C + alpha*A*B, complex, row-major.
 template <typename T>
 void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
@@ -389,6 +398,15 @@ void rhs_correlation_kernel(hipStream_t s, const Level& l1, const Level& l2, con
 // C_d = Wgt_l1(dir0 + d) K Wgt_l2(dir0 + d)^H for d < nd at C + d * dstride (row stride ldc)
 void rhs_correlation_multi(hipStream_t s, const Level& l1, const Level& l2, const fosb_cov& cov, int64_t dir0,
                            int64_t nd, c128* C, int64_t ldc, int64_t dstride);
+// PMCHWT right-hand side b = [e; h] (2N x ndir, row stride ndir): e[m] = int phi_m . p e^{ik d.x},
+// h[m] = int phi_m . (d x p) e^{ik d.x}
+void incident_rhs_pmchwt(hipStream_t s, const Mesh& m, double k, const double* dirs_dev, const double* pols_dev,
+                         int ndir, c128* b);
+// PMCHWT far-field map (3 n_a x 2N): i k [(I - x x^T) A_m | -x x A_m], A_m = int phi_m e^{-ik x.y}
+void far_field_matrix_pmchwt(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a, c128* FF);
+// C[i][j] = b1[i] conj(b2[j]) (b1: n1 x nd, b2: n2 x nd, column dir)
+void rank_one_correlation(hipStream_t s, const c128* b1, int64_t n1, const c128* b2, int64_t n2, int64_t nd,
+                          int64_t dir, c128* C, int64_t ldc);
 void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a,
                              c128* FF);
 // NF[(c*n_p + p)][m]: scattered field at the field points x_p (device, n_p x 3) of each RWG

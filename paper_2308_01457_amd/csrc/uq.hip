@@ -68,6 +68,70 @@ void incident_rhs(hipStream_t s, const Mesh& m, double k, const double* dirs_dev
   FOSB_LAUNCH_CHECK();
 }
 
+// PMCHWT incident data: e[m] = int phi_m . p e^{ik d.x} (rows 0..N-1) and
+// h[m] = int phi_m . (d x p) e^{ik d.x} (rows N..2N-1), 6-point rule.
+__global__ void k_incident_rhs_pmchwt(MeshDev md, Rule6Q R, double k, const double* __restrict__ dirs,
+                                      const double* __restrict__ pols, int ndir, c128* __restrict__ b) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int dr = blockIdx.y;
+  if (m >= md.ne || dr >= ndir) return;
+  const double d[3] = {dirs[3 * dr], dirs[3 * dr + 1], dirs[3 * dr + 2]};
+  const double p[3] = {pols[3 * dr], pols[3 * dr + 1], pols[3 * dr + 2]};
+  const double hp[3] = {d[1] * p[2] - d[2] * p[1], d[2] * p[0] - d[0] * p[2], d[0] * p[1] - d[1] * p[0]};
+  double er = 0, ei = 0, hr = 0, hi = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int t = md.edge_tri[side * md.ne + m];
+    const int a = md.edge_loc[side * md.ne + m];
+    double P[3][3];
+    tri_vertices(md, t, P);
+    const double half_alpha = 0.5 * md.alpha[a * md.nt + t];
+    const double At = md.area[t];
+    for (int q = 0; q < 6; ++q) {
+      double x[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) x[c] = R.l[q][0] * P[0][c] + R.l[q][1] * P[1][c] + R.l[q][2] * P[2][c];
+      double sn, cs;
+      sincos(k * (d[0] * x[0] + d[1] * x[1] + d[2] * x[2]), &sn, &cs);
+      const double v0 = x[0] - P[a][0], v1 = x[1] - P[a][1], v2 = x[2] - P[a][2];
+      const double f = R.w[q] * At * half_alpha;
+      const double pe = f * (p[0] * v0 + p[1] * v1 + p[2] * v2);
+      const double ph = f * (hp[0] * v0 + hp[1] * v1 + hp[2] * v2);
+      er += pe * cs;
+      ei += pe * sn;
+      hr += ph * cs;
+      hi += ph * sn;
+    }
+  }
+  b[(int64_t)m * ndir + dr] = c128{er, ei};
+  b[(int64_t)(md.ne + m) * ndir + dr] = c128{hr, hi};
+}
+
+void incident_rhs_pmchwt(hipStream_t s, const Mesh& m, double k, const double* dirs_dev, const double* pols_dev,
+                         int ndir, c128* b) {
+  dim3 g((unsigned)((m.h.ne + 255) / 256), (unsigned)ndir);
+  hipLaunchKernelGGL(k_incident_rhs_pmchwt, g, dim3(256), 0, s, m.dev(), make_rule(), k, dirs_dev, pols_dev, ndir,
+                     b);
+  FOSB_LAUNCH_CHECK();
+}
+
+// C[i][j] = b1[i][dir] conj(b2[j][dir])
+__global__ void k_rank_one(const c128* __restrict__ b1, int64_t n1, const c128* __restrict__ b2, int64_t n2,
+                           int64_t nd, int64_t dir, c128* __restrict__ C, int64_t ldc) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j >= n2 || i >= n1) return;
+  const c128 u = b1[i * nd + dir], v = b2[j * nd + dir];
+  C[i * ldc + j] = c128{u.re * v.re + u.im * v.im, u.im * v.re - u.re * v.im};
+}
+
+void rank_one_correlation(hipStream_t s, const c128* b1, int64_t n1, const c128* b2, int64_t n2, int64_t nd,
+                          int64_t dir, c128* C, int64_t ldc) {
+  if (n1 <= 0 || n2 <= 0) return;
+  dim3 g((unsigned)((n2 + 255) / 256), (unsigned)n1);
+  hipLaunchKernelGGL(k_rank_one, g, dim3(256), 0, s, b1, n1, b2, n2, nd, dir, C, ldc);
+  FOSB_LAUNCH_CHECK();
+}
+
 // qx[c][6t + q]: physical 6-point nodes
 __global__ void k_quad_nodes(MeshDev md, Rule6Q R, double* __restrict__ qx) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -414,6 +478,55 @@ __global__ void k_far_field_matrix(MeshDev md, Rule6Q R, double k, const double*
     // -i k (pr + i pi) = k pi - i k pr
     FF[((int64_t)c * n_a + i) * md.ne + m] = c128{k * pi, -k * pr};
   }
+}
+
+// PMCHWT far field: FF[(c n_a + i)][m] = i k ((I - x x^T) A_m)_c and
+// FF[(c n_a + i)][N + m] = -i k (x x A_m)_c, A_m = int phi_m(y) e^{-ik x.y} dy.
+__global__ void k_far_field_pmchwt(MeshDev md, Rule6Q R, double k, const double* __restrict__ xh, int n_a,
+                                   c128* __restrict__ FF) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (m >= md.ne || i >= n_a) return;
+  const double xv[3] = {xh[3 * i], xh[3 * i + 1], xh[3 * i + 2]};
+  double Ar[3] = {0, 0, 0}, Ai[3] = {0, 0, 0};
+  for (int side = 0; side < 2; ++side) {
+    const int t = md.edge_tri[side * md.ne + m];
+    const int a = md.edge_loc[side * md.ne + m];
+    double P[3][3];
+    tri_vertices(md, t, P);
+    const double ha = 0.5 * md.alpha[a * md.nt + t] * md.area[t];
+    for (int q = 0; q < 6; ++q) {
+      double y[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = R.l[q][0] * P[0][c] + R.l[q][1] * P[1][c] + R.l[q][2] * P[2][c];
+      double sn, cs;
+      sincos(-k * (xv[0] * y[0] + xv[1] * y[1] + xv[2] * y[2]), &sn, &cs);
+      const double f = R.w[q] * ha;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double ph = f * (y[c] - P[a][c]);
+        Ar[c] += ph * cs;
+        Ai[c] += ph * sn;
+      }
+    }
+  }
+  const double dr = xv[0] * Ar[0] + xv[1] * Ar[1] + xv[2] * Ar[2];
+  const double di = xv[0] * Ai[0] + xv[1] * Ai[1] + xv[2] * Ai[2];
+  const double xr[3] = {xv[1] * Ar[2] - xv[2] * Ar[1], xv[2] * Ar[0] - xv[0] * Ar[2], xv[0] * Ar[1] - xv[1] * Ar[0]};
+  const double xi[3] = {xv[1] * Ai[2] - xv[2] * Ai[1], xv[2] * Ai[0] - xv[0] * Ai[2], xv[0] * Ai[1] - xv[1] * Ai[0]};
+  const int64_t ld = 2LL * md.ne;
+  for (int c = 0; c < 3; ++c) {
+    const double pr = Ar[c] - xv[c] * dr, pi = Ai[c] - xv[c] * di;
+    // i k (pr + i pi) = -k pi + i k pr;  -i k (xr + i xi) = k xi - i k xr
+    FF[((int64_t)c * n_a + i) * ld + m] = c128{-k * pi, k * pr};
+    FF[((int64_t)c * n_a + i) * ld + md.ne + m] = c128{k * xi[c], -k * xr[c]};
+  }
+}
+
+void far_field_matrix_pmchwt(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a, c128* FF) {
+  dim3 g((unsigned)((m.h.ne + 255) / 256), (unsigned)n_a);
+  hipLaunchKernelGGL(k_far_field_pmchwt, g, dim3(256), 0, s, m.dev(), make_rule(), k, xhat_dev, (int)n_a, FF);
+  FOSB_LAUNCH_CHECK();
 }
 
 void far_field_matrix_kernel(hipStream_t s, const Mesh& m, double k, const double* xhat_dev, int64_t n_a, c128* FF) {

@@ -25,6 +25,7 @@ STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SINGULAR", 3: "E_NOCONV", 4: "E_WORKSPA
           6: "E_DEVICE", 7: "E_UNSUPPORTED"}
 COV_KINDS = {"gaussian": GAUSSIAN, "matern32": MATERN32, "constant": CONSTANT, "normal_dot": NORMAL_DOT}
 FIELDS = {"radial": RADIAL, "normal": NORMAL}
+FORM_EFIE, FORM_PMCHWT = 0, 1
 
 
 class FosbError(RuntimeError):
@@ -73,6 +74,10 @@ _SIGS = {
     "fosb_assemble": (C.c_int, [_P, _P, _D, C.POINTER(Opts), _P, _I64]),
     "fosb_level_create": (C.c_int, [_P, _P, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64, _I32, C.POINTER(Opts),
                                     C.POINTER(_P)]),
+    "fosb_assemble_pmchwt": (C.c_int, [_P, _P, _D, _D, _D, C.POINTER(Opts), _P, _I64]),
+    "fosb_level_create_pmchwt": (C.c_int, [_P, _P, _D, _D, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64,
+                                           C.POINTER(Opts), C.POINTER(_P)]),
+    "fosb_level_formulation": (C.c_int, [_P, C.POINTER(_I32), C.POINTER(_D), C.POINTER(_D)]),
     "fosb_level_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
     "fosb_level_workspace_size": (C.c_int, [_P, _I32, _I64, _I64, C.POINTER(_I64), C.POINTER(_I64)]),
     "fosb_level_certificate": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_D)]),
@@ -310,6 +315,18 @@ def assemble(ctx: Context, mesh: Mesh, k: float, opts: Opts | None = None, Z=Non
     return Z
 
 
+def assemble_pmchwt(ctx: Context, mesh: Mesh, k0: float, eps_r: float, mu_r: float = 1.0,
+                    opts: Opts | None = None, Z=None):
+    """fosb_assemble_pmchwt: returns the 2N x 2N complex128 PMCHWT matrix (torch, on device)."""
+    import torch
+    n = 2 * mesh.n_edges
+    if Z is None:
+        Z = torch.empty((n, n), dtype=torch.complex128, device=ctx.torch_device)
+    _check(lib().fosb_assemble_pmchwt(ctx.h, mesh.h, float(k0), float(eps_r), float(mu_r),
+                                      C.byref(opts) if opts else None, _dev(Z, torch.complex128), Z.stride(0)))
+    return Z
+
+
 class Level:
     """fosb_level_create.  FP64: Z is factorised in place.  MIXED: Z is kept and
     a complex64 copy (allocated here unless given) receives the FP32 LU."""
@@ -337,6 +354,37 @@ class Level:
         self.h = h
         self.n = n
         self.n_dirs = d.shape[0]
+
+    @classmethod
+    def pmchwt(cls, ctx: "Context", mesh: "Mesh", k0: float, eps_r: float, mu_r: float, Z, precision: int = FP64,
+               dirs=((0.0, 0.0, 1.0),), pols=((1.0, 0.0, 0.0),), opts: Opts | None = None, Zlow=None):
+        """fosb_level_create_pmchwt: a dielectric level on the 2N x 2N matrix Z
+        of assemble_pmchwt (factorised in place for FP64, kept for MIXED)."""
+        import torch
+        self = cls.__new__(cls)
+        self.ctx, self.mesh, self.k, self.Z = ctx, mesh, float(k0), Z
+        self.precision = precision
+        n = 2 * mesh.n_edges
+        if precision == MIXED and Zlow is None:
+            Zlow = torch.empty((n, n), dtype=torch.complex64, device=ctx.torch_device)
+        self.Zlow = Zlow
+        d = _host_f64(dirs).reshape(-1, 3)
+        p = _host_f64(pols).reshape(-1, 3)
+        h = _P()
+        _check(lib().fosb_level_create_pmchwt(ctx.h, mesh.h, self.k, float(eps_r), float(mu_r), precision,
+                                              _dev(Z, torch.complex128), Z.stride(0),
+                                              _dev(Zlow, torch.complex64) if Zlow is not None else None,
+                                              Zlow.stride(0) if Zlow is not None else 0, d.ctypes.data_as(_P),
+                                              p.ctypes.data_as(_P), d.shape[0], C.byref(opts) if opts else None,
+                                              C.byref(h)))
+        self.h, self.n, self.n_dirs = h, n, d.shape[0]
+        return self
+
+    def formulation(self) -> tuple[int, float, float]:
+        """fosb_level_formulation: (FORM_EFIE or FORM_PMCHWT, eps_r, mu_r)."""
+        f, e, m = _I32(), _D(), _D()
+        _check(lib().fosb_level_formulation(self.h, C.byref(f), C.byref(e), C.byref(m)))
+        return f.value, e.value, m.value
 
     def solve(self, B, stats: Stats | None = None):
         import torch
@@ -401,8 +449,8 @@ def rhs_correlation(ctx: Context, l1: Level, l2: Level, cov: Cov, dir: int = 0, 
     import torch
     if C_out is None:
         C_out = torch.empty((l1.n, l2.n), dtype=torch.complex128, device=ctx.torch_device)
-    _check(lib().fosb_rhs_correlation(ctx.h, l1.h, l2.h, C.byref(cov), dir, _dev(C_out, torch.complex128),
-                                      C_out.stride(0)))
+    _check(lib().fosb_rhs_correlation(ctx.h, l1.h, l2.h, C.byref(cov) if cov is not None else None, dir,
+                                      _dev(C_out, torch.complex128), C_out.stride(0)))
     return C_out
 
 
@@ -425,7 +473,8 @@ def correlation(ctx: Context, levels: list[Level], L0: int, L: int, cov: Cov, di
     lv = (_P * len(levels))(*[l.h for l in levels])
     bp = (_P * len(blocks))(*[_dev(b, torch.complex128) for b in blocks])
     ld = (_I64 * len(blocks))(*[b.stride(0) for b in blocks])
-    _check(lib().fosb_correlation(ctx.h, lv, len(levels), L0, L, C.byref(cov), dir, bp, ld, C.byref(st)))
+    _check(lib().fosb_correlation(ctx.h, lv, len(levels), L0, L, C.byref(cov) if cov is not None else None, dir,
+                                  bp, ld, C.byref(st)))
     return blocks
 
 
