@@ -74,11 +74,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--progress", action="store_true", help="print a line after every stage of every step")
-    ap.add_argument("--workload", default="mixed_k5", choices=["mixed_k5", "superquad_k8", "ellipsoids"],
+    ap.add_argument("--workload", default="mixed_k5", choices=["mixed_k5", "superquad_k8", "ellipsoids", "dielectric"],
                     help="mixed_k5: the k=5 icosphere ladder (default); superquad_k8: the superquadric ladder "
                          "|x|^4+|y|^4+|z|^4=1, k=8, to --max-level (s=6 does not fit both precisions' matrices "
                          "on one GPU); ellipsoids: 64 seeded ellipsoids x 16 "
-                         "incidences, 3 levels each, Matern-3/2 covariance, all incidences solved together")
+                         "incidences, 3 levels each, Matern-3/2 covariance, all incidences solved together; "
+                         "dielectric: the sphere experiment's rank-one DE second moment (PMCHWT, eps_r 2.1, k0 3) "
+                         "on the icosphere ladder s=2..--max-level")
     ap.add_argument("--shapes", type=int, default=64, help="ellipsoids: number of shapes")
     ap.add_argument("--workers", type=int, default=4,
                     help="ellipsoids: shapes in flight at once (fosb_second_moment_batch); 0 = one call per shape")
@@ -548,6 +550,111 @@ def calibrate_copy():
                       "launches": 5}), flush=True)
 
 
+def run_dielectric(args):
+    """The sphere experiment's DE second moment: unit icosphere s = 2..L
+    (2N up to 2 x 30 x 4^L), eps_r 2.1, mu_r 1, k0 3, incidence d = e_x,
+    p = e_z, rank-one right-hand side M2[f] = f (x) f over the CT index set
+    (L0 = 2), far-field second moment at 1801 angles in the plane z = 0.  A step
+    assembles every PMCHWT matrix, factors each level and solves its first
+    moment, forms and solves every CT pair and contracts the far field."""
+    import torch
+
+    import workloads
+    from paper_2308_01457_amd import fosb
+    K0, EPS, MU, L0 = 3.0, 2.1, 1.0, 2
+    L = args.max_level
+    D, P = (1.0, 0.0, 0.0), (0.0, 0.0, 1.0)
+    xh = workloads.angles_xy(1801)
+    ctx = fosb.Context(0)
+    meshes = [fosb.Mesh(ctx, *workloads.icosphere(s)) for s in range(L0, L + 1)]
+    pairs = fosb.ct_pairs(L0, L)
+    npairs = len(pairs)
+    precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    Z = [torch.empty((2 * m.n_edges, 2 * m.n_edges), dtype=torch.complex128, device=ctx.torch_device)
+         for m in meshes]
+    Zlow = [torch.empty((2 * m.n_edges, 2 * m.n_edges), dtype=torch.complex64, device=ctx.torch_device)
+            for m in meshes] if "mixed" in precs else [None] * len(meshes)
+    blocks = [torch.empty((2 * meshes[a - L0].n_edges, 2 * meshes[b - L0].n_edges), dtype=torch.complex128,
+                          device=ctx.torch_device) for a, b, _, _ in pairs]
+    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
+
+    def step(prec):
+        levels = []
+        for m, z, zl in zip(meshes, Z, Zlow):
+            fosb.assemble_pmchwt(ctx, m, K0, EPS, MU, opts, Z=z)
+            levels.append(fosb.Level.pmchwt(ctx, m, K0, EPS, MU, z, prec, dirs=[D], pols=[P], opts=opts,
+                                            Zlow=zl if prec == fosb.MIXED else None))
+        st = fosb.Stats()
+        fosb.correlation(ctx, levels, L0, L, None, 0, blocks=blocks, stats=st)
+        var = fosb.far_field_moments(ctx, levels, L0, L, blocks, xh)
+        for lv in levels:
+            lv.close()
+        return var, st
+
+    out = {}
+    for pname in precs:
+        prec = fosb.MIXED if pname == "mixed" else fosb.FP64
+        log(f"[bench] dielectric {pname}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            step(prec)
+        times = []
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            var, st = step(prec)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            log(f"[bench] dielectric {pname} step {i}: {times[-1]:.3f} s  (ir sweeps {st.ir_sweeps})")
+        t = float(np.mean(times))
+        out[pname] = {"seconds_per_step": t, "pair_solves_per_s": npairs / t, "ir_sweeps": int(st.ir_sweeps),
+                      "var": var.cpu().numpy()}
+        if not args.no_profile:
+            log(f"[bench] dielectric {pname}: profiled step")
+            fosb.profile_enable(ctx, True)
+            step(prec)
+            out[pname]["profile"] = fosb.profile_read(ctx)
+            fosb.profile_enable(ctx, False)
+    head = "mixed" if "mixed" in out else "fp64"
+    n_top = 2 * meshes[-1].n_edges
+    line = {"metric": "Cor[u'] level-pair solves/sec + MFMA TFLOP/s, mixed vs FP64 at 1e-6 rel err",
+            "value": out[head]["pair_solves_per_s"], "unit": "level-pair solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[head]["seconds_per_step"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "c64+f64" if head == "mixed" else "c128", "data": "synthetic",
+            "config": {"workload": f"dielectric sphere experiment: unit icosphere s={L0}..{L} (PMCHWT, 2N up to "
+                                   f"{n_top}), eps_r 2.1, mu_r 1, k0 3, d = e_x, p = e_z, rank-one RHS f (x) f, "
+                                   f"L0={L0} L={L} ({npairs} pairs), 1801 angles in z = 0",
+                       "precision": head, "ir_tol": args.ir_tol}}
+    for pname, rec in out.items():
+        line[pname] = {k: v for k, v in rec.items() if k not in ("var", "profile")}
+    with open(os.path.join(ROOT, "tests", "golden", "dielectric_mie_k3.json")) as f:
+        mie_f2 = np.asarray(json.load(f)["abs_F2"])   # |F_c|^2 of the Mie series, stored
+    for pname, rec in out.items():   # discretisation + CT error against the mesh-free value
+        line[pname]["abs_F2_vs_mie_rel_err"] = float(np.linalg.norm(rec["var"] - mie_f2) / np.linalg.norm(mie_f2))
+        line[pname]["abs_Fz2_vs_mie_rel_err"] = float(np.linalg.norm(rec["var"][2] - mie_f2[2]) /
+                                                      np.linalg.norm(mie_f2[2]))
+    if "mixed" in out and "fp64" in out:
+        a, b = out["mixed"]["var"], out["fp64"]["var"]
+        line["mixed_speedup_vs_fp64"] = out["fp64"]["seconds_per_step"] / out["mixed"]["seconds_per_step"]
+        line["mixed_vs_fp64_var_rel_err"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    for pname, rec in out.items():
+        prof = rec.get("profile")
+        if not prof:
+            continue
+        line[f"kernel_profile_{pname}"] = {k: {"launches": v[0], "seconds": v[1],
+                                               "tflops": (v[2] / v[1] / 1e12) if v[1] else 0,
+                                               "gbs": (v[3] / v[1] / 1e9) if v[1] else 0} for k, v in prof.items()}
+        kname = "gemm_f32" if pname == "mixed" else "gemm_f64"
+        n, sec, fl, by = prof[kname]
+        ach = fl / sec / 1e12 if sec > 0 else 0.0
+        key = "roofline" if pname == head else f"roofline_{pname}"
+        line[key] = {"kernel": f"k_gemm<{'float' if pname == 'mixed' else 'double'}>", "bound": "mfma",
+                     "achieved": ach, "peak": PEAK[pname], "unit": "TFLOP/s", "frac": ach / PEAK[pname],
+                     "traffic": None, "launches": n, "avg_launch_us": sec / max(n, 1) * 1e6,
+                     "algorithmic_flop_per_launch": fl / max(n, 1), "algorithmic_bytes_per_launch": by / max(n, 1)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     global PROGRESS
@@ -560,6 +667,9 @@ def main():
         sys.exit(2)
     if args.workload == "ellipsoids":
         run_batched(args)
+        return
+    if args.workload == "dielectric":
+        run_dielectric(args)
         return
     W = Workload(args.workload, args.max_level)
     gpu, (lu_f, solve_f, ff_f, npairs) = run_gpu(args, W)

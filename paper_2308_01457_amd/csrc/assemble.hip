@@ -760,17 +760,19 @@ __global__ __launch_bounds__(256) void k_pm_singular(MeshDev md, const int32_t* 
   }
 }
 
-// The 2N x 2N PMCHWT matrix from one band of EFIE (Tc) and MFIO (Kc) local
-// blocks at one wavenumber:  Z[m][n] (+)= cT1 T,  Z[m][N+n] (+)= K,
-// Z[N+m][n] (+)= -K,  Z[N+m][N+n] (+)= cT2 T, with T and K the sums of the
-// (up to) four local blocks of the band.  Stored where `first` is set and the
-// band holds T+ of n, added otherwise, so every entry is a fixed-order sum.
+// The 2N x 2N PMCHWT matrix from one band of local blocks at both
+// wavenumbers (EFIE T0, T1 and MFIO K0, K1, same layout):
+//   Z[m][n] = T0 + eta T1,  Z[m][N+n] = K0 + K1,  Z[N+m][n] = -(K0 + K1),
+//   Z[N+m][N+n] = T0 + T1/eta,
+// each block the sum of the (up to) four local blocks of the band.  Stored
+// when the band holds T+ of n, added otherwise (the band of T- when it comes
+// later), so every entry is a fixed-order sum.
 __global__ __launch_bounds__(256) void k_pm_gather(int ne, const int32_t* __restrict__ edge_tri,
                                                    const int32_t* __restrict__ edge_loc, int j0, int j1,
                                                    const int32_t* __restrict__ cols, int ncols,
-                                                   const c128* __restrict__ Tc, const c128* __restrict__ Kc,
-                                                   int64_t ldc, double cT1, double cT2, int first,
-                                                   c128* __restrict__ Z, int64_t ldz) {
+                                                   const c128* __restrict__ T0c, const c128* __restrict__ K0c,
+                                                   const c128* __restrict__ T1c, const c128* __restrict__ K1c,
+                                                   int64_t ldc, double eta, c128* __restrict__ Z, int64_t ldz) {
   const int ci = blockIdx.x * 64 + (threadIdx.x & 63);
   const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (ci >= ncols || m >= ne) return;
@@ -778,32 +780,29 @@ __global__ __launch_bounds__(256) void k_pm_gather(int ne, const int32_t* __rest
   const int tp = edge_tri[n], tm = edge_tri[ne + n];
   const int64_t rp = 3 * (int64_t)edge_tri[m] + edge_loc[m];
   const int64_t rm = 3 * (int64_t)edge_tri[ne + m] + edge_loc[ne + m];
-  double tr = 0.0, ti = 0.0, kr = 0.0, ki = 0.0;
+  double t0r = 0, t0i = 0, t1r = 0, t1i = 0, kr = 0, ki = 0;
+  auto add = [&](int64_t c) {
+    const c128 a = T0c[rp * ldc + c], b = T0c[rm * ldc + c];
+    const c128 e = T1c[rp * ldc + c], f = T1c[rm * ldc + c];
+    const c128 x = K0c[rp * ldc + c], y = K0c[rm * ldc + c];
+    const c128 u = K1c[rp * ldc + c], v = K1c[rm * ldc + c];
+    t0r += a.re + b.re;
+    t0i += a.im + b.im;
+    t1r += e.re + f.re;
+    t1i += e.im + f.im;
+    kr += (x.re + y.re) + (u.re + v.re);
+    ki += (x.im + y.im) + (u.im + v.im);
+  };
   const bool has_p = tp >= j0 && tp < j1;
-  if (has_p) {
-    const int64_t c = 3 * (int64_t)(tp - j0) + edge_loc[n];
-    const c128 u = Tc[rp * ldc + c], v = Tc[rm * ldc + c];
-    const c128 x = Kc[rp * ldc + c], y = Kc[rm * ldc + c];
-    tr += u.re + v.re;
-    ti += u.im + v.im;
-    kr += x.re + y.re;
-    ki += x.im + y.im;
-  }
-  if (tm >= j0 && tm < j1) {
-    const int64_t c = 3 * (int64_t)(tm - j0) + edge_loc[ne + n];
-    const c128 u = Tc[rp * ldc + c], v = Tc[rm * ldc + c];
-    const c128 x = Kc[rp * ldc + c], y = Kc[rm * ldc + c];
-    tr += u.re + v.re;
-    ti += u.im + v.im;
-    kr += x.re + y.re;
-    ki += x.im + y.im;
-  }
+  if (has_p) add(3 * (int64_t)(tp - j0) + edge_loc[n]);
+  if (tm >= j0 && tm < j1) add(3 * (int64_t)(tm - j0) + edge_loc[ne + n]);
+  const double ie = 1.0 / eta;
+  const c128 v00{t0r + eta * t1r, t0i + eta * t1i}, v01{kr, ki}, v10{-kr, -ki}, v11{t0r + ie * t1r, t0i + ie * t1i};
   c128* z00 = Z + (int64_t)m * ldz + n;
   c128* z01 = z00 + ne;
   c128* z10 = Z + (int64_t)(ne + m) * ldz + n;
   c128* z11 = z10 + ne;
-  const c128 v00{cT1 * tr, cT1 * ti}, v01{kr, ki}, v10{-kr, -ki}, v11{cT2 * tr, cT2 * ti};
-  if (first && has_p) {
+  if (has_p) {
     *z00 = v00;
     *z01 = v01;
     *z10 = v10;
@@ -829,13 +828,14 @@ void assemble_pmchwt(Context& ctx, const Mesh& m, double k0, double eps_r, doubl
   ensure_ss_table(ctx, n_gauss);
   Rule6 R;
   rule6(R.l, R.w);
-  // two band buffers (EFIE and MFIO blocks) of up to 512 MiB each
-  const int64_t budget = (int64_t)512 << 20;
+  // four band buffers (EFIE and MFIO blocks at k0 and k1) of up to 256 MiB each
+  const int64_t budget = (int64_t)256 << 20;
   int jc = (int)std::max<int64_t>(1, std::min<int64_t>(nt, budget / (9LL * nt * (int64_t)sizeof(c128))));
   if (jc < nt) jc = std::max(64, jc / 64 * 64);
   jc = std::min(jc, nt);
   const int64_t ldc = 3LL * jc;
-  DevBuf tband((size_t)(3LL * nt) * ldc * sizeof(c128)), kband((size_t)(3LL * nt) * ldc * sizeof(c128));
+  const size_t bb = (size_t)(3LL * nt) * ldc * sizeof(c128);
+  DevBuf band[4] = {DevBuf(bb), DevBuf(bb), DevBuf(bb), DevBuf(bb)};   // T0, K0, T1, K1
   std::vector<int32_t> cols;
   std::vector<int64_t> cbeg;
   for (int j0 = 0; j0 < nt; j0 += jc) {
@@ -850,35 +850,36 @@ void assemble_pmchwt(Context& ctx, const Mesh& m, double k0, double eps_r, doubl
   DevBuf dcols;
   upload(dcols, cols, s);
   const MeshDev md = m.dev();
-  const double kk[2] = {k0, k1}, c1[2] = {1.0, eta}, c2[2] = {1.0, 1.0 / eta};
-  for (int pass = 0; pass < 2; ++pass) {
-    int bi = 0;
-    for (int j0 = 0; j0 < nt; j0 += jc, ++bi) {
-      const int j1 = std::min(nt, j0 + jc);
-      const int w = j1 - j0;
+  const double kk[2] = {k0, k1};
+  int bi = 0;
+  for (int j0 = 0; j0 < nt; j0 += jc, ++bi) {
+    const int j1 = std::min(nt, j0 + jc);
+    const int w = j1 - j0;
+    const int pb = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j0) - h.tp_j.begin());
+    const int pe = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j1) - h.tp_j.begin());
+    for (int q = 0; q < 2; ++q) {
+      c128* Tc = band[2 * q].as<c128>();
+      c128* Kc = band[2 * q + 1].as<c128>();
       dim3 g1((w + 63) / 64, (nt + 3) / 4);
-      hipLaunchKernelGGL(k_pm_regular, g1, dim3(256), 0, s, md, R, kk[pass], j0, w, tband.as<c128>(),
-                         kband.as<c128>(), ldc);
+      hipLaunchKernelGGL(k_pm_regular, g1, dim3(256), 0, s, md, R, kk[q], j0, w, Tc, Kc, ldc);
       FOSB_LAUNCH_CHECK();
-      const int pb = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j0) - h.tp_j.begin());
-      const int pe = (int)(std::lower_bound(h.tp_j.begin(), h.tp_j.end(), j1) - h.tp_j.begin());
       if (pe > pb) {
         dim3 g2((pe - pb + 3) / 4);
         hipLaunchKernelGGL(k_pm_singular, g2, dim3(256), 0, s, md, m.tp_i.as<int32_t>(), m.tp_j.as<int32_t>(),
                            m.tp_kind.as<int32_t>(), m.tp_ord.as<int32_t>(), pb, pe, ctx.ss[n_gauss].as<double>(),
                            ctx.ss_off[n_gauss][0], ctx.ss_off[n_gauss][1], ctx.ss_off[n_gauss][2],
-                           ctx.ss_cnt[n_gauss][0], ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], kk[pass], j0,
-                           tband.as<c128>(), kband.as<c128>(), ldc);
+                           ctx.ss_cnt[n_gauss][0], ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], kk[q], j0, Tc,
+                           Kc, ldc);
         FOSB_LAUNCH_CHECK();
       }
-      const int nc = (int)(cbeg[bi + 1] - cbeg[bi]);
-      if (nc > 0) {
-        dim3 g3((nc + 63) / 64, (ne + 3) / 4);
-        hipLaunchKernelGGL(k_pm_gather, g3, dim3(256), 0, s, ne, md.edge_tri, md.edge_loc, j0, j1,
-                           dcols.as<int32_t>() + cbeg[bi], nc, tband.as<c128>(), kband.as<c128>(), ldc, c1[pass],
-                           c2[pass], pass == 0 ? 1 : 0, Z, ldz);
-        FOSB_LAUNCH_CHECK();
-      }
+    }
+    const int nc = (int)(cbeg[bi + 1] - cbeg[bi]);
+    if (nc > 0) {
+      dim3 g3((nc + 63) / 64, (ne + 3) / 4);
+      hipLaunchKernelGGL(k_pm_gather, g3, dim3(256), 0, s, ne, md.edge_tri, md.edge_loc, j0, j1,
+                         dcols.as<int32_t>() + cbeg[bi], nc, band[0].as<c128>(), band[1].as<c128>(),
+                         band[2].as<c128>(), band[3].as<c128>(), ldc, eta, Z, ldz);
+      FOSB_LAUNCH_CHECK();
     }
   }
   FOSB_HIP(hipStreamSynchronize(s));
