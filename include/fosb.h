@@ -240,9 +240,23 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
  * plane wave E^inc = p exp(i k0 d.x), H~^inc = (d x p) exp(i k0 d.x):
  *   b = [e; h],  e[m] = int phi_m . E^inc,  h[m] = int phi_m . H~^inc.
  * The level keeps b: fosb_rhs_correlation and fosb_correlation on dielectric
- * levels take cov = NULL and form the rank-one right-hand side
- * C = b_l1 b_l2^H of the paper's sphere validation (a second moment with
- * M2[f] = f (x) f, whose solution is u_l1 u_l2^H).  fosb_level_solve,
+ * levels with cov = NULL form the rank-one right-hand side C = b_l1 b_l2^H of
+ * the paper's sphere validation (a second moment with M2[f] = f (x) f, whose
+ * solution is u_l1 u_l2^H).
+ * field >= 0 (FOSB_FIELD_RADIAL or FOSB_FIELD_NORMAL; mu_r must be 1, else
+ * FOSB_E_UNSUPPORTED) also builds the shape-derivative weights W (FOA section,
+ * the DE shape-derivative equation), 2N x 6 nt per incidence, kept by the
+ * level: the derivative's traces solve Z [J'; M'] = W v for the amplitude v at
+ * the 6-point nodes, with the data derived from the transmission conditions
+ * (non-magnetic interior): jumps a = n x [E'] = grad_G(v_n [E_n]) x n and
+ * b = n x [H~'] = i k0 (1 - eps_r) v_n E_t, [E_n] = (1 - 1/eps_r) E_n^0, and
+ *   r_E = -eta <E_k1 b> - <H_k1 a> + 1/2 <n x a>,  r_H = -<H_k1 b> + <E_k1 a>/eta + 1/2 <n x b>
+ * (<X>[m] = int phi_m . X, principal values; 6-point rule on non-touching
+ * pairs with the source at the nodes, Sauter-Schwab with the amplitude's
+ * quadratic interpolant on touching ones).  fosb_rhs_correlation and
+ * fosb_correlation with a covariance then form C = W_l1 K W_l2^H (K at the
+ * nodes of both levels; v_n = v_r (x/|x|).n for the radial field).  field = -1
+ * builds none.  fosb_level_solve,
  * fosb_level_solve_adjoint, fosb_level_first_moment, fosb_two_sided_solve,
  * fosb_far_field_matrix and fosb_far_field_moments accept dielectric levels;
  * the entry points that need the shape-derivative weights of the PEC
@@ -251,7 +265,12 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
 fosb_status fosb_level_create_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, double k0, double eps_r,
                                      double mu_r, int32_t precision, void* Z, int64_t ldz, void* Zlow,
                                      int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs,
-                                     const fosb_opts* opts, fosb_level** out);
+                                     int32_t field, const fosb_opts* opts, fosb_level** out);
+/* Copies the shape-derivative weights of incidence dir of a dielectric level
+ * built with field >= 0 into W (device, 2N x 6 nt complex128, row stride
+ * ldw >= 6 nt; column 6 t + q is node q of triangle t, the radial factor
+ * included).  FOSB_E_INVALID for a level without them. */
+fosb_status fosb_level_sd_weights(fosb_context* ctx, const fosb_level* level, int64_t dir, void* W, int64_t ldw);
 /* The level's formulation (fosb_formulation) and, for FOSB_FORM_PMCHWT, its
  * eps_r and mu_r (1 for EFIE levels).  Any output pointer may be NULL. */
 fosb_status fosb_level_formulation(const fosb_level* level, int32_t* form, double* eps_r, double* mu_r);
@@ -286,9 +305,10 @@ fosb_status fosb_level_destroy(fosb_level* level);
  * second-moment tensor equation; combination-technique sub-systems), with K
  * the covariance of the amplitude at the quadrature nodes of both levels.
  * C: device, N1 x N2 complex128, row stride ldc >= N2.  dir selects the
- * incidence (first moment) of both levels.  Dielectric levels (cov = NULL):
- * the rank-one C = b_l1 b_l2^H of their right-hand sides (sphere validation
- * of the DE second moment, M2[f] = f (x) f). */
+ * incidence (first moment) of both levels.  Dielectric levels: with
+ * cov = NULL the rank-one C = b_l1 b_l2^H of their right-hand sides (sphere
+ * validation of the DE second moment, M2[f] = f (x) f); with a covariance
+ * (levels built with shape-derivative weights) C = W_l1 K W_l2^H. */
 fosb_status fosb_rhs_correlation(fosb_context* ctx, const fosb_level* l1, const fosb_level* l2,
                                  const fosb_cov* cov, int64_t dir, void* C, int64_t ldc);
 /* In place: C (N1 x N2) <- Sigma with Z1 Sigma Z2^H = C, i.e. the sub-system
@@ -305,7 +325,8 @@ fosb_status fosb_ct_pairs(int32_t L0, int32_t L, int32_t* l1, int32_t* l2, int32
 /* All Sigma blocks of Lambda_H for direction dir.  levels[i] is level L0 + i
  * (n_levels = L - L0 + 1); blocks[p] (device, N_l1 x N_l2 complex128, row
  * stride ldb[p]) receives the block of pair p in fosb_ct_pairs order.
- * Dielectric levels take cov = NULL (rank-one right-hand sides). */
+ * Dielectric levels take cov = NULL (rank-one right-hand sides) or, when built
+ * with shape-derivative weights, a covariance. */
 fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
                              int32_t L0, int32_t L, const fosb_cov* cov, int64_t dir,
                              void* const* blocks, const int64_t* ldb, fosb_stats* stats);

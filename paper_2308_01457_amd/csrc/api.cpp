@@ -368,7 +368,7 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
                                                void* Z, int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs,
                                                const double* pols, int64_t n_dirs, int32_t field,
                                                const fosb_opts& o, int32_t form = FOSB_FORM_EFIE,
-                                               double eps_r = 1.0, double mu_r = 1.0) {
+                                               double eps_r = 1.0, double mu_r = 1.0, int32_t sd_field = -1) {
   hipStream_t s = c.stream;
   const bool pm = form == FOSB_FORM_PMCHWT;
   const int64_t n = pm ? 2 * mesh->h.ne : mesh->h.ne;
@@ -453,6 +453,16 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     incident_rhs_pmchwt(s, *mesh, k, ddir.as<double>(), dpol.as<double>(), (int)n_dirs, L->b.as<c128>());
     copy_c128(s, L->b.as<c128>(), n_dirs, L->u.as<c128>(), n_dirs, n, n_dirs);
     level_solve_inplace(c, *L, L->u.as<c128>(), n_dirs, n_dirs, nullptr);
+    if (sd_field >= 0) {  // shape-derivative weights per incidence, and the nodes for the covariance
+      const int64_t Q = 6LL * mesh->h.nt;
+      L->sd_field = sd_field;
+      L->qx.alloc((size_t)3 * Q * sizeof(double));
+      quad_nodes(s, *mesh, L->qx.as<double>());
+      L->Wsd.alloc((size_t)n_dirs * n * Q * sizeof(c128));
+      for (int64_t d = 0; d < n_dirs; ++d)
+        sd_weights(c, *mesh, k, eps_r, sd_field, L->u.as<c128>(), n_dirs, d, o.n_gauss_singular,
+                   L->Wsd.as<c128>() + d * n * Q, Q);
+    }
     if (o.certify) L->kappa1 = L->z_one * inverse_norm1_estimate(c, *L);
     FOSB_HIP(hipStreamSynchronize(s));
     return L;
@@ -520,8 +530,8 @@ static void check_pair(const fosb_context* ctx, const fosb_level* a, const fosb_
   REQUIRE(a->k == b->k, "levels have different wavenumbers");
   REQUIRE(a->n_dirs == b->n_dirs, "levels have different incidence sets");
   REQUIRE(a->field == b->field, "levels use different perturbation fields");
-  REQUIRE(a->form == b->form && a->eps_r == b->eps_r && a->mu_r == b->mu_r,
-          "levels use different formulations or materials");
+  REQUIRE(a->form == b->form && a->eps_r == b->eps_r && a->mu_r == b->mu_r && a->sd_field == b->sd_field,
+          "levels use different formulations, materials or perturbation fields");
 }
 
 // Entry points built on the PEC shape-derivative weights take EFIE levels only.
@@ -540,14 +550,38 @@ static void level_far_field(hipStream_t s, const Level& l, const double* dx, int
     far_field_matrix_kernel(s, *l.mesh, l.k, dx, n_a, FF);
 }
 
-// RHS correlation of a pair: the covariance form (EFIE) or the rank-one
-// b_l1 b_l2^H (PMCHWT, cov NULL).
-static void pair_rhs(hipStream_t s, const Level& a, const Level& b, const fosb_cov* cov, int64_t dir, c128* C,
+// C = Wsd_a K Wsd_b^H for dielectric levels with shape-derivative weights, K
+// the amplitude covariance at the nodes of both levels, formed in row chunks
+// of at most 2^26 entries: T = K_chunk Wsd_b^H, C += Wsd_a[:, chunk] T.
+static void sd_correlation(Context& c, const Level& a, const Level& b, const fosb_cov& cov, int64_t dir, c128* C,
+                           int64_t ldc) {
+  hipStream_t s = c.stream;
+  const int64_t Q1 = 6LL * a.mesh->h.nt, Q2 = 6LL * b.mesh->h.nt, n1 = a.n, n2 = b.n;
+  const c128* W1 = a.Wsd.as<c128>() + dir * n1 * Q1;
+  const c128* W2 = b.Wsd.as<c128>() + dir * n2 * Q2;
+  DevBuf W2h((size_t)Q2 * n2 * sizeof(c128));
+  conj_transpose_c128(s, W2, Q2, W2h.as<c128>(), n2, n2, Q2);
+  const int64_t na = std::max<int64_t>(1, std::min<int64_t>(Q1, ((int64_t)1 << 26) / Q2));
+  DevBuf Kc((size_t)na * Q2 * sizeof(c128)), T((size_t)na * n2 * sizeof(c128));
+  for (int64_t a0 = 0; a0 < Q1; a0 += na) {
+    const int64_t nr = std::min(na, Q1 - a0);
+    cov_matrix(s, a, b, cov, a0, nr, Kc.as<c128>());
+    gemm<double>(c, nr, n2, Q2, 1.0, Kc.as<c128>(), Q2, W2h.as<c128>(), n2, 0.0, T.as<c128>(), n2);
+    gemm<double>(c, n1, n2, nr, 1.0, W1 + a0, Q1, T.as<c128>(), n2, a0 == 0 ? 0.0 : 1.0, C, ldc);
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
+}
+
+// RHS correlation of a pair: the covariance form (EFIE, or dielectric levels
+// with shape-derivative weights) or the rank-one b_l1 b_l2^H (dielectric, cov NULL).
+static void pair_rhs(Context& c, const Level& a, const Level& b, const fosb_cov* cov, int64_t dir, c128* C,
                      int64_t ldc) {
-  if (a.form == FOSB_FORM_PMCHWT)
-    rank_one_correlation(s, a.b.as<c128>(), a.n, b.b.as<c128>(), b.n, a.n_dirs, dir, C, ldc);
+  if (a.form == FOSB_FORM_PMCHWT && !cov)
+    rank_one_correlation(c.stream, a.b.as<c128>(), a.n, b.b.as<c128>(), b.n, a.n_dirs, dir, C, ldc);
+  else if (a.form == FOSB_FORM_PMCHWT)
+    sd_correlation(c, a, b, *cov, dir, C, ldc);
   else
-    rhs_correlation_kernel(s, a, b, *cov, dir, C, ldc);
+    rhs_correlation_kernel(c.stream, a, b, *cov, dir, C, ldc);
 }
 
 static void check_cov_for(const fosb_level* l, const fosb_cov* cov);
@@ -561,10 +595,11 @@ static void check_cov(const fosb_cov* cov) {
 }
 
 static void check_cov_for(const fosb_level* l, const fosb_cov* cov) {
+  if (l->form == FOSB_FORM_PMCHWT && !cov) return;   // rank-one right-hand side
   if (l->form == FOSB_FORM_PMCHWT)
-    REQUIRE(!cov, "dielectric levels take cov = NULL (rank-one right-hand side)");
-  else
-    check_cov(cov);
+    REQUIRE(l->sd_field >= 0, "a covariance right-hand side needs dielectric levels built with shape-derivative "
+                              "weights (field >= 0)");
+  check_cov(cov);
 }
 
 static std::vector<std::array<int32_t, 4>> ct_pairs_vec(int32_t L0, int32_t L) {
@@ -913,7 +948,7 @@ fosb_status fosb_assemble_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, doubl
 fosb_status fosb_level_create_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, double k0, double eps_r,
                                      double mu_r, int32_t precision, void* Z, int64_t ldz, void* Zlow,
                                      int64_t ldzlow, const double* dirs, const double* pols, int64_t n_dirs,
-                                     const fosb_opts* opts, fosb_level** out) {
+                                     int32_t field, const fosb_opts* opts, fosb_level** out) {
   API_BEGIN
   REQUIRE(ctx && mesh && out, "ctx/mesh/out is NULL");
   *out = nullptr;
@@ -929,17 +964,35 @@ fosb_status fosb_level_create_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, d
   } else {
     REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
   }
+  REQUIRE(field == -1 || field == FOSB_FIELD_RADIAL || field == FOSB_FIELD_NORMAL, "unknown field %d", field);
+  if (field >= 0 && mu_r != 1.0)
+    fail(FOSB_E_UNSUPPORTED, "the dielectric shape-derivative weights are built for mu_r = 1");
   fosb_opts o = opts_or_default(opts);
   bind(*ctx);
-  check_device_memory(*ctx, level_bytes(n, 0, precision, n_dirs) + solve_work_bytes(n, precision, n_dirs),
+  const int64_t sd_bytes = field >= 0 ? n_dirs * n * 6LL * mesh->h.nt * 16 + 24LL * mesh->h.nt : 0;
+  check_device_memory(*ctx, level_bytes(n, 0, precision, n_dirs) + solve_work_bytes(n, precision, n_dirs) + sd_bytes,
                       "the level");
   auto L = level_build(*ctx, mesh, k0, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, FOSB_FIELD_NORMAL, o,
-                       FOSB_FORM_PMCHWT, eps_r, mu_r);
+                       FOSB_FORM_PMCHWT, eps_r, mu_r, field);
   {
     std::lock_guard<std::mutex> lock(ctx->reg_mu);
     ctx->live_levels.insert(L.get());
   }
   *out = L.release();
+  API_END
+}
+
+fosb_status fosb_level_sd_weights(fosb_context* ctx, const fosb_level* level, int64_t dir, void* W, int64_t ldw) {
+  API_BEGIN
+  REQUIRE(ctx && level && W, "NULL argument");
+  REQUIRE(level->ctx == ctx, "level belongs to another context");
+  REQUIRE(level->form == FOSB_FORM_PMCHWT && level->sd_field >= 0, "the level has no shape-derivative weights");
+  REQUIRE(dir >= 0 && dir < level->n_dirs, "dir out of range");
+  const int64_t Q = 6LL * level->mesh->h.nt;
+  if (ldw < Q) fail(FOSB_E_WORKSPACE, "ldw < 6 nt");
+  bind(*ctx);
+  copy_c128(ctx->stream, level->Wsd.as<c128>() + dir * level->n * Q, Q, static_cast<c128*>(W), ldw, level->n, Q);
+  FOSB_HIP(hipStreamSynchronize(ctx->stream));
   API_END
 }
 
@@ -1037,7 +1090,7 @@ fosb_status fosb_rhs_correlation(fosb_context* ctx, const fosb_level* l1, const 
   REQUIRE(dir >= 0 && dir < l1->n_dirs, "dir out of range");
   if (ldc < l2->n) fail(FOSB_E_WORKSPACE, "ldc < N2");
   bind(*ctx);
-  pair_rhs(ctx->stream, *l1, *l2, cov, dir, static_cast<c128*>(C), ldc);
+  pair_rhs(*ctx, *l1, *l2, cov, dir, static_cast<c128*>(C), ldc);
   API_END
 }
 
@@ -1089,7 +1142,7 @@ fosb_status fosb_correlation(fosb_context* ctx, const fosb_level* const* levels,
     c128* C = static_cast<c128*>(blocks[p]);
     {
       ProfScope prof(*ctx, FOSB_K_RHS, 0.0, 16.0 * (double)a->n * (double)b->n);
-      pair_rhs(ctx->stream, *a, *b, cov, dir, C, ldb[p]);
+      pair_rhs(*ctx, *a, *b, cov, dir, C, ldb[p]);
     }
     two_sided(*ctx, *a, *b, C, ldb[p], stats);
   }

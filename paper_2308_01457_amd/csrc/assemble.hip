@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include <functional>
+#include <map>
 
 #include "common.h"
 
@@ -881,6 +882,410 @@ void assemble_pmchwt(Context& ctx, const Mesh& m, double k0, double eps_r, doubl
                          band[2].as<c128>(), band[3].as<c128>(), ldc, eta, Z, ldz);
       FOSB_LAUNCH_CHECK();
     }
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ dielectric shape-derivative right-hand side
+//
+// W (2N x 6 nt) maps the perturbation amplitude at the 6-point nodes to the
+// PMCHWT right-hand side of the shape derivative (non-magnetic interior):
+//   r_E = -eta <E_k1 b> - <H_k1 a> + 1/2 <n x a>,   r_H = -<H_k1 b> + <E_k1 a>/eta + 1/2 <n x b>,
+// with the jumps a = curl_G psi, psi = v_n (1 - 1/eps_r) E^0_n, E^0_n = -(i/k0) div J, and
+// b = i k0 (1 - eps_r) v_n E_t, E_t = n x M, and (by parts onto the kernel)
+//   <E_k a> = i k int int phi_m . (grad_x G x n_y) psi,  <n x a> = -int psi div phi_m,
+//   <H_k a> = k^2 int int G phi_m . n_y psi - int int div phi_m (grad_x G . n_y) psi,
+//   <E_k b> = i k int int G phi_m . b - (i/k) int int div phi_m grad_x G . b,
+//   <H_k b> = int int phi_m . (grad_x G x b).
+// Non-touching triangle pairs: the 6-point rule in x, the source at the node;
+// touching pairs: Sauter-Schwab points with the amplitude's quadratic
+// interpolant through the source triangle's six nodes.
+
+struct SdParams {
+  double k0, k1, eta, cbi;   // cb = i k0 (1 - eps_r) = i cbi
+  int field;                 // FOSB_FIELD_RADIAL or FOSB_FIELD_NORMAL
+  double lag[6][6];          // ell_q(l1, l2) = sum_k mono_k(l1, l2) lag[k][q], mono = (1, l1, l2, l1^2, l1 l2, l2^2)
+};
+
+// Per triangle t: c_psi (re, im) and the M coefficients of its three local RWG functions.
+__global__ void k_sd_tri_data(MeshDev md, const c128* __restrict__ u, int64_t ldu, int64_t dir, double k0,
+                              double eps_r, double* __restrict__ td) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= md.nt) return;
+  double dr = 0, di = 0;
+  double* o = td + 8LL * t;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int e = md.tri_edge[a * md.nt + t];
+    const c128 uj = u[(int64_t)e * ldu + dir], um = u[(int64_t)(md.ne + e) * ldu + dir];
+    const double al = md.alpha[a * md.nt + t];
+    dr += al * uj.re;
+    di += al * uj.im;
+    o[2 + 2 * a] = um.re;
+    o[3 + 2 * a] = um.im;
+  }
+  // E_n = -(i/k0) div J;  c_psi = (1 - 1/eps_r) E_n
+  const double f = (1.0 - 1.0 / eps_r) / k0;
+  o[0] = f * di;
+  o[1] = -f * dr;
+}
+
+__device__ __forceinline__ bool tri_touch(const MeshDev& md, int i, int j) {
+  const int nt = md.nt;
+  const int a0 = md.fv[i], a1 = md.fv[nt + i], a2 = md.fv[2 * nt + i];
+  const int b0 = md.fv[j], b1 = md.fv[nt + j], b2 = md.fv[2 * nt + j];
+  return a0 == b0 || a0 == b1 || a0 == b2 || a1 == b0 || a1 == b1 || a1 == b2 || a2 == b0 || a2 == b1 || a2 == b2;
+}
+
+// E_t(y) = n x sum_b uM_b (alpha_b / 2)(y - P_b) on triangle t, y and P relative to the same origin.
+__device__ __forceinline__ void sd_et(const double* td, const double al[3], const double P[3][3], const double n[3],
+                                      const double y[3], double er[3], double ei[3]) {
+  double mr[3] = {0, 0, 0}, mi[3] = {0, 0, 0};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const double h = 0.5 * al[b];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = h * (y[c] - P[b][c]);
+      mr[c] += td[2 + 2 * b] * v;
+      mi[c] += td[3 + 2 * b] * v;
+    }
+  }
+  cross3(n, mr, er);
+  cross3(n, mi, ei);
+}
+
+// The four kernel sums of one point pair (x, y), weight folded into Gr/Gi:
+// EA += h f.(d x n), HA += k^2 G f.n - alpha h d.n, EB += i k G f.E - (i/k) alpha h d.E,
+// HB += h f.(d x E), with h = G (i k R - 1) / R^2, d = x - y.
+struct SdAcc {
+  double EAr = 0, EAi = 0, HAr = 0, HAi = 0, EBr = 0, EBi = 0, HBr = 0, HBi = 0;
+};
+
+__device__ __forceinline__ void sd_point(double k, const double f[3], double alpha, const double d[3], double r,
+                                         double ir, double Gr, double Gi, const double n[3], const double er[3],
+                                         const double ei[3], double s, SdAcc& A) {
+  const double ir2 = ir * ir, kr = k * r;
+  const double hr = (-Gr - Gi * kr) * ir2, hi = (Gr * kr - Gi) * ir2;
+  double dn[3], dEr[3], dEi[3];
+  cross3(d, n, dn);
+  cross3(d, er, dEr);
+  cross3(d, ei, dEi);
+  const double fdn = f[0] * dn[0] + f[1] * dn[1] + f[2] * dn[2];
+  const double fn = f[0] * n[0] + f[1] * n[1] + f[2] * n[2];
+  const double ddn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+  const double fEr = f[0] * er[0] + f[1] * er[1] + f[2] * er[2], fEi = f[0] * ei[0] + f[1] * ei[1] + f[2] * ei[2];
+  const double dEr_ = d[0] * er[0] + d[1] * er[1] + d[2] * er[2], dEi_ = d[0] * ei[0] + d[1] * ei[1] + d[2] * ei[2];
+  const double fdEr = f[0] * dEr[0] + f[1] * dEr[1] + f[2] * dEr[2];
+  const double fdEi = f[0] * dEi[0] + f[1] * dEi[1] + f[2] * dEi[2];
+  A.EAr += s * hr * fdn;
+  A.EAi += s * hi * fdn;
+  A.HAr += s * (k * k * Gr * fn - alpha * hr * ddn);
+  A.HAi += s * (k * k * Gi * fn - alpha * hi * ddn);
+  // i k G (fEr + i fEi) = k (-Gi fEr - Gr fEi) + i k (Gr fEr - Gi fEi)
+  // -(i/k) alpha h (dEr + i dEi) = (alpha/k) (hr dEi + hi dEr) + i (alpha/k) (hi dEi - hr dEr)
+  A.EBr += s * (k * (-Gi * fEr - Gr * fEi) + alpha / k * (hr * dEi_ + hi * dEr_));
+  A.EBi += s * (k * (Gr * fEr - Gi * fEi) + alpha / k * (hi * dEi_ - hr * dEr_));
+  A.HBr += s * (hr * fdEr - hi * fdEi);
+  A.HBi += s * (hr * fdEi + hi * fdEr);
+}
+
+// Combines the sums of one (row m, source node) into W[m][col], W[N+m][col]:
+// WE = -eta cb EB - c_psi HA, WH = -cb HB + i k c_psi EA / eta, plus the identity parts.
+__device__ __forceinline__ void sd_combine(const SdParams& sp, const SdAcc& A, double cpr, double cpi, double IEr,
+                                           double IEi, double IHr, double IHi, double nu, double& WEr, double& WEi,
+                                           double& WHr, double& WHi) {
+  // cb X = i cbi (Xr + i Xi) = -cbi Xi + i cbi Xr
+  const double cEBr = -sp.cbi * A.EBi, cEBi = sp.cbi * A.EBr;
+  const double cHBr = -sp.cbi * A.HBi, cHBi = sp.cbi * A.HBr;
+  const double pHAr = cpr * A.HAr - cpi * A.HAi, pHAi = cpr * A.HAi + cpi * A.HAr;
+  const double pEAr = cpr * A.EAr - cpi * A.EAi, pEAi = cpr * A.EAi + cpi * A.EAr;
+  // i k pEA / eta
+  const double kEAr = -sp.k1 * pEAi / sp.eta, kEAi = sp.k1 * pEAr / sp.eta;
+  WEr = nu * (-sp.eta * cEBr - pHAr + IEr);
+  WEi = nu * (-sp.eta * cEBi - pHAi + IEi);
+  WHr = nu * (-cHBr + kEAr + IHr);
+  WHi = nu * (-cHBi + kEAi + IHi);
+}
+
+// One thread per (RWG row m, source node col = 6 j + q): the non-touching triangles of m
+// with the 6-point rule, the identity parts; stores W[m][col] and W[N+m][col].
+__global__ __launch_bounds__(256) void k_sd_regular(MeshDev md, Rule6 R, SdParams sp, const double* __restrict__ td,
+                                                    c128* __restrict__ W, int64_t ldw) {
+  const int64_t Q = 6LL * md.nt;
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int m = blockIdx.y;
+  if (col >= Q || m >= md.ne) return;
+  const int j = (int)(col / 6), q = (int)(col % 6);
+  const int nt = md.nt, ne = md.ne;
+  double Pj[3][3], cj[3];
+  load_tri(md, j, Pj, cj);
+  const double nj[3] = {md.nrm[j], md.nrm[nt + j], md.nrm[2 * nt + j]};
+  const double alj[3] = {md.alpha[j], md.alpha[nt + j], md.alpha[2 * nt + j]};
+  double y[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[c] = R.l[q][0] * Pj[0][c] + R.l[q][1] * Pj[1][c] + R.l[q][2] * Pj[2][c];
+  const double wq = R.w[q] * md.area[j];
+  const double* tj = td + 8LL * j;
+  double er[3], ei[3];
+  sd_et(tj, alj, Pj, nj, y, er, ei);
+  double nu = 1.0;
+  if (sp.field == FOSB_FIELD_RADIAL) {
+    const double iy = rsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    nu = (y[0] * nj[0] + y[1] * nj[1] + y[2] * nj[2]) * iy;
+  }
+  SdAcc A;
+  double IEr = 0, IEi = 0, IHr = 0, IHi = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int i = md.edge_tri[side * ne + m];
+    const int a = md.edge_loc[side * ne + m];
+    double Pi[3][3], ci[3];
+    load_tri(md, i, Pi, ci);
+    const double ala = md.alpha[a * nt + i];
+    if (i == j) {  // identity parts: -1/2 c_psi alpha_a w_q, 1/2 cb phi_a(y).(n x E_t) w_q
+      double nE_r[3], nE_i[3];
+      cross3(nj, er, nE_r);
+      cross3(nj, ei, nE_i);
+      double fr = 0, fi = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double fc = 0.5 * ala * (y[c] - Pi[a][c]);
+        fr += fc * nE_r[c];
+        fi += fc * nE_i[c];
+      }
+      IEr += -0.5 * tj[0] * ala * wq;
+      IEi += -0.5 * tj[1] * ala * wq;
+      // 1/2 i cbi (fr + i fi) wq
+      IHr += -0.5 * sp.cbi * fi * wq;
+      IHi += 0.5 * sp.cbi * fr * wq;
+    }
+    if (tri_touch(md, i, j)) continue;  // integrated by k_sd_singular
+    for (int p = 0; p < 6; ++p) {
+      double x[3], f[3], d[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x[c] = R.l[p][0] * Pi[0][c] + R.l[p][1] * Pi[1][c] + R.l[p][2] * Pi[2][c];
+        f[c] = 0.5 * ala * (x[c] - Pi[a][c]);
+        d[c] = x[c] - y[c];
+      }
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const double ir = rsqrt(r2);
+      const double r = r2 * ir;
+      double sn, cs;
+      sincos_phase(sp.k1 * r, &sn, &cs);
+      const double g = R.w[p] * md.area[i] * wq * kInv4Pi * ir;
+      sd_point(sp.k1, f, ala, d, r, ir, cs * g, sn * g, nj, er, ei, 1.0, A);
+    }
+  }
+  double WEr, WEi, WHr, WHi;
+  sd_combine(sp, A, tj[0], tj[1], IEr, IEi, IHr, IHi, nu, WEr, WEi, WHr, WHi);
+  W[(int64_t)m * ldw + col] = c128{WEr, WEi};
+  W[(int64_t)(ne + m) * ldw + col] = c128{WHr, WHi};
+}
+
+// One wavefront per (RWG row m, source triangle j) with a triangle of m touching j:
+// Sauter-Schwab points over the lanes, the amplitude's quadratic interpolant in j;
+// adds to W[m][6 j + q] and W[N+m][6 j + q], q = 0..5.
+__global__ __launch_bounds__(256) void k_sd_singular(MeshDev md, Rule6 R, SdParams sp, const double* __restrict__ td,
+                                                     const int32_t* __restrict__ sm_m, const int32_t* __restrict__ sm_j,
+                                                     const int32_t* __restrict__ sm_p, int nS,
+                                                     const int32_t* __restrict__ tp_kind,
+                                                     const int32_t* __restrict__ tp_ord, const double* __restrict__ ss,
+                                                     int off0, int off1, int off2, int cnt0, int cnt1, int cnt2,
+                                                     c128* __restrict__ W, int64_t ldw) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (e >= nS) return;
+  const int m = sm_m[e], j = sm_j[e];
+  const int nt = md.nt, ne = md.ne;
+  double Pj[3][3], cj[3];
+  load_tri(md, j, Pj, cj);
+  double Lj[3][3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Lj[v][c] = Pj[v][c] - cj[c];
+  const double nj[3] = {md.nrm[j], md.nrm[nt + j], md.nrm[2 * nt + j]};
+  const double alj[3] = {md.alpha[j], md.alpha[nt + j], md.alpha[2 * nt + j]};
+  const double* tj = td + 8LL * j;
+  SdAcc A[6];
+  for (int side = 0; side < 2; ++side) {
+    const int p = sm_p[2 * e + side];
+    if (p < 0) continue;
+    const int i = md.edge_tri[side * ne + m];
+    const int a = md.edge_loc[side * ne + m];
+    const int kind = tp_kind[p];
+    const int* ord = tp_ord + 6 * p;
+    double Pi[3][3], ci[3], Li[3][3];
+    load_tri(md, i, Pi, ci);
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Li[v][c] = Pi[v][c] - ci[c];
+    const double ala = md.alpha[a * nt + i];
+    const double dc[3] = {ci[0] - cj[0], ci[1] - cj[1], ci[2] - cj[2]};
+    double S0[3], S1[3], S2[3], T0[3], T1[3], T2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      S0[c] = Li[ord[0]][c]; S1[c] = Li[ord[1]][c] - Li[ord[0]][c]; S2[c] = Li[ord[2]][c] - Li[ord[1]][c];
+      T0[c] = Lj[ord[3]][c]; T1[c] = Lj[ord[4]][c] - Lj[ord[3]][c]; T2[c] = Lj[ord[5]][c] - Lj[ord[4]][c];
+    }
+    const double jac = 4.0 * md.area[i] * md.area[j] * kInv4Pi;
+    const int off = kind == 0 ? off0 : (kind == 1 ? off1 : off2);
+    const int cnt = kind == 0 ? cnt0 : (kind == 1 ? cnt1 : cnt2);
+    for (int mm = lane; mm < cnt; mm += 64) {
+      const double* pt = ss + 5 * (int64_t)(off + mm);
+      const double x1 = pt[0], x2 = pt[1], y1 = pt[2], y2 = pt[3], w = pt[4];
+      double x[3], y[3], f[3], d[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x[c] = S0[c] + x1 * S1[c] + x2 * S2[c];
+        y[c] = T0[c] + y1 * T1[c] + y2 * T2[c];
+        f[c] = 0.5 * ala * (x[c] - Li[a][c]);
+        d[c] = x[c] - y[c] + dc[c];
+      }
+      // barycentric coordinates of y in j's own vertex order
+      double lam[3];
+      lam[ord[3]] = 1.0 - y1;
+      lam[ord[4]] = y1 - y2;
+      lam[ord[5]] = y2;
+      const double l1 = lam[1], l2 = lam[2];
+      const double mono[6] = {1.0, l1, l2, l1 * l1, l1 * l2, l2 * l2};
+      double er[3], ei[3];
+      sd_et(tj, alj, Lj, nj, y, er, ei);
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      const double ir = rsqrt(r2);
+      const double r = r2 * ir;
+      double sn, cs;
+      sincos(sp.k1 * r, &sn, &cs);
+      const double g = w * jac * ir;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        double ell = 0;
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) ell += mono[kk] * sp.lag[kk][q];
+        sd_point(sp.k1, f, ala, d, r, ir, cs * g, sn * g, nj, er, ei, ell, A[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    A[q].EAr = wave_sum(A[q].EAr);
+    A[q].EAi = wave_sum(A[q].EAi);
+    A[q].HAr = wave_sum(A[q].HAr);
+    A[q].HAi = wave_sum(A[q].HAi);
+    A[q].EBr = wave_sum(A[q].EBr);
+    A[q].EBi = wave_sum(A[q].EBi);
+    A[q].HBr = wave_sum(A[q].HBr);
+    A[q].HBi = wave_sum(A[q].HBi);
+  }
+  if (lane < 6) {
+    const int q = lane;
+    SdAcc Aq;
+#pragma unroll
+    for (int qq = 0; qq < 6; ++qq)
+      if (qq == q) Aq = A[qq];
+    double nu = 1.0;
+    if (sp.field == FOSB_FIELD_RADIAL) {  // (y_q / |y_q|) . n at node q of j
+      double y[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = R.l[q][0] * Pj[0][c] + R.l[q][1] * Pj[1][c] + R.l[q][2] * Pj[2][c];
+      nu = (y[0] * nj[0] + y[1] * nj[1] + y[2] * nj[2]) * rsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    }
+    const int64_t col = 6LL * j + q;
+    double WEr, WEi, WHr, WHi;
+    sd_combine(sp, Aq, tj[0], tj[1], 0.0, 0.0, 0.0, 0.0, nu, WEr, WEi, WHr, WHi);
+    c128* w0 = W + (int64_t)m * ldw + col;
+    c128* w1 = W + (int64_t)(ne + m) * ldw + col;
+    const c128 o0 = *w0, o1 = *w1;
+    *w0 = c128{o0.re + WEr, o0.im + WEi};
+    *w1 = c128{o1.re + WHr, o1.im + WHi};
+  }
+}
+
+// Inverse of the 6 x 6 matrix of the monomials (1, l1, l2, l1^2, l1 l2, l2^2) at
+// the 6-point nodes (Gauss-Jordan with partial pivoting): the coefficients of
+// the quadratic Lagrange basis through the nodes.
+static void lagrange6(double out[6][6]) {
+  double bary[6][3], w[6];
+  rule6(bary, w);
+  double A[6][12];
+  for (int r = 0; r < 6; ++r) {
+    const double l1 = bary[r][1], l2 = bary[r][2];
+    const double mono[6] = {1.0, l1, l2, l1 * l1, l1 * l2, l2 * l2};
+    for (int c = 0; c < 6; ++c) {
+      A[r][c] = mono[c];
+      A[r][6 + c] = r == c ? 1.0 : 0.0;
+    }
+  }
+  for (int c = 0; c < 6; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 6; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    for (int k = 0; k < 12; ++k) std::swap(A[c][k], A[piv][k]);
+    const double d = A[c][c];
+    for (int k = 0; k < 12; ++k) A[c][k] /= d;
+    for (int r = 0; r < 6; ++r)
+      if (r != c) {
+        const double f = A[r][c];
+        for (int k = 0; k < 12; ++k) A[r][k] -= f * A[c][k];
+      }
+  }
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) out[r][c] = A[r][6 + c];
+}
+
+void sd_weights(Context& ctx, const Mesh& m, double k0, double eps_r, int field, const c128* u, int64_t ldu,
+                int64_t dir, int n_gauss, c128* W, int64_t ldw) {
+  hipStream_t s = ctx.stream;
+  const MeshHost& h = m.h;
+  const int nt = (int)h.nt, ne = (int)h.ne;
+  ensure_ss_table(ctx, n_gauss);
+  Rule6 R;
+  rule6(R.l, R.w);
+  SdParams sp;
+  sp.k0 = k0;
+  sp.k1 = k0 * std::sqrt(eps_r);
+  sp.eta = 1.0 / std::sqrt(eps_r);
+  sp.cbi = k0 * (1.0 - eps_r);
+  sp.field = field;
+  lagrange6(sp.lag);
+  DevBuf td((size_t)8 * nt * sizeof(double));
+  hipLaunchKernelGGL(k_sd_tri_data, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, m.dev(), u, ldu, dir, k0,
+                     eps_r, td.as<double>());
+  FOSB_LAUNCH_CHECK();
+  const int64_t Q = 6LL * nt;
+  dim3 g1((unsigned)((Q + 255) / 256), (unsigned)ne);
+  hipLaunchKernelGGL(k_sd_regular, g1, dim3(256), 0, s, m.dev(), R, sp, td.as<double>(), W, ldw);
+  FOSB_LAUNCH_CHECK();
+  // (row m, source triangle j) with a triangle of m touching j, and the touching-pair index per side
+  std::vector<std::vector<std::pair<int, int>>> by_i(nt);   // i -> (j, pair index)
+  for (size_t p = 0; p < h.tp_i.size(); ++p) by_i[h.tp_i[p]].push_back({h.tp_j[p], (int)p});
+  std::vector<int32_t> sm_m, sm_j, sm_p;
+  for (int e = 0; e < ne; ++e) {
+    const int ip = h.edge_tri[2 * e], im = h.edge_tri[2 * e + 1];
+    std::map<int, std::pair<int, int>> js;
+    for (auto& jp : by_i[ip]) js[jp.first].first = jp.second + 1;
+    for (auto& jp : by_i[im]) js[jp.first].second = jp.second + 1;
+    for (auto& kv : js) {
+      sm_m.push_back(e);
+      sm_j.push_back(kv.first);
+      sm_p.push_back(kv.second.first - 1);   // -1: that side does not touch j
+      sm_p.push_back(kv.second.second - 1);
+    }
+  }
+  const int nS = (int)sm_m.size();
+  DevBuf dm, dj, dp;
+  upload(dm, sm_m, s);
+  upload(dj, sm_j, s);
+  upload(dp, sm_p, s);
+  if (nS > 0) {
+    hipLaunchKernelGGL(k_sd_singular, dim3((unsigned)((nS + 3) / 4)), dim3(256), 0, s, m.dev(), R, sp,
+                       td.as<double>(), dm.as<int32_t>(), dj.as<int32_t>(), dp.as<int32_t>(), nS,
+                       m.tp_kind.as<int32_t>(), m.tp_ord.as<int32_t>(), ctx.ss[n_gauss].as<double>(),
+                       ctx.ss_off[n_gauss][0], ctx.ss_off[n_gauss][1], ctx.ss_off[n_gauss][2], ctx.ss_cnt[n_gauss][0],
+                       ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], W, ldw);
+    FOSB_LAUNCH_CHECK();
   }
   FOSB_HIP(hipStreamSynchronize(s));
 }

@@ -303,6 +303,8 @@ struct Level {
   int form = FOSB_FORM_EFIE;
   double eps_r = 1.0, mu_r = 1.0;
   DevBuf b;                    // PMCHWT: c128 [n][n_dirs]
+  int sd_field = -1;           // PMCHWT: field of the shape-derivative weights (-1: none built)
+  DevBuf Wsd;                  // PMCHWT: c128 [n_dirs][n][6 nt] shape-derivative weights (with nu)
   const void* lu() const { return precision == FOSB_PREC_FP64 ? Z : Zlow; }
 };
 
@@ -320,6 +322,11 @@ void efie_residual(Context& ctx, const Mesh& m, double k, int n_gauss, const c12
 // blocks K at k0 and k1 = k0 sqrt(eps_r mu_r), eta = sqrt(mu_r / eps_r)); synchronises the stream
 void assemble_pmchwt(Context& ctx, const Mesh& m, double k0, double eps_r, double mu_r, int n_gauss, c128* Z,
                      int64_t ldz);
+// W (2N x 6 nt, row stride ldw) of the dielectric shape derivative (mu_r = 1) for the first moment
+// in column dir of u (2N x ldu): r = W v for the amplitude v at the 6-point nodes (field: radial or
+// normal); synchronises the stream
+void sd_weights(Context& ctx, const Mesh& m, double k0, double eps_r, int field, const c128* u, int64_t ldu,
+                int64_t dir, int n_gauss, c128* W, int64_t ldw);
 // gemm.hip: C = beta*C + alpha*A*B, complex, row-major.
 template <typename T>
 void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,

@@ -75,9 +75,10 @@ _SIGS = {
     "fosb_level_create": (C.c_int, [_P, _P, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64, _I32, C.POINTER(Opts),
                                     C.POINTER(_P)]),
     "fosb_assemble_pmchwt": (C.c_int, [_P, _P, _D, _D, _D, C.POINTER(Opts), _P, _I64]),
-    "fosb_level_create_pmchwt": (C.c_int, [_P, _P, _D, _D, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64,
+    "fosb_level_create_pmchwt": (C.c_int, [_P, _P, _D, _D, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64, _I32,
                                            C.POINTER(Opts), C.POINTER(_P)]),
     "fosb_level_formulation": (C.c_int, [_P, C.POINTER(_I32), C.POINTER(_D), C.POINTER(_D)]),
+    "fosb_level_sd_weights": (C.c_int, [_P, _P, _I64, _P, _I64]),
     "fosb_level_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
     "fosb_level_workspace_size": (C.c_int, [_P, _I32, _I64, _I64, C.POINTER(_I64), C.POINTER(_I64)]),
     "fosb_level_certificate": (C.c_int, [_P, C.POINTER(_D), C.POINTER(_D)]),
@@ -357,9 +358,11 @@ class Level:
 
     @classmethod
     def pmchwt(cls, ctx: "Context", mesh: "Mesh", k0: float, eps_r: float, mu_r: float, Z, precision: int = FP64,
-               dirs=((0.0, 0.0, 1.0),), pols=((1.0, 0.0, 0.0),), opts: Opts | None = None, Zlow=None):
+               dirs=((0.0, 0.0, 1.0),), pols=((1.0, 0.0, 0.0),), opts: Opts | None = None, Zlow=None,
+               field: str | int | None = None):
         """fosb_level_create_pmchwt: a dielectric level on the 2N x 2N matrix Z
-        of assemble_pmchwt (factorised in place for FP64, kept for MIXED)."""
+        of assemble_pmchwt (factorised in place for FP64, kept for MIXED);
+        field ("radial" / "normal") also builds its shape-derivative weights."""
         import torch
         self = cls.__new__(cls)
         self.ctx, self.mesh, self.k, self.Z = ctx, mesh, float(k0), Z
@@ -375,10 +378,19 @@ class Level:
                                               _dev(Z, torch.complex128), Z.stride(0),
                                               _dev(Zlow, torch.complex64) if Zlow is not None else None,
                                               Zlow.stride(0) if Zlow is not None else 0, d.ctypes.data_as(_P),
-                                              p.ctypes.data_as(_P), d.shape[0], C.byref(opts) if opts else None,
-                                              C.byref(h)))
+                                              p.ctypes.data_as(_P), d.shape[0],
+                                              -1 if field is None else (FIELDS[field] if isinstance(field, str)
+                                                                        else int(field)),
+                                              C.byref(opts) if opts else None, C.byref(h)))
         self.h, self.n, self.n_dirs = h, n, d.shape[0]
         return self
+
+    def sd_weights(self, dir: int = 0):
+        """fosb_level_sd_weights: the dielectric shape-derivative weights (2N x 6 nt)."""
+        import torch
+        W = torch.empty((self.n, 6 * self.mesh.n_triangles), dtype=torch.complex128, device=self.ctx.torch_device)
+        _check(lib().fosb_level_sd_weights(self.ctx.h, self.h, dir, _dev(W), W.stride(0)))
+        return W
 
     def formulation(self) -> tuple[int, float, float]:
         """fosb_level_formulation: (FORM_EFIE or FORM_PMCHWT, eps_r, mu_r)."""

@@ -148,3 +148,87 @@ def test_rank_one_ct_full_ladder(fz):
     e = _rel(var[2], np.abs(Fm[:, 2]) ** 2)
     print(f"[gpu]   blocks vs u u^H {worst:.2e}, |F_z|^2 vs Mie {e:.2e}", flush=True)
     assert worst < 1e-9 and e < 0.02
+
+
+# ----------------------------------------------------------------------------- DE shape derivative
+SIG, ELL = 0.01, 0.5
+
+
+@pytest.fixture(scope="module")
+def oracle_sd():
+    """Oracle shape-derivative levels (radial field) on s = 1, 2 and their CT second moment."""
+    from oracle import pmchwt_sd
+    lv = {s: pmchwt_sd.Level(*workloads.icosphere(s), K0, EPS, np.array(D), np.array(P), field_kind="radial")
+          for s in (1, 2)}
+    xh = workloads.angles_xy(91)
+    V, blocks = pmchwt_sd.second_moment(lv, 1, 2, "gaussian", SIG, ELL, xh)
+    return lv, xh, V, blocks
+
+
+def _sd_level(fosb, ctx, torch, s, precision, field, opts=None):
+    V, F = workloads.icosphere(s)
+    m = fosb.Mesh(ctx, V, F)
+    Z = fosb.assemble_pmchwt(ctx, m, K0, EPS, MU)
+    return m, fosb.Level.pmchwt(ctx, m, K0, EPS, MU, Z, precision, dirs=[D], pols=[P], opts=opts, field=field)
+
+
+@pytest.mark.parametrize("s", [1, 2])
+def test_sd_weights_parity(fz, oracle_sd, s):
+    """The shape-derivative weights W (2N x 6 nt) entry by entry against the oracle."""
+    fosb, ctx, torch = fz
+    lv_o = oracle_sd[0][s]
+    print(f"[gpu] DE shape-derivative weights s={s}", flush=True)
+    m, lv = _sd_level(fosb, ctx, torch, s, fosb.FP64, "radial")
+    W = lv.sd_weights(0).cpu().numpy()
+    err = np.abs(W - lv_o.Wgt).max() / np.abs(lv_o.Wgt).max()
+    print(f"[gpu]   max entry error / max entry {err:.2e}, Frobenius {_rel(W, lv_o.Wgt):.2e}", flush=True)
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_sd_second_moment_parity(fz, oracle_sd, precision, tol):
+    """CT variance of the dielectric shape derivative (s = 1, 2, radial Gaussian
+    covariance) and its Sigma blocks against the oracle."""
+    fosb, ctx, torch = fz
+    _, xh, Vo, Bo = oracle_sd
+    prec = fosb.FP64 if precision == "fp64" else fosb.MIXED
+    opts = fosb.opts_default(ir_tol=1e-12, ir_max_sweeps=20)
+    lvs = [_sd_level(fosb, ctx, torch, s, prec, "radial", opts)[1] for s in (1, 2)]
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    blocks = fosb.correlation(ctx, lvs, 1, 2, cov, 0)
+    var = fosb.far_field_moments(ctx, lvs, 1, 2, blocks, xh).cpu().numpy().reshape(3, -1)
+    eb = max(_rel(b.cpu().numpy(), Bo[(a, c)]) for b, (a, c, _, _) in zip(blocks, fosb.ct_pairs(1, 2)))
+    ev = _rel(var, Vo)
+    print(f"[gpu] DE second moment {precision}: blocks {eb:.2e}, variance {ev:.2e}", flush=True)
+    assert eb < tol and ev < tol
+
+
+def test_sd_translation_and_breathing_on_the_ladder(fz):
+    """GPU only, s = 2, 3, 4 (2N up to 15360), normal field: the rigid-translation
+    covariance gives Var[F'_c] -> sigma^2 k0^2 |d - x|^2 |F_c|^2, and the
+    constant covariance gives sigma^2 |dF_c/da|^2 (radius derivative of the Mie
+    series); both approach their limits at second order."""
+    fosb, ctx, torch = fz
+    from oracle import mie
+    xh = workloads.angles_xy(91)
+    h = 1e-3
+    f = lambda a: mie.dielectric_far_field_oriented(K0, a, EPS, MU, D, P, xh)
+    dF = (-f(1 + 2 * h) + 8 * f(1 + h) - 8 * f(1 - h) + f(1 - 2 * h)) / (12 * h)
+    et, eb = [], []
+    for s in (2, 3, 4):
+        print(f"[gpu] DE shape derivative s={s}", flush=True)
+        m, lv = _sd_level(fosb, ctx, torch, s, fosb.FP64, "normal")
+        FF = fosb.far_field_matrix(ctx, lv, xh)
+        F = (FF @ lv.first_moment(0)).reshape(3, -1).cpu().numpy()
+        dd = np.sum((np.array(D)[None, :] - xh) ** 2, axis=1)[None, :]
+        for kind, ref, out in (("normal_dot", 0.01 ** 2 * K0 ** 2 * dd * np.abs(F) ** 2, et),
+                               ("constant", 0.01 ** 2 * np.abs(dF.T) ** 2, eb)):
+            blocks = fosb.correlation(ctx, [lv], s, s, fosb.make_cov(kind, 0.01, 1.0), 0)
+            var = fosb.far_field_moments(ctx, [lv], s, s, blocks, xh).cpu().numpy().reshape(3, -1)
+            out.append(_rel(var, ref))
+            del blocks
+        lv.close()
+        del FF
+    print(f"[gpu]   translation {et}, breathing {eb}", flush=True)
+    assert et[2] < 0.01 and et[0] / et[1] > 3.0 and et[1] / et[2] > 3.0
+    assert eb[2] < 0.02 and eb[0] / eb[1] > 3.0 and eb[1] / eb[2] > 3.0
