@@ -74,13 +74,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--progress", action="store_true", help="print a line after every stage of every step")
-    ap.add_argument("--workload", default="mixed_k5", choices=["mixed_k5", "superquad_k8", "ellipsoids", "dielectric"],
+    ap.add_argument("--workload", default="mixed_k5", choices=["mixed_k5", "superquad_k8", "ellipsoids", "dielectric",
+                                                            "dielectric_uq"],
                     help="mixed_k5: the k=5 icosphere ladder (default); superquad_k8: the superquadric ladder "
                          "|x|^4+|y|^4+|z|^4=1, k=8, to --max-level (s=6 does not fit both precisions' matrices "
                          "on one GPU); ellipsoids: 64 seeded ellipsoids x 16 "
                          "incidences, 3 levels each, Matern-3/2 covariance, all incidences solved together; "
                          "dielectric: the sphere experiment's rank-one DE second moment (PMCHWT, eps_r 2.1, k0 3) "
-                         "on the icosphere ladder s=2..--max-level")
+                         "on the icosphere ladder s=2..--max-level; dielectric_uq: the DE shape-uncertainty second "
+                         "moment (radial Gaussian covariance 0.01, 0.5) on the same ladder")
     ap.add_argument("--shapes", type=int, default=64, help="ellipsoids: number of shapes")
     ap.add_argument("--workers", type=int, default=4,
                     help="ellipsoids: shapes in flight at once (fosb_second_moment_batch); 0 = one call per shape")
@@ -556,7 +558,11 @@ def run_dielectric(args):
     p = e_z, rank-one right-hand side M2[f] = f (x) f over the CT index set
     (L0 = 2), far-field second moment at 1801 angles in the plane z = 0.  A step
     assembles every PMCHWT matrix, factors each level and solves its first
-    moment, forms and solves every CT pair and contracts the far field."""
+    moment, forms and solves every CT pair and contracts the far field.
+    dielectric_uq: the same ladder with the shape-uncertainty second moment
+    (radial Gaussian amplitude, sigma 0.01, ell 0.5): each level also builds
+    its shape-derivative weights, and each pair's right-hand side is
+    W_l1 K W_l2^H."""
     import torch
 
     import workloads
@@ -577,15 +583,18 @@ def run_dielectric(args):
     blocks = [torch.empty((2 * meshes[a - L0].n_edges, 2 * meshes[b - L0].n_edges), dtype=torch.complex128,
                           device=ctx.torch_device) for a, b, _, _ in pairs]
     opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
+    uq = args.workload == "dielectric_uq"
+    cov = fosb.make_cov("gaussian", 0.01, 0.5) if uq else None
 
     def step(prec):
         levels = []
         for m, z, zl in zip(meshes, Z, Zlow):
             fosb.assemble_pmchwt(ctx, m, K0, EPS, MU, opts, Z=z)
             levels.append(fosb.Level.pmchwt(ctx, m, K0, EPS, MU, z, prec, dirs=[D], pols=[P], opts=opts,
-                                            Zlow=zl if prec == fosb.MIXED else None))
+                                            Zlow=zl if prec == fosb.MIXED else None,
+                                            field="radial" if uq else None))
         st = fosb.Stats()
-        fosb.correlation(ctx, levels, L0, L, None, 0, blocks=blocks, stats=st)
+        fosb.correlation(ctx, levels, L0, L, cov, 0, blocks=blocks, stats=st)
         var = fosb.far_field_moments(ctx, levels, L0, L, blocks, xh)
         for lv in levels:
             lv.close()
@@ -621,15 +630,19 @@ def run_dielectric(args):
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": out[head]["seconds_per_step"] * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "c64+f64" if head == "mixed" else "c128", "data": "synthetic",
-            "config": {"workload": f"dielectric sphere experiment: unit icosphere s={L0}..{L} (PMCHWT, 2N up to "
-                                   f"{n_top}), eps_r 2.1, mu_r 1, k0 3, d = e_x, p = e_z, rank-one RHS f (x) f, "
-                                   f"L0={L0} L={L} ({npairs} pairs), 1801 angles in z = 0",
+            "config": {"workload": (f"dielectric sphere: unit icosphere s={L0}..{L} (PMCHWT, 2N up to {n_top}), "
+                                    f"eps_r 2.1, mu_r 1, k0 3, d = e_x, p = e_z, "
+                                    + ("shape-uncertainty second moment, radial Gaussian amplitude (0.01, 0.5)"
+                                       if uq else "rank-one RHS f (x) f (sphere experiment)")
+                                    + f", L0={L0} L={L} ({npairs} pairs), 1801 angles in z = 0"),
                        "precision": head, "ir_tol": args.ir_tol}}
     for pname, rec in out.items():
         line[pname] = {k: v for k, v in rec.items() if k not in ("var", "profile")}
     with open(os.path.join(ROOT, "tests", "golden", "dielectric_mie_k3.json")) as f:
         mie_f2 = np.asarray(json.load(f)["abs_F2"])   # |F_c|^2 of the Mie series, stored
     for pname, rec in out.items():   # discretisation + CT error against the mesh-free value
+        if uq:
+            break
         line[pname]["abs_F2_vs_mie_rel_err"] = float(np.linalg.norm(rec["var"] - mie_f2) / np.linalg.norm(mie_f2))
         line[pname]["abs_Fz2_vs_mie_rel_err"] = float(np.linalg.norm(rec["var"][2] - mie_f2[2]) /
                                                       np.linalg.norm(mie_f2[2]))
@@ -668,7 +681,7 @@ def main():
     if args.workload == "ellipsoids":
         run_batched(args)
         return
-    if args.workload == "dielectric":
+    if args.workload in ("dielectric", "dielectric_uq"):
         run_dielectric(args)
         return
     W = Workload(args.workload, args.max_level)

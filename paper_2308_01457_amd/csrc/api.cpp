@@ -459,6 +459,7 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
       L->qx.alloc((size_t)3 * Q * sizeof(double));
       quad_nodes(s, *mesh, L->qx.as<double>());
       L->Wsd.alloc((size_t)n_dirs * n * Q * sizeof(c128));
+      ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)n_dirs * (double)n * (double)Q);
       for (int64_t d = 0; d < n_dirs; ++d)
         sd_weights(c, *mesh, k, eps_r, sd_field, L->u.as<c128>(), n_dirs, d, o.n_gauss_singular,
                    L->Wsd.as<c128>() + d * n * Q, Q);
