@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--reassemble", action="store_true",
                     help="mixed path: the finest level keeps no complex128 copy of Z (Zlow assembled in FP64 bands, "
                          "refinement residuals with Z re-assembled band by band); needed for superquad_k8 at s=6")
+    ap.add_argument("--lowrank", action="store_true",
+                    help="dielectric_uq: the low-rank covariance route (pivoted Cholesky to 1e-10) with shape-derivative "
+                         "weights recomputed by source bands instead of stored")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the extra step through the step-by-step calls that times each stage")
     ap.add_argument("--save-var", default=None, metavar="NPZ",
@@ -581,7 +584,7 @@ def run_dielectric(args):
     Zlow = [torch.empty((2 * m.n_edges, 2 * m.n_edges), dtype=torch.complex64, device=ctx.torch_device)
             for m in meshes] if "mixed" in precs else [None] * len(meshes)
     blocks = [torch.empty((2 * meshes[a - L0].n_edges, 2 * meshes[b - L0].n_edges), dtype=torch.complex128,
-                          device=ctx.torch_device) for a, b, _, _ in pairs]
+                          device=ctx.torch_device) for a, b, _, _ in pairs] if not args.lowrank else None
     opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
     uq = args.workload == "dielectric_uq"
     cov = fosb.make_cov("gaussian", 0.01, 0.5) if uq else None
@@ -592,10 +595,16 @@ def run_dielectric(args):
             fosb.assemble_pmchwt(ctx, m, K0, EPS, MU, opts, Z=z)
             levels.append(fosb.Level.pmchwt(ctx, m, K0, EPS, MU, z, prec, dirs=[D], pols=[P], opts=opts,
                                             Zlow=zl if prec == fosb.MIXED else None,
-                                            field="radial" if uq else None))
+                                            field="radial" if uq else None, streamed=uq and args.lowrank))
         st = fosb.Stats()
-        fosb.correlation(ctx, levels, L0, L, cov, 0, blocks=blocks, stats=st)
-        var = fosb.far_field_moments(ctx, levels, L0, L, blocks, xh)
+        if uq and args.lowrank:
+            lr = fosb.LowRank(ctx, levels, cov, 8192, 1e-10)
+            var = lr.far_field_moments(L0, L, xh, stats=st)
+            step.rank = lr.rank
+            lr.close()
+        else:
+            fosb.correlation(ctx, levels, L0, L, cov, 0, blocks=blocks, stats=st)
+            var = fosb.far_field_moments(ctx, levels, L0, L, blocks, xh)
         for lv in levels:
             lv.close()
         return var, st
@@ -635,7 +644,11 @@ def run_dielectric(args):
                                     + ("shape-uncertainty second moment, radial Gaussian amplitude (0.01, 0.5)"
                                        if uq else "rank-one RHS f (x) f (sphere experiment)")
                                     + f", L0={L0} L={L} ({npairs} pairs), 1801 angles in z = 0"),
-                       "precision": head, "ir_tol": args.ir_tol}}
+                       "precision": head, "ir_tol": args.ir_tol,
+                       "route": "low-rank covariance (tol 1e-10), streamed weights" if (uq and args.lowrank) else
+                                ("dense covariance" if uq else "rank-one")}}
+    if uq and args.lowrank:
+        line["config"]["lowrank_rank"] = getattr(step, "rank", None)
     for pname, rec in out.items():
         line[pname] = {k: v for k, v in rec.items() if k not in ("var", "profile")}
     with open(os.path.join(ROOT, "tests", "golden", "dielectric_mie_k3.json")) as f:

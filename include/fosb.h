@@ -82,7 +82,10 @@ typedef enum fosb_cov_kind {
 /* How the scalar amplitude v_r becomes the normal velocity v_n. */
 typedef enum fosb_field {
   FOSB_FIELD_RADIAL = 0,   /* v = v_r x/|x|, v_n = v_r (x/|x|).n                   */
-  FOSB_FIELD_NORMAL = 1    /* v_n = v_r                                            */
+  FOSB_FIELD_NORMAL = 1,   /* v_n = v_r                                            */
+  FOSB_SD_STREAMED = 16    /* flag for fosb_level_create_pmchwt: keep no shape-
+                              derivative weights, recompute them by source bands
+                              where the low-rank route needs them               */
 } fosb_field;
 
 /* Boundary integral equation of a level. */
@@ -256,7 +259,11 @@ fosb_status fosb_level_create(fosb_context* ctx, const fosb_mesh* mesh, double k
  * quadratic interpolant on touching ones).  fosb_rhs_correlation and
  * fosb_correlation with a covariance then form C = W_l1 K W_l2^H (K at the
  * nodes of both levels; v_n = v_r (x/|x|).n for the radial field).  field = -1
- * builds none.  fosb_level_solve,
+ * builds none.  field | FOSB_SD_STREAMED stores no weights (2N x 6 nt x 16
+ * bytes per incidence, 121 GB at 2N = 61440): the low-rank route
+ * (fosb_lowrank_*) then forms W_l L_l from weights recomputed in source-triangle
+ * bands of at most 2 GiB, and the dense covariance route returns
+ * FOSB_E_UNSUPPORTED.  fosb_level_solve,
  * fosb_level_solve_adjoint, fosb_level_first_moment, fosb_two_sided_solve,
  * fosb_far_field_matrix and fosb_far_field_moments accept dielectric levels;
  * the entry points that need the shape-derivative weights of the PEC
@@ -269,7 +276,8 @@ fosb_status fosb_level_create_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, d
 /* Copies the shape-derivative weights of incidence dir of a dielectric level
  * built with field >= 0 into W (device, 2N x 6 nt complex128, row stride
  * ldw >= 6 nt; column 6 t + q is node q of triangle t, the radial factor
- * included).  FOSB_E_INVALID for a level without them. */
+ * included); a level with streamed weights computes them into W.
+ * FOSB_E_INVALID for a level without them. */
 fosb_status fosb_level_sd_weights(fosb_context* ctx, const fosb_level* level, int64_t dir, void* W, int64_t ldw);
 /* The level's formulation (fosb_formulation) and, for FOSB_FORM_PMCHWT, its
  * eps_r and mu_r (1 for EFIE levels).  Any output pointer may be NULL. */
@@ -390,6 +398,8 @@ fosb_status fosb_far_field_variance_adjoint(fosb_context* ctx, const fosb_level*
  * at max_rank columns.  The factor is exact on the pivots and bounded by the
  * remaining diagonal elsewhere.  FP64 throughout; device memory about
  * 8 max_rank (number of nodes) bytes.  The levels must outlive the handle.
+ * Dielectric levels built with shape-derivative weights (stored or streamed)
+ * take Wgt_l = their W (2N x 6 nt).
  * E_INVALID for bad arguments (max_rank 1..min(8192, nodes), 0 <= tol < 1). */
 fosb_status fosb_lowrank_create(fosb_context* ctx, const fosb_level* const* levels, int32_t n_levels,
                                 const fosb_cov* cov, int32_t max_rank, double tol, fosb_lowrank** out);

@@ -368,7 +368,8 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
                                                void* Z, int64_t ldz, void* Zlow, int64_t ldzlow, const double* dirs,
                                                const double* pols, int64_t n_dirs, int32_t field,
                                                const fosb_opts& o, int32_t form = FOSB_FORM_EFIE,
-                                               double eps_r = 1.0, double mu_r = 1.0, int32_t sd_field = -1) {
+                                               double eps_r = 1.0, double mu_r = 1.0, int32_t sd_field = -1,
+                                               bool sd_streamed = false) {
   hipStream_t s = c.stream;
   const bool pm = form == FOSB_FORM_PMCHWT;
   const int64_t n = pm ? 2 * mesh->h.ne : mesh->h.ne;
@@ -456,13 +457,16 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     if (sd_field >= 0) {  // shape-derivative weights per incidence, and the nodes for the covariance
       const int64_t Q = 6LL * mesh->h.nt;
       L->sd_field = sd_field;
+      L->sd_streamed = sd_streamed ? 1 : 0;
       L->qx.alloc((size_t)3 * Q * sizeof(double));
       quad_nodes(s, *mesh, L->qx.as<double>());
-      L->Wsd.alloc((size_t)n_dirs * n * Q * sizeof(c128));
-      ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)n_dirs * (double)n * (double)Q);
-      for (int64_t d = 0; d < n_dirs; ++d)
-        sd_weights(c, *mesh, k, eps_r, sd_field, L->u.as<c128>(), n_dirs, d, o.n_gauss_singular,
-                   L->Wsd.as<c128>() + d * n * Q, Q);
+      if (!sd_streamed) {
+        L->Wsd.alloc((size_t)n_dirs * n * Q * sizeof(c128));
+        ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)n_dirs * (double)n * (double)Q);
+        for (int64_t d = 0; d < n_dirs; ++d)
+          sd_weights(c, *mesh, k, eps_r, sd_field, L->u.as<c128>(), n_dirs, d, o.n_gauss_singular,
+                     L->Wsd.as<c128>() + d * n * Q, Q);
+      }
     }
     if (o.certify) L->kappa1 = L->z_one * inverse_norm1_estimate(c, *L);
     FOSB_HIP(hipStreamSynchronize(s));
@@ -597,9 +601,12 @@ static void check_cov(const fosb_cov* cov) {
 
 static void check_cov_for(const fosb_level* l, const fosb_cov* cov) {
   if (l->form == FOSB_FORM_PMCHWT && !cov) return;   // rank-one right-hand side
-  if (l->form == FOSB_FORM_PMCHWT)
+  if (l->form == FOSB_FORM_PMCHWT) {
     REQUIRE(l->sd_field >= 0, "a covariance right-hand side needs dielectric levels built with shape-derivative "
                               "weights (field >= 0)");
+    if (l->sd_streamed)
+      fail(FOSB_E_UNSUPPORTED, "levels with streamed shape-derivative weights take the low-rank route");
+  }
   check_cov(cov);
 }
 
@@ -965,16 +972,18 @@ fosb_status fosb_level_create_pmchwt(fosb_context* ctx, const fosb_mesh* mesh, d
   } else {
     REQUIRE(!Zlow, "FP64 precision takes no Zlow buffer");
   }
+  const bool streamed = field >= 0 && (field & FOSB_SD_STREAMED);
+  if (field >= 0) field &= ~FOSB_SD_STREAMED;
   REQUIRE(field == -1 || field == FOSB_FIELD_RADIAL || field == FOSB_FIELD_NORMAL, "unknown field %d", field);
   if (field >= 0 && mu_r != 1.0)
     fail(FOSB_E_UNSUPPORTED, "the dielectric shape-derivative weights are built for mu_r = 1");
   fosb_opts o = opts_or_default(opts);
   bind(*ctx);
-  const int64_t sd_bytes = field >= 0 ? n_dirs * n * 6LL * mesh->h.nt * 16 + 24LL * mesh->h.nt : 0;
+  const int64_t sd_bytes = field >= 0 ? (streamed ? 0 : n_dirs * n * 6LL * mesh->h.nt * 16) + 24LL * mesh->h.nt : 0;
   check_device_memory(*ctx, level_bytes(n, 0, precision, n_dirs) + solve_work_bytes(n, precision, n_dirs) + sd_bytes,
                       "the level");
   auto L = level_build(*ctx, mesh, k0, precision, Z, ldz, Zlow, ldzlow, dirs, pols, n_dirs, FOSB_FIELD_NORMAL, o,
-                       FOSB_FORM_PMCHWT, eps_r, mu_r, field);
+                       FOSB_FORM_PMCHWT, eps_r, mu_r, field, streamed);
   {
     std::lock_guard<std::mutex> lock(ctx->reg_mu);
     ctx->live_levels.insert(L.get());
@@ -992,7 +1001,11 @@ fosb_status fosb_level_sd_weights(fosb_context* ctx, const fosb_level* level, in
   const int64_t Q = 6LL * level->mesh->h.nt;
   if (ldw < Q) fail(FOSB_E_WORKSPACE, "ldw < 6 nt");
   bind(*ctx);
-  copy_c128(ctx->stream, level->Wsd.as<c128>() + dir * level->n * Q, Q, static_cast<c128*>(W), ldw, level->n, Q);
+  if (level->sd_streamed)
+    sd_weights(*ctx, *level->mesh, level->k, level->eps_r, level->sd_field, level->u.as<c128>(), level->n_dirs, dir,
+               level->opts.n_gauss_singular, static_cast<c128*>(W), ldw);
+  else
+    copy_c128(ctx->stream, level->Wsd.as<c128>() + dir * level->n * Q, Q, static_cast<c128*>(W), ldw, level->n, Q);
   FOSB_HIP(hipStreamSynchronize(ctx->stream));
   API_END
 }
@@ -1248,7 +1261,9 @@ fosb_status fosb_lowrank_create(fosb_context* ctx, const fosb_level* const* leve
   REQUIRE(ctx && levels && out, "NULL argument");
   *out = nullptr;
   REQUIRE(n_levels >= 1 && n_levels <= 64, "n_levels must be 1..64");
-  require_efie(levels, n_levels);
+  for (int32_t i = 0; i < n_levels; ++i)
+    REQUIRE(levels[i] && (levels[i]->form == FOSB_FORM_EFIE || levels[i]->sd_field >= 0),
+            "dielectric levels need shape-derivative weights (field >= 0) for the low-rank route");
   check_cov(cov);
   for (int32_t i = 0; i < n_levels; ++i) check_pair(ctx, levels[0], levels[i]);
   REQUIRE(std::isfinite(tol) && tol >= 0.0 && tol < 1.0, "tol must be in [0, 1)");
@@ -1323,11 +1338,48 @@ fosb_status fosb_lowrank_destroy(fosb_lowrank* lr) {
 }
 
 // Y (N x rank, row stride ldy) = Z^{-1} Wgt_dir L_l for ladder level i.
+// M (N x r) = Wsd_dir L_l for a dielectric level: one product with the stored
+// weights, or a sum over source-triangle bands of weights recomputed into a
+// band buffer (at most 2 GiB) when the level stores none.
+static void sd_times_factor(Context& c, const Level& l, int64_t dir, const double* Lr, int r, c128* M) {
+  hipStream_t s = c.stream;
+  const int64_t Q = 6LL * l.mesh->h.nt, n = l.n;
+  DevBuf Lc((size_t)Q * r * sizeof(c128));
+  real_to_c128(s, Lr, Q * r, Lc.as<c128>());
+  if (!l.sd_streamed) {
+    gemm<double>(c, n, r, Q, 1.0, l.Wsd.as<c128>() + dir * n * Q, Q, Lc.as<c128>(), r, 0.0, M, r);
+    return;
+  }
+  const int nt = (int)l.mesh->h.nt;
+  int w = (int)std::max<int64_t>(1, std::min<int64_t>(nt, ((int64_t)2 << 30) / (n * 6 * 16)));
+  SdPlan P;
+  sd_plan(c, *l.mesh, l.k, l.eps_r, l.u.as<c128>(), l.n_dirs, dir, P);
+  DevBuf Wb((size_t)n * 6 * w * sizeof(c128));
+  {
+    ProfScope prof(c, FOSB_K_RHS, 0.0, 16.0 * (double)n * (double)Q);
+    for (int j0 = 0; j0 < nt; j0 += w) {
+      const int j1 = std::min(nt, j0 + w);
+      const int64_t nb = 6LL * (j1 - j0);
+      sd_band(c, *l.mesh, P, l.k, l.eps_r, l.sd_field, l.opts.n_gauss_singular, j0, j1, Wb.as<c128>(), nb);
+      gemm<double>(c, n, r, nb, 1.0, Wb.as<c128>(), nb, Lc.as<c128>() + 6LL * j0 * r, r, j0 == 0 ? 0.0 : 1.0, M, r);
+    }
+  }
+  FOSB_HIP(hipStreamSynchronize(s));
+}
+
 static void lowrank_factor_impl(Context& c, const fosb_lowrank& lr, int32_t i, int64_t dir, c128* Y, int64_t ldy,
                                 fosb_stats* st) {
   const Level& l = *lr.levels[i];
   const int r = lr.rank;
   DevBuf Lr((size_t)6 * l.mesh->h.nt * r * sizeof(double));
+  if (l.form == FOSB_FORM_PMCHWT) {
+    DevBuf M((size_t)l.n * r * sizeof(c128));
+    lr_rows(c.stream, l, lr.L.as<double>(), lr.nc, lr.off[i], r, Lr.as<double>());
+    sd_times_factor(c, l, dir, Lr.as<double>(), r, M.as<c128>());
+    level_solve_inplace(c, l, M.as<c128>(), r, r, st);
+    copy_c128(c.stream, M.as<c128>(), r, Y, ldy, l.n, r);
+    return;
+  }
   if (ldy == r) {
     lr_rhs(c.stream, l, dir, lr.L.as<double>(), lr.nc, lr.off[i], r, Lr.as<double>(), Y);
     level_solve_inplace(c, l, Y, ldy, r, st);
@@ -1388,7 +1440,7 @@ fosb_status fosb_far_field_moments_lowrank(fosb_context* ctx, const fosb_lowrank
     const Level& l = *lr->levels[i];
     DevBuf Y((size_t)l.n * r * sizeof(c128)), FF((size_t)R * l.n * sizeof(c128));
     lowrank_factor_impl(*ctx, *lr, i, dir, Y.as<c128>(), r, stats);
-    far_field_matrix_kernel(s, *l.mesh, l.k, dx.as<double>(), n_a, FF.as<c128>());
+    level_far_field(s, l, dx.as<double>(), n_a, FF.as<c128>());
     G[i].alloc((size_t)R * r * sizeof(c128));
     gemm<double>(*ctx, R, r, l.n, 1.0, FF.as<c128>(), l.n, Y.as<c128>(), r, 0.0, G[i].as<c128>(), r);
   }

@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include <functional>
+#include <array>
 #include <map>
 
 #include "common.h"
@@ -1011,11 +1012,11 @@ __device__ __forceinline__ void sd_combine(const SdParams& sp, const SdAcc& A, d
 // One thread per (RWG row m, source node col = 6 j + q): the non-touching triangles of m
 // with the 6-point rule, the identity parts; stores W[m][col] and W[N+m][col].
 __global__ __launch_bounds__(256) void k_sd_regular(MeshDev md, Rule6 R, SdParams sp, const double* __restrict__ td,
-                                                    c128* __restrict__ W, int64_t ldw) {
-  const int64_t Q = 6LL * md.nt;
-  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+                                                    int64_t col0, int64_t ncol, c128* __restrict__ W, int64_t ldw) {
+  const int64_t lc = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int m = blockIdx.y;
-  if (col >= Q || m >= md.ne) return;
+  if (lc >= ncol || m >= md.ne) return;
+  const int64_t col = col0 + lc;
   const int j = (int)(col / 6), q = (int)(col % 6);
   const int nt = md.nt, ne = md.ne;
   double Pj[3][3], cj[3];
@@ -1079,8 +1080,8 @@ __global__ __launch_bounds__(256) void k_sd_regular(MeshDev md, Rule6 R, SdParam
   }
   double WEr, WEi, WHr, WHi;
   sd_combine(sp, A, tj[0], tj[1], IEr, IEi, IHr, IHi, nu, WEr, WEi, WHr, WHi);
-  W[(int64_t)m * ldw + col] = c128{WEr, WEi};
-  W[(int64_t)(ne + m) * ldw + col] = c128{WHr, WHi};
+  W[(int64_t)m * ldw + lc] = c128{WEr, WEi};
+  W[(int64_t)(ne + m) * ldw + lc] = c128{WHr, WHi};
 }
 
 // One wavefront per (RWG row m, source triangle j) with a triangle of m touching j:
@@ -1088,14 +1089,14 @@ __global__ __launch_bounds__(256) void k_sd_regular(MeshDev md, Rule6 R, SdParam
 // adds to W[m][6 j + q] and W[N+m][6 j + q], q = 0..5.
 __global__ __launch_bounds__(256) void k_sd_singular(MeshDev md, Rule6 R, SdParams sp, const double* __restrict__ td,
                                                      const int32_t* __restrict__ sm_m, const int32_t* __restrict__ sm_j,
-                                                     const int32_t* __restrict__ sm_p, int nS,
+                                                     const int32_t* __restrict__ sm_p, int e0, int nS, int64_t col0,
                                                      const int32_t* __restrict__ tp_kind,
                                                      const int32_t* __restrict__ tp_ord, const double* __restrict__ ss,
                                                      int off0, int off1, int off2, int cnt0, int cnt1, int cnt2,
                                                      c128* __restrict__ W, int64_t ldw) {
-  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int e = e0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (e >= nS) return;
+  if (e >= e0 + nS) return;
   const int m = sm_m[e], j = sm_j[e];
   const int nt = md.nt, ne = md.ne;
   double Pj[3][3], cj[3];
@@ -1192,7 +1193,7 @@ __global__ __launch_bounds__(256) void k_sd_singular(MeshDev md, Rule6 R, SdPara
       for (int c = 0; c < 3; ++c) y[c] = R.l[q][0] * Pj[0][c] + R.l[q][1] * Pj[1][c] + R.l[q][2] * Pj[2][c];
       nu = (y[0] * nj[0] + y[1] * nj[1] + y[2] * nj[2]) * rsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     }
-    const int64_t col = 6LL * j + q;
+    const int64_t col = 6LL * j + q - col0;
     double WEr, WEi, WHr, WHi;
     sd_combine(sp, Aq, tj[0], tj[1], 0.0, 0.0, 0.0, 0.0, nu, WEr, WEi, WHr, WHi);
     c128* w0 = W + (int64_t)m * ldw + col;
@@ -1235,11 +1236,50 @@ static void lagrange6(double out[6][6]) {
     for (int c = 0; c < 6; ++c) out[r][c] = A[r][6 + c];
 }
 
-void sd_weights(Context& ctx, const Mesh& m, double k0, double eps_r, int field, const c128* u, int64_t ldu,
-                int64_t dir, int n_gauss, c128* W, int64_t ldw) {
+void sd_plan(Context& ctx, const Mesh& m, double k0, double eps_r, const c128* u, int64_t ldu, int64_t dir,
+             SdPlan& P) {
   hipStream_t s = ctx.stream;
   const MeshHost& h = m.h;
   const int nt = (int)h.nt, ne = (int)h.ne;
+  P.td.alloc((size_t)8 * nt * sizeof(double));
+  hipLaunchKernelGGL(k_sd_tri_data, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, m.dev(), u, ldu, dir, k0,
+                     eps_r, P.td.as<double>());
+  FOSB_LAUNCH_CHECK();
+  // (row m, source triangle j) with a triangle of m touching j, sorted by j, and the
+  // touching-pair index of each side (-1: that side does not touch j)
+  std::vector<std::vector<std::pair<int, int>>> by_i(nt);
+  for (size_t p = 0; p < h.tp_i.size(); ++p) by_i[h.tp_i[p]].push_back({h.tp_j[p], (int)p});
+  std::vector<std::vector<std::array<int32_t, 3>>> by_j(nt);   // j -> (m, p+, p-)
+  for (int e = 0; e < ne; ++e) {
+    const int ip = h.edge_tri[2 * e], im = h.edge_tri[2 * e + 1];
+    std::map<int, std::pair<int, int>> js;
+    for (auto& jp : by_i[ip]) js[jp.first].first = jp.second + 1;
+    for (auto& jp : by_i[im]) js[jp.first].second = jp.second + 1;
+    for (auto& kv : js) by_j[kv.first].push_back({e, kv.second.first - 1, kv.second.second - 1});
+  }
+  std::vector<int32_t> sm_m, sm_j, sm_p;
+  P.jbeg.assign(nt + 1, 0);
+  for (int j = 0; j < nt; ++j) {
+    P.jbeg[j] = (int64_t)sm_m.size();
+    for (auto& r : by_j[j]) {
+      sm_m.push_back(r[0]);
+      sm_j.push_back(j);
+      sm_p.push_back(r[1]);
+      sm_p.push_back(r[2]);
+    }
+  }
+  P.jbeg[nt] = (int64_t)sm_m.size();
+  upload(P.dm, sm_m, s);
+  upload(P.dj, sm_j, s);
+  upload(P.dp, sm_p, s);
+  FOSB_HIP(hipStreamSynchronize(s));
+}
+
+void sd_band(Context& ctx, const Mesh& m, const SdPlan& P, double k0, double eps_r, int field, int n_gauss, int j0,
+             int j1, c128* W, int64_t ldw) {
+  hipStream_t s = ctx.stream;
+  const int ne = (int)m.h.ne;
+  if (j1 <= j0) return;
   ensure_ss_table(ctx, n_gauss);
   Rule6 R;
   rule6(R.l, R.w);
@@ -1250,44 +1290,27 @@ void sd_weights(Context& ctx, const Mesh& m, double k0, double eps_r, int field,
   sp.cbi = k0 * (1.0 - eps_r);
   sp.field = field;
   lagrange6(sp.lag);
-  DevBuf td((size_t)8 * nt * sizeof(double));
-  hipLaunchKernelGGL(k_sd_tri_data, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, m.dev(), u, ldu, dir, k0,
-                     eps_r, td.as<double>());
+  const int64_t col0 = 6LL * j0, ncol = 6LL * (j1 - j0);
+  dim3 g1((unsigned)((ncol + 255) / 256), (unsigned)ne);
+  hipLaunchKernelGGL(k_sd_regular, g1, dim3(256), 0, s, m.dev(), R, sp, P.td.as<double>(), col0, ncol, W, ldw);
   FOSB_LAUNCH_CHECK();
-  const int64_t Q = 6LL * nt;
-  dim3 g1((unsigned)((Q + 255) / 256), (unsigned)ne);
-  hipLaunchKernelGGL(k_sd_regular, g1, dim3(256), 0, s, m.dev(), R, sp, td.as<double>(), W, ldw);
-  FOSB_LAUNCH_CHECK();
-  // (row m, source triangle j) with a triangle of m touching j, and the touching-pair index per side
-  std::vector<std::vector<std::pair<int, int>>> by_i(nt);   // i -> (j, pair index)
-  for (size_t p = 0; p < h.tp_i.size(); ++p) by_i[h.tp_i[p]].push_back({h.tp_j[p], (int)p});
-  std::vector<int32_t> sm_m, sm_j, sm_p;
-  for (int e = 0; e < ne; ++e) {
-    const int ip = h.edge_tri[2 * e], im = h.edge_tri[2 * e + 1];
-    std::map<int, std::pair<int, int>> js;
-    for (auto& jp : by_i[ip]) js[jp.first].first = jp.second + 1;
-    for (auto& jp : by_i[im]) js[jp.first].second = jp.second + 1;
-    for (auto& kv : js) {
-      sm_m.push_back(e);
-      sm_j.push_back(kv.first);
-      sm_p.push_back(kv.second.first - 1);   // -1: that side does not touch j
-      sm_p.push_back(kv.second.second - 1);
-    }
-  }
-  const int nS = (int)sm_m.size();
-  DevBuf dm, dj, dp;
-  upload(dm, sm_m, s);
-  upload(dj, sm_j, s);
-  upload(dp, sm_p, s);
+  const int e0 = (int)P.jbeg[j0], nS = (int)(P.jbeg[j1] - P.jbeg[j0]);
   if (nS > 0) {
     hipLaunchKernelGGL(k_sd_singular, dim3((unsigned)((nS + 3) / 4)), dim3(256), 0, s, m.dev(), R, sp,
-                       td.as<double>(), dm.as<int32_t>(), dj.as<int32_t>(), dp.as<int32_t>(), nS,
+                       P.td.as<double>(), P.dm.as<int32_t>(), P.dj.as<int32_t>(), P.dp.as<int32_t>(), e0, nS, col0,
                        m.tp_kind.as<int32_t>(), m.tp_ord.as<int32_t>(), ctx.ss[n_gauss].as<double>(),
                        ctx.ss_off[n_gauss][0], ctx.ss_off[n_gauss][1], ctx.ss_off[n_gauss][2], ctx.ss_cnt[n_gauss][0],
                        ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], W, ldw);
     FOSB_LAUNCH_CHECK();
   }
-  FOSB_HIP(hipStreamSynchronize(s));
+}
+
+void sd_weights(Context& ctx, const Mesh& m, double k0, double eps_r, int field, const c128* u, int64_t ldu,
+                int64_t dir, int n_gauss, c128* W, int64_t ldw) {
+  SdPlan P;
+  sd_plan(ctx, m, k0, eps_r, u, ldu, dir, P);
+  sd_band(ctx, m, P, k0, eps_r, field, n_gauss, 0, (int)m.h.nt, W, ldw);
+  FOSB_HIP(hipStreamSynchronize(ctx.stream));
 }
 
 void efie_residual(Context& ctx, const Mesh& m, double k, int n_gauss, const c128* X, int64_t ldx, int64_t nrhs,

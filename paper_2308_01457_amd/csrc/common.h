@@ -304,6 +304,7 @@ struct Level {
   double eps_r = 1.0, mu_r = 1.0;
   DevBuf b;                    // PMCHWT: c128 [n][n_dirs]
   int sd_field = -1;           // PMCHWT: field of the shape-derivative weights (-1: none built)
+  int sd_streamed = 0;         // PMCHWT: weights recomputed by source bands when used, none stored
   DevBuf Wsd;                  // PMCHWT: c128 [n_dirs][n][6 nt] shape-derivative weights (with nu)
   const void* lu() const { return precision == FOSB_PREC_FP64 ? Z : Zlow; }
 };
@@ -327,6 +328,17 @@ void assemble_pmchwt(Context& ctx, const Mesh& m, double k0, double eps_r, doubl
 // normal); synchronises the stream
 void sd_weights(Context& ctx, const Mesh& m, double k0, double eps_r, int field, const c128* u, int64_t ldu,
                 int64_t dir, int n_gauss, c128* W, int64_t ldw);
+// The same weights by source-triangle bands: sd_plan once per (level, incidence) (per-triangle data
+// and the touching (row, triangle) list sorted by triangle), then sd_band writes columns
+// [6 j0, 6 j1) into W (2N x 6 (j1 - j0), row stride ldw), enqueued on the stream.
+struct SdPlan {
+  DevBuf td, dm, dj, dp;
+  std::vector<int64_t> jbeg;
+};
+void sd_plan(Context& ctx, const Mesh& m, double k0, double eps_r, const c128* u, int64_t ldu, int64_t dir,
+             SdPlan& P);
+void sd_band(Context& ctx, const Mesh& m, const SdPlan& P, double k0, double eps_r, int field, int n_gauss, int j0,
+             int j1, c128* W, int64_t ldw);
 // gemm.hip: C = beta*C + alpha*A*B, complex, row-major.
 template <typename T>
 void gemm(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const cplx<T>* A, int64_t lda,
@@ -461,6 +473,9 @@ void lr_pivot(hipStream_t s, const double* d, int64_t nc, double tie, double* ou
 void lr_column(hipStream_t s, const double* Xc, const double* Nc, int64_t nc, const fosb_cov& cov, double* L, int j,
                int64_t p, double dp, double* d);
 // M (N x rank) = Wgt_dir L_l with L_l the factor's rows [off, off + 6 nt) (Lr: scratch, 6 nt x rank doubles)
+// the level's rows of the factor, node-major (Q x rank); a real array widened to complex128
+void lr_rows(hipStream_t s, const Level& l, const double* L, int64_t nc, int64_t off, int rank, double* Lr);
+void real_to_c128(hipStream_t s, const double* a, int64_t n, c128* b);
 void lr_rhs(hipStream_t s, const Level& l, int64_t dir, const double* L, int64_t nc, int64_t off, int rank,
             double* Lr, c128* M);
 

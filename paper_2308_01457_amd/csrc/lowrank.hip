@@ -165,6 +165,25 @@ __global__ __launch_bounds__(256) void k_lr_rhs(const int32_t* __restrict__ edge
   M[m * rank + k] = c128{ar, ai};
 }
 
+// Lc (n x rank, complex128) = Lr (real)
+__global__ void k_real_to_c128(const double* __restrict__ a, int64_t n, c128* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = c128{a[i], 0.0};
+}
+
+void lr_rows(hipStream_t s, const Level& l, const double* L, int64_t nc, int64_t off, int rank, double* Lr) {
+  const int64_t Q = 6LL * l.mesh->h.nt;
+  dim3 g((unsigned)((Q + 31) / 32), (unsigned)((rank + 31) / 32));
+  hipLaunchKernelGGL(k_lr_rows, g, dim3(256), 0, s, L, nc, off, Q, rank, Lr);
+  FOSB_LAUNCH_CHECK();
+}
+
+void real_to_c128(hipStream_t s, const double* a, int64_t n, c128* b) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_real_to_c128, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, n, b);
+  FOSB_LAUNCH_CHECK();
+}
+
 void lr_rhs(hipStream_t s, const Level& l, int64_t dir, const double* L, int64_t nc, int64_t off, int rank,
             double* Lr, c128* M) {
   const Mesh& m = *l.mesh;

@@ -26,6 +26,7 @@ STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SINGULAR", 3: "E_NOCONV", 4: "E_WORKSPA
 COV_KINDS = {"gaussian": GAUSSIAN, "matern32": MATERN32, "constant": CONSTANT, "normal_dot": NORMAL_DOT}
 FIELDS = {"radial": RADIAL, "normal": NORMAL}
 FORM_EFIE, FORM_PMCHWT = 0, 1
+SD_STREAMED = 16
 
 
 class FosbError(RuntimeError):
@@ -359,10 +360,12 @@ class Level:
     @classmethod
     def pmchwt(cls, ctx: "Context", mesh: "Mesh", k0: float, eps_r: float, mu_r: float, Z, precision: int = FP64,
                dirs=((0.0, 0.0, 1.0),), pols=((1.0, 0.0, 0.0),), opts: Opts | None = None, Zlow=None,
-               field: str | int | None = None):
+               field: str | int | None = None, streamed: bool = False):
         """fosb_level_create_pmchwt: a dielectric level on the 2N x 2N matrix Z
         of assemble_pmchwt (factorised in place for FP64, kept for MIXED);
-        field ("radial" / "normal") also builds its shape-derivative weights."""
+        field ("radial" / "normal") also builds its shape-derivative weights,
+        or, with streamed, recomputes them by source bands where the low-rank
+        route needs them."""
         import torch
         self = cls.__new__(cls)
         self.ctx, self.mesh, self.k, self.Z = ctx, mesh, float(k0), Z
@@ -380,7 +383,8 @@ class Level:
                                               Zlow.stride(0) if Zlow is not None else 0, d.ctypes.data_as(_P),
                                               p.ctypes.data_as(_P), d.shape[0],
                                               -1 if field is None else (FIELDS[field] if isinstance(field, str)
-                                                                        else int(field)),
+                                                                        else int(field)) | (SD_STREAMED if streamed
+                                                                                            else 0),
                                               C.byref(opts) if opts else None, C.byref(h)))
         self.h, self.n, self.n_dirs = h, n, d.shape[0]
         return self

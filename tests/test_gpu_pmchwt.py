@@ -232,3 +232,37 @@ def test_sd_translation_and_breathing_on_the_ladder(fz):
     print(f"[gpu]   translation {et}, breathing {eb}", flush=True)
     assert et[2] < 0.01 and et[0] / et[1] > 3.0 and et[1] / et[2] > 3.0
     assert eb[2] < 0.02 and eb[0] / eb[1] > 3.0 and eb[1] / eb[2] > 3.0
+
+
+def test_sd_lowrank_route(fz):
+    """Dielectric shape derivative through the low-rank covariance (s = 2, 3):
+    stored and streamed weights give the same factor and variance, and the
+    low-rank variance matches the dense covariance route."""
+    fosb, ctx, torch = fz
+    xh = workloads.angles_xy(91)
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    print("[gpu] DE low-rank route s=2..3", flush=True)
+    stored = [_sd_level(fosb, ctx, torch, s, fosb.FP64, "radial")[1] for s in (2, 3)]
+    streamed = []
+    for s in (2, 3):
+        V, F = workloads.icosphere(s)
+        m = fosb.Mesh(ctx, V, F)
+        Z = fosb.assemble_pmchwt(ctx, m, K0, EPS, MU)
+        streamed.append(fosb.Level.pmchwt(ctx, m, K0, EPS, MU, Z, fosb.FP64, dirs=[D], pols=[P], field="radial",
+                                          streamed=True))
+    ew = _rel(streamed[1].sd_weights(0).cpu().numpy(), stored[1].sd_weights(0).cpu().numpy())
+    blocks = fosb.correlation(ctx, stored, 2, 3, cov, 0)
+    Vd = fosb.far_field_moments(ctx, stored, 2, 3, blocks, xh).cpu().numpy()
+    lr1 = fosb.LowRank(ctx, stored, cov, 4000, 1e-11)
+    lr2 = fosb.LowRank(ctx, streamed, cov, 4000, 1e-11)
+    V1 = lr1.far_field_moments(2, 3, xh).cpu().numpy()
+    V2 = lr2.far_field_moments(2, 3, xh).cpu().numpy()
+    ey = _rel(lr2.factor(1).cpu().numpy(), lr1.factor(1).cpu().numpy())
+    e12, ed = _rel(V2, V1), _rel(V1, Vd)
+    print(f"[gpu]   rank {lr1.rank}; streamed vs stored: weights {ew:.1e}, factor {ey:.1e}, variance {e12:.1e}; "
+          f"low-rank vs dense {ed:.1e}", flush=True)
+    assert ew < 1e-15 and ey < 1e-12 and e12 < 1e-12 and ed < 1e-7
+    with pytest.raises(fosb.FosbError):
+        fosb.correlation(ctx, streamed, 2, 3, cov, 0)
+    lr1.close()
+    lr2.close()
