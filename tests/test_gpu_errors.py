@@ -124,3 +124,54 @@ def test_phase_range_is_enforced(fz):
     assert e.value.name == "E_INVALID"
     assert "bounding-box" in fosb.lib().fosb_last_error().decode()
     assert torch.isfinite(fosb.assemble(ctx, m, 1.0e4).abs()).all()
+
+
+def test_dielectric_argument_errors(fz):
+    """The dielectric entry points reject bad materials, mixed formulations and
+    requests that need data the levels do not have, with the context usable."""
+    fosb, ctx, torch = fz
+    m = fosb.Mesh(ctx, *workloads.icosphere(1))
+    n2 = 2 * m.n_edges
+    print("[gpu] dielectric argument errors", flush=True)
+    for eps, mu in ((0.0, 1.0), (-2.0, 1.0), (2.0, float("nan"))):
+        with pytest.raises(fosb.FosbError) as e:
+            fosb.assemble_pmchwt(ctx, m, 3.0, eps, mu)
+        assert e.value.name == "E_INVALID"
+    Zs = torch.empty((n2, n2 - 1), dtype=torch.complex128, device=ctx.torch_device)
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.assemble_pmchwt(ctx, m, 3.0, 2.1, 1.0, Z=Zs)
+    assert e.value.name == "E_WORKSPACE"
+    # shape-derivative weights are built for a non-magnetic interior only
+    Z = fosb.assemble_pmchwt(ctx, m, 3.0, 2.1, 1.5)
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.Level.pmchwt(ctx, m, 3.0, 2.1, 1.5, Z, fosb.FP64, field="radial")
+    assert e.value.name == "E_UNSUPPORTED"
+    # levels without weights: no covariance right-hand side, no low-rank route
+    Z = fosb.assemble_pmchwt(ctx, m, 3.0, 2.1, 1.0)
+    lv = fosb.Level.pmchwt(ctx, m, 3.0, 2.1, 1.0, Z, fosb.FP64)
+    cov = fosb.make_cov("gaussian", 0.01, 0.5)
+    for call in (lambda: fosb.rhs_correlation(ctx, lv, lv, cov),
+                 lambda: fosb.LowRank(ctx, [lv], cov, 100, 1e-8)):
+        with pytest.raises(fosb.FosbError) as e:
+            call()
+        assert e.value.name == "E_INVALID"
+    with pytest.raises(fosb.FosbError) as e:
+        lv.sd_weights(0)
+    assert e.value.name == "E_INVALID"
+    # PEC-only entry points
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.near_field_matrix(ctx, lv, np.array([[0.0, 0.0, 2.0]]))
+    assert e.value.name == "E_UNSUPPORTED"
+    # an EFIE level and a dielectric level do not pair; an EFIE level needs a covariance
+    Ze = fosb.assemble(ctx, m, 3.0)
+    le = fosb.Level(ctx, m, 3.0, Ze, fosb.FP64)
+    C = torch.empty((lv.n, le.n), dtype=torch.complex128, device=ctx.torch_device)
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.two_sided_solve(ctx, lv, le, C)
+    assert e.value.name == "E_INVALID"
+    with pytest.raises(fosb.FosbError) as e:
+        fosb.rhs_correlation(ctx, le, le, None)
+    assert e.value.name == "E_INVALID"
+    # still usable: the rank-one right-hand side of the dielectric level
+    C1 = fosb.rhs_correlation(ctx, lv, lv, None)
+    assert torch.isfinite(C1.abs()).all()
