@@ -36,13 +36,15 @@ if ROOT not in sys.path:
 PEAK = {"fp64": 78.6, "mixed": 157.3}          # dense MFMA TFLOP/s (FP64, FP32)
 HBM_PEAK = 8000.0                               # GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_gemm_f32_mixed_k5.txt")
-GEMM_SRC = os.path.join(ROOT, "paper_2308_01457_amd", "csrc", "gemm.hip")
+# the kernel's source and the factorisation that sets its launch shapes
+GEMM_SRC = [os.path.join(ROOT, "paper_2308_01457_amd", "csrc", f) for f in ("gemm.hip", "lu.hip")]
 
 
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, or None when it is missing or the kernel source has
-    changed since the counters were taken."""
+    counter summary, or None when it is missing or the kernel's source or the
+    factorisation that shapes its launches has changed since the counters were
+    taken."""
     import hashlib
     try:
         kv = {}
@@ -50,7 +52,7 @@ def measured_traffic():
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in GEMM_SRC)).hexdigest()
         if kv.get("source_sha256") != sha:
             return None
         return float(kv["traffic_bytes_per_launch"])
@@ -103,6 +105,8 @@ def parse():
     ap.add_argument("--lowrank", action="store_true",
                     help="dielectric_uq: the low-rank covariance route (pivoted Cholesky to 1e-10) with shape-derivative "
                          "weights recomputed by source bands instead of stored")
+    ap.add_argument("--lu-pivoting", type=int, default=0, choices=[0, 1],
+                    help="mixed levels: 0 lets symmetric EFIE matrices skip pivoting, 1 always pivots")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the extra step through the step-by-step calls that times each stage")
     ap.add_argument("--save-var", default=None, metavar="NPZ",
@@ -220,10 +224,20 @@ def assembly_point_pairs(W, n_gauss=5):
     return int(reg), int(sing)
 
 
-def stage_report(t, lu_f, solve_f, pname, sweeps):
+def lu_flops_as_factored(levels):
+    """Flops of the factorisations the levels kept: (8/3) N^3 for LU with
+    partial pivoting, (4/3) N^3 for the symmetric factorisation (trailing
+    updates of the lower triangle only)."""
+    from paper_2308_01457_amd import fosb
+    kinds = {lv.n: lv.factorization() for lv in levels}
+    flop = sum((4.0 if k == fosb.FACTOR_SYM else 8.0) / 3.0 * n ** 3 for n, k in kinds.items())
+    return flop, {str(n): ("symmetric" if k == fosb.FACTOR_SYM else "pivoted") for n, k in sorted(kinds.items())}
+
+
+def stage_report(t, lu_f, solve_f, pname, sweeps, lu_kinds=None):
     """Seconds per stage of one step through the step-by-step calls, and each
-    compute stage against its MFMA bound.  LU: (8/3) N^3 per level at the
-    factor's precision.  Pairs: the two-sided solves, 8 N1 N2 (N1 + N2) per pair;
+    compute stage against its MFMA bound.  LU: the flops of the factorisations
+    kept (lu_flops_as_factored) at the factor's precision.  Pairs: the two-sided solves, 8 N1 N2 (N1 + N2) per pair;
     on the mixed path each refinement sweep adds one FP64 residual product and
     one FP32 correction solve of the same flop count, so the stage executes
     (1 + sweeps) x that in FP32 and sweeps x that in FP64."""
@@ -237,8 +251,9 @@ def stage_report(t, lu_f, solve_f, pname, sweeps):
         lu_peak = p64
     bound = f32 / p32 + f64 / p64
     return {"assemble_s": asm, "far_field_s": ff,
-            "lu_first_moment": {"seconds": lu, "algorithmic_flop": lu_f, "achieved_tflops": lu_f / lu / 1e12,
-                                "peak_tflops": lu_peak / 1e12, "frac": lu_f / lu_peak / lu},
+            "lu_first_moment": {"seconds": lu, "algorithmic_flop": lu_f, "factorisation_by_n": lu_kinds,
+                                "achieved_tflops": lu_f / lu / 1e12, "peak_tflops": lu_peak / 1e12,
+                                "frac": lu_f / lu_peak / lu},
             "pairs": {"seconds": pairs, "algorithmic_flop": solve_f, "refinement_sweeps": sweeps,
                       "executed_flop_fp32": f32, "executed_flop_fp64": f64, "bound_seconds_at_peaks": bound,
                       "frac": bound / pairs}}
@@ -254,7 +269,7 @@ def run_gpu(args, W):
         with open(args.tune_load) as f:
             fosb.autotune_load(ctx, {int(k): v for k, v in json.load(f).items()})
     cov = fosb.make_cov(W.w.cov_kind, W.w.sigma, W.w.ell)
-    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
+    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10, lu_pivoting=args.lu_pivoting)
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     if args.reassemble and precs != ["mixed"]:
         raise SystemExit("--reassemble applies to the mixed path only (use --precision mixed)")
@@ -306,7 +321,6 @@ def run_gpu(args, W):
             stage /= max(1, args.steps)
             rec["stage_s"] = {"assemble": stage[0], "lu_first_moment": stage[1], "pairs": stage[2],
                               "far_field": stage[3]}
-            rec["lu_tflops"] = lu_f / stage[1] / 1e12
         if prof_timed:
             rec["profile"] = {k: (v[0] // max(1, args.steps), v[1] / max(1, args.steps), v[2] / max(1, args.steps),
                                   v[3] / max(1, args.steps)) for k, v in fosb.profile_read(ctx).items()}
@@ -324,12 +338,13 @@ def run_gpu(args, W):
             torch.cuda.synchronize()
             _, blk, lvs, sst = one_step(fosb, torch, ctx, W, meshes, Z, Zlow, prec, cov, opts, ev)
             torch.cuda.synchronize()
+            lu_used, kinds = lu_flops_as_factored(lvs)
             del blk, lvs
-            rec["stages"] = stage_report([ev[j].elapsed_time(ev[j + 1]) * 1e-3 for j in range(4)], lu_f, solve_f,
-                                         pname, int(sst.ir_sweeps))
+            rec["stages"] = stage_report([ev[j].elapsed_time(ev[j + 1]) * 1e-3 for j in range(4)], lu_used,
+                                         solve_f, pname, int(sst.ir_sweeps), kinds)
         if args.certify:
             log(f"[bench] {pname}: certified step")
-            copts = fosb.opts_default(ir_tol=1e-13, ir_max_sweeps=20, certify=1)
+            copts = fosb.opts_default(ir_tol=1e-13, ir_max_sweeps=20, certify=1, lu_pivoting=args.lu_pivoting)
             if args.schedule == "concurrent":
                 _, cst = one_step_concurrent(fosb, ctx, W, meshes, Z, Zlow, prec, cov, copts, blocks)
             else:
@@ -367,7 +382,7 @@ def run_batched(args):
     meshes = [[fosb.Mesh(ctx, V, F) for V, F in w.meshes] for w in shapes]
     N = [[m.n_edges for m in ms] for ms in meshes]
     pairs = fosb.ct_pairs(0, 2)
-    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
+    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10, lu_pivoting=args.lu_pivoting)
     npairs = len(pairs) * 16 * len(shapes)
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     out = {}
@@ -585,7 +600,7 @@ def run_dielectric(args):
             for m in meshes] if "mixed" in precs else [None] * len(meshes)
     blocks = [torch.empty((2 * meshes[a - L0].n_edges, 2 * meshes[b - L0].n_edges), dtype=torch.complex128,
                           device=ctx.torch_device) for a, b, _, _ in pairs] if not args.lowrank else None
-    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10)
+    opts = fosb.opts_default(ir_tol=args.ir_tol, ir_max_sweeps=10, lu_pivoting=args.lu_pivoting)
     uq = args.workload == "dielectric_uq"
     cov = fosb.make_cov("gaussian", 0.01, 0.5) if uq else None
 
@@ -716,7 +731,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": W.describe(npairs),
                    "precision": head, "schedule": args.schedule, "ir_tol": args.ir_tol, "autotune": args.autotune,
-                   "finest_level_reassembled": bool(args.reassemble),
+                   "finest_level_reassembled": bool(args.reassemble), "lu_pivoting": args.lu_pivoting,
                    "profile_mode": args.profile_mode},
         "algorithmic_flop_per_step": {"lu": lu_f, "pair_solves": solve_f, "far_field": ff_f},
     }

@@ -32,7 +32,7 @@ static void check_opts(const fosb_opts& o) {
   if (o.ir_max_sweeps < 0 || o.ir_max_sweeps > 50) fail(FOSB_E_INVALID, "opts: ir_max_sweeps must be 0..50");
   if (!(o.ir_tol > 0.0) || !std::isfinite(o.ir_tol)) fail(FOSB_E_INVALID, "opts: ir_tol must be positive");
   if (o.certify != 0 && o.certify != 1) fail(FOSB_E_INVALID, "opts: certify must be 0 or 1");
-  if (o.reserved != 0) fail(FOSB_E_INVALID, "opts: reserved must be 0");
+  if (o.lu_pivoting != 0 && o.lu_pivoting != 1) fail(FOSB_E_INVALID, "opts: lu_pivoting must be 0 or 1");
 }
 
 static fosb_opts opts_or_default(const fosb_opts* o) {
@@ -41,7 +41,7 @@ static fosb_opts opts_or_default(const fosb_opts* o) {
   r.ir_max_sweeps = 10;
   r.ir_tol = 1e-10;
   r.certify = 0;
-  r.reserved = 0;
+  r.lu_pivoting = 0;
   if (o) r = *o;
   check_opts(r);
   return r;
@@ -426,8 +426,38 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     const size_t bytes = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(c64);
     L->inv_L.alloc(bytes);
     L->inv_U.alloc(bytes);
-    info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(), L->perm,
-                            L->inv_L.as<c64>());
+    bool factored = false;
+    if (!pm && o.lu_pivoting == 0 && n >= 2048) {
+      // symmetric EFIE matrix: no pivoting, half the trailing-update flops; kept when no
+      // pivot vanished and the growth factor stays below 1e3
+      double zn[3];
+      DevBuf nrm(8 * sizeof(double));
+      matrix_norms<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, false, nrm.as<double>());
+      FOSB_HIP(hipMemcpyAsync(zn, nrm.p, sizeof(zn), hipMemcpyDeviceToHost, s));
+      FOSB_HIP(hipStreamSynchronize(s));
+      const double zmax = zn[0];
+      const double defect = sym_defect<float>(c, static_cast<const c64*>(Zlow), n, ldzlow);
+      if (zmax > 0 && defect <= 1e-5 * zmax) {
+        info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
+                                L->perm, L->inv_L.as<c64>(), true);
+        matrix_norms<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, true, nrm.as<double>());
+        double un[3];
+        FOSB_HIP(hipMemcpyAsync(un, nrm.p, sizeof(un), hipMemcpyDeviceToHost, s));
+        FOSB_HIP(hipStreamSynchronize(s));
+        const double growth = un[0] / zmax;
+        factored = info == 0 && std::isfinite(growth) && growth <= 1e3;
+        L->sym_lu = factored ? 1 : 0;
+        if (!factored) {  // start again from the assembled matrix with pivoting
+          if (Z)
+            copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
+          else
+            assemble_efie_c64(c, *mesh, k, o.n_gauss_singular, static_cast<c64*>(Zlow), ldzlow);
+        }
+      }
+    }
+    if (!factored)
+      info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
+                              L->perm, L->inv_L.as<c64>());
     if (info == 0)
       upper_block_inverses<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, L->dinv_U.as<c64>(),
                                   L->inv_U.as<c64>());
@@ -1016,6 +1046,13 @@ fosb_status fosb_level_formulation(const fosb_level* level, int32_t* form, doubl
   if (form) *form = level->form;
   if (eps_r) *eps_r = level->eps_r;
   if (mu_r) *mu_r = level->mu_r;
+  API_END
+}
+
+fosb_status fosb_level_factorization(const fosb_level* level, int32_t* kind) {
+  API_BEGIN
+  REQUIRE(level && kind, "level/kind is NULL");
+  *kind = level->sym_lu ? FOSB_FACTOR_SYM : FOSB_FACTOR_LU;
   API_END
 }
 

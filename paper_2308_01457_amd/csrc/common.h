@@ -305,6 +305,7 @@ struct Level {
   DevBuf b;                    // PMCHWT: c128 [n][n_dirs]
   int sd_field = -1;           // PMCHWT: field of the shape-derivative weights (-1: none built)
   int sd_streamed = 0;         // PMCHWT: weights recomputed by source bands when used, none stored
+  int sym_lu = 0;              // MIXED: factored without pivoting (symmetric form)
   DevBuf Wsd;                  // PMCHWT: c128 [n_dirs][n][6 nt] shape-derivative weights (with nu)
   const void* lu() const { return precision == FOSB_PREC_FP64 ? Z : Zlow; }
 };
@@ -354,9 +355,16 @@ void gemm_ch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const 
 // invL (optional, complex64 factors): receives the kInvBlock x kInvBlock
 // diagonal-block inverses of L (layout as for upper_block_inverses); the
 // blocked factorisation then also solves its block rows through them.
+// sym: the matrix is (numerically) symmetric; for n >= 2048 it is factored
+// without pivoting, A = L U with U = D L^T formed from the multipliers and the
+// trailing updates restricted to the lower triangle (about half the flops).
+// The caller judges the result (zero pivot through the return value, growth).
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
-                  std::vector<int32_t>& perm, cplx<T>* invL = nullptr);
+                  std::vector<int32_t>& perm, cplx<T>* invL = nullptr, bool sym = false);
+// max over i, j of |A[i][j] - A[j][i]| (synchronises the stream)
+template <typename T>
+double sym_defect(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda);
 template <typename T>
 void trsm_lower_unit(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0,
                      int64_t n, cplx<T>* B, int64_t ldb, int64_t nrhs);

@@ -15,6 +15,7 @@
 // the 256-row leaves solve with the stored 32x32 diagonal-block inverses.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "common.h"
 
@@ -367,6 +368,107 @@ __global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __re
   if (tid >= ncand && tid < NB) out[tid] = -1;
 }
 
+// Panel without pivoting (the symmetric factorisation below): LU of the
+// panel's top w x w block in LDS with the pivots in place, and the same
+// outputs as a tournament root (top block, inverses of both diagonal factors,
+// an empty row-move list, the first exactly zero pivot).
+template <typename T>
+__global__ __launch_bounds__(Node<T>::size) void k_nopiv_root(const cplx<T>* __restrict__ A, int64_t lda, int64_t k,
+                                                              int w, int32_t* __restrict__ moves,
+                                                              int32_t* __restrict__ info, cplx<T>* __restrict__ top,
+                                                              cplx<T>* __restrict__ invL, cplx<T>* __restrict__ invU) {
+  constexpr int NODE = Node<T>::size;
+  __shared__ cplx<T> lu[NB][NB + 1];
+  __shared__ int win[NB];
+  __shared__ int szc;
+  const int tid = threadIdx.x;
+  raise_wave_priority();
+  for (int e = tid; e < NB * NB; e += NODE) {
+    const int r = e / NB, c = e % NB;
+    lu[r][c] = (r < w && c < w) ? A[(k + r) * lda + k + c] : cplx<T>{T(0), T(0)};
+  }
+  if (tid < NB) win[tid] = (int)(k + tid);
+  if (tid == 0) szc = -1;
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    const cplx<T> p = lu[j][j];
+    if (tid == 0 && szc < 0 && p.re == T(0) && p.im == T(0)) szc = j;
+    const cplx<T> pi = cinv(p);   // zero for an exactly zero pivot (reported through info)
+    const int rows = w - j - 1;
+    for (int e = tid; e < rows; e += NODE) lu[j + 1 + e][j] = cmul(lu[j + 1 + e][j], pi);
+    __syncthreads();
+    for (int e = tid; e < rows * rows; e += NODE) {
+      const int i = j + 1 + e / rows, c = j + 1 + e % rows;
+      const cplx<T> l = lu[i][j], u = lu[j][c];
+      lu[i][c].re -= l.re * u.re - l.im * u.im;
+      lu[i][c].im -= l.re * u.im + l.im * u.re;
+    }
+    __syncthreads();
+  }
+  const int zc = szc;
+  panel_root(lu, win, w, w, zc, k, tid, moves, info, top, invL, invU);
+}
+
+// U12 = D L21^T for a symmetric factorisation without pivoting: rows
+// kj .. kj + wj of columns c0 .. c0 + cn receive d_t A[c][kj + t], d_t the
+// diagonal of U in the block's diagonal square (32 x 32 tiles through LDS).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_u12(cplx<T>* __restrict__ A, int64_t lda, int64_t kj, int64_t wj,
+                                                 int64_t c0, int64_t cn) {
+  __shared__ cplx<T> tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int64_t t0 = (int64_t)blockIdx.y * 32, cb = c0 + (int64_t)blockIdx.x * 32;
+  for (int r = ty; r < 32; r += 8) {   // read rows c = cb + r, columns kj + t0 + tx (the multipliers)
+    const int64_t c = cb + r, t = t0 + tx;
+    tile[r][tx] = (c < c0 + cn && t < wj) ? A[c * lda + kj + t] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {   // write rows kj + t, t = t0 + r, columns cb + tx
+    const int64_t t = t0 + r, c = cb + tx;
+    if (t < wj && c < c0 + cn) {
+      const cplx<T> d = A[(kj + t) * lda + kj + t];
+      const cplx<T> l = tile[tx][r];
+      A[(kj + t) * lda + c] = cplx<T>{d.re * l.re - d.im * l.im, d.re * l.im + d.im * l.re};
+    }
+  }
+}
+
+template <typename T>
+static void sym_u12(hipStream_t s, cplx<T>* A, int64_t lda, int64_t kj, int64_t wj, int64_t c0, int64_t cn) {
+  if (wj <= 0 || cn <= 0) return;
+  dim3 g((unsigned)((cn + 31) / 32), (unsigned)((wj + 31) / 32));
+  hipLaunchKernelGGL(k_sym_u12<T>, g, dim3(256), 0, s, A, lda, kj, wj, c0, cn);
+  FOSB_LAUNCH_CHECK();
+}
+
+// Largest |A[i][j] - A[j][i]| over the matrix, as float bits folded with
+// atomicMax (non-negative floats order like their bit patterns, and a maximum
+// does not depend on the order).  32 x 32 tile pairs through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_defect(const cplx<T>* __restrict__ A, int64_t lda, int64_t n,
+                                                    unsigned* __restrict__ out) {
+  __shared__ cplx<T> tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bj * 32 + r, j = bi * 32 + tx;   // the mirrored tile, row-major
+    tile[r][tx] = (i < n && j < n) ? A[i * lda + j] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  float m = 0.f;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+    if (i < n && j < n) {
+      const cplx<T> a = A[i * lda + j], b = tile[tx][r];
+      const double dr = (double)a.re - (double)b.re, di = (double)a.im - (double)b.im;
+      m = fmaxf(m, (float)sqrt(dr * dr + di * di));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
 // Apply npl consecutive row-move lists (list q at plist + q * kMoveStride, in
 // order) to the columns of up to two ranges [c0[r], c1[r]), in stripes of 64.
 struct ColRanges {
@@ -694,12 +796,14 @@ struct LuRun {
   cplx<T>* top;
   int64_t pc0, pc1;  // columns a panel permutes at once (the rest is the update stream's)
   cplx<T>* invL = nullptr;  // optional: NL x NL diagonal-block inverses of L, filled per block
+  bool sym = false;         // symmetric matrix, no pivoting: lower-triangle trailing updates, U12 = D L21^T
 };
 
 constexpr int kMoveStride = 1 + 4 * NB;
 static_assert(kMoveStride == kMoveStrideDev, "row-move list stride");
 constexpr int64_t kLookaheadMinN = 2048;  // smaller matrices: plain recursion on one stream
 constexpr int64_t kTrailChunk = 16384;     // columns per trailing-update launch (measured: 2048..16384)
+constexpr int64_t kSymChunk = 2048;        // symmetric form: its rows start at the chunk, so narrower chunks waste less
 
 static inline int64_t split_half(int64_t w) { return (int64_t)NB * (((w / NB) + 1) / 2); }
 
@@ -710,6 +814,15 @@ static void panel(LuRun<T>& R, int64_t k, int w) {
   const int64_t blk = k / NB;
   int32_t* moves = R.moves + blk * kMoveStride;
   ProfScope prof(*R.ctx, FOSB_K_PANEL, 0.0, (double)sizeof(cplx<T>) * (double)m * w * 3.0);
+  if (R.sym) {  // pivots in place: factor the top block, then the multipliers below it
+    hipLaunchKernelGGL(k_nopiv_root<T>, dim3(1), dim3(Node<T>::size), 0, s, R.A, R.lda, k, w, moves, R.info, R.top,
+                       R.dinvL + blk * NB * NB, R.dinvU + blk * NB * NB);
+    FOSB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_panel_finish<T>, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, R.A, R.lda, R.n, k, w,
+                       R.top, R.dinvU + blk * NB * NB);
+    FOSB_LAUNCH_CHECK();
+    return;
+  }
   // leaf level over consecutive rows, then FANIN-way merges until one node remains
   constexpr int NODE = Node<T>::size, FANIN = NODE / NB;
   int nodes = (int)((m + NODE - 1) / NODE);
@@ -822,7 +935,7 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
     const int64_t kj = j * nb, wj = std::min(nb, n - kj);
     FOSB_HIP(hipStreamWaitEvent(sb, ev_panel, 0));
     if (R.invL) block_inverses<T, true>(U, A, n, lda, R.dinvL, R.invL, kj / NL, (wj + NL - 1) / NL);
-    {
+    if (!R.sym) {
       ColRanges cr{{0, kj + wj}, {kj, n}};
       const int64_t width = kj + (n - kj - wj);
       if (width > 0) {
@@ -834,6 +947,21 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
     }
     if (j + 1 == nblk) break;
     const int64_t k1 = kj + wj, w1 = std::min(nb, n - k1);
+    if (R.sym) {  // symmetric, no pivoting: U12 = D L21^T, trailing updates of the lower triangle only
+      sym_u12<T>(sb, A, lda, kj, wj, k1, w1);
+      gemm<T>(U, n - k1, w1, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + k1, lda, 1.0, A + k1 * lda + k1, lda);
+      FOSB_HIP(hipEventRecord(ev_look, sb));
+      FOSB_HIP(hipStreamWaitEvent(sa, ev_look, 0));
+      panel_block(k1, w1);
+      // chunks of whole blocks (a block's diagonal square lies in one chunk, whose rows start at it)
+      const int64_t chunk = std::max<int64_t>(nb, kSymChunk / nb * nb);
+      for (int64_t c0 = k1 + w1; c0 < n; c0 += chunk) {
+        const int64_t cn = std::min<int64_t>(chunk, n - c0);
+        sym_u12<T>(sb, A, lda, kj, wj, c0, cn);
+        gemm<T>(U, n - c0, cn, wj, -1.0, A + c0 * lda + kj, lda, A + kj * lda + c0, lda, 1.0, A + c0 * lda + c0, lda);
+      }
+      continue;
+    }
     block_row_solve(R, U, kj, wj, A + kj * lda + k1, w1);
     gemm<T>(U, n - k1, w1, wj, -1.0, A + k1 * lda + kj, lda, A + kj * lda + k1, lda, 1.0, A + k1 * lda + k1, lda);
     FOSB_HIP(hipEventRecord(ev_look, sb));
@@ -856,7 +984,7 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
 
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
-                  std::vector<int32_t>& perm, cplx<T>* invL) {
+                  std::vector<int32_t>& perm, cplx<T>* invL, bool sym) {
   hipStream_t s = ctx.stream;
   const int64_t maxnodes = (n + Node<T>::size - 1) / Node<T>::size;
   const int64_t npanel = (n + NB - 1) / NB;
@@ -879,6 +1007,7 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   R.pc0 = 0;
   R.pc1 = n;
   R.invL = invL;
+  R.sym = sym && n >= kLookaheadMinN;
   // first zero pivot, reduced with atomicMin: starts above every index (0x7f7f7f7f)
   FOSB_HIP(hipMemsetAsync(R.info, 0x7f, sizeof(int32_t), s));
   if (n >= kLookaheadMinN) {
@@ -1001,8 +1130,31 @@ void trsm_lower_unit_ch(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<
   trsm_lower_unit_ch<T>(ctx, A, lda, dinvL, k0, n1, B, ldb, nrhs);
 }
 
-template int64_t lu_factor<double>(Context&, c128*, int64_t, int64_t, c128*, c128*, std::vector<int32_t>&, c128*);
-template int64_t lu_factor<float>(Context&, c64*, int64_t, int64_t, c64*, c64*, std::vector<int32_t>&, c64*);
+template int64_t lu_factor<double>(Context&, c128*, int64_t, int64_t, c128*, c128*, std::vector<int32_t>&, c128*,
+                                   bool);
+template int64_t lu_factor<float>(Context&, c64*, int64_t, int64_t, c64*, c64*, std::vector<int32_t>&, c64*, bool);
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+template <typename T>
+double sym_defect(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda) {
+  hipStream_t s = ctx.stream;
+  ctx.norms.reserve(64);
+  unsigned* d = reinterpret_cast<unsigned*>(ctx.norms.p);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d);
+  FOSB_LAUNCH_CHECK();
+  const unsigned nb = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_sym_defect<T>, dim3(nb, nb), dim3(256), 0, s, A, lda, n, d);
+  FOSB_LAUNCH_CHECK();
+  unsigned h = 0;
+  FOSB_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+  FOSB_HIP(hipStreamSynchronize(s));
+  float f;
+  std::memcpy(&f, &h, sizeof(f));
+  return (double)f;
+}
+template double sym_defect<float>(Context&, const c64*, int64_t, int64_t);
+template double sym_defect<double>(Context&, const c128*, int64_t, int64_t);
 template void trsm_lower_unit<double>(Context&, const c128*, int64_t, const c128*, int64_t, int64_t, c128*,
                                       int64_t, int64_t);
 template void trsm_lower_unit<float>(Context&, const c64*, int64_t, const c64*, int64_t, int64_t, c64*, int64_t,

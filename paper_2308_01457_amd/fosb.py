@@ -26,6 +26,7 @@ STATUS = {0: "OK", 1: "E_INVALID", 2: "E_SINGULAR", 3: "E_NOCONV", 4: "E_WORKSPA
 COV_KINDS = {"gaussian": GAUSSIAN, "matern32": MATERN32, "constant": CONSTANT, "normal_dot": NORMAL_DOT}
 FIELDS = {"radial": RADIAL, "normal": NORMAL}
 FORM_EFIE, FORM_PMCHWT = 0, 1
+FACTOR_LU, FACTOR_SYM = 0, 1
 SD_STREAMED = 16
 
 
@@ -38,7 +39,7 @@ class FosbError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("n_gauss_singular", C.c_int32), ("ir_max_sweeps", C.c_int32), ("ir_tol", C.c_double),
-                ("certify", C.c_int32), ("reserved", C.c_int32)]
+                ("certify", C.c_int32), ("lu_pivoting", C.c_int32)]
 
 
 class Cov(C.Structure):
@@ -79,6 +80,7 @@ _SIGS = {
     "fosb_level_create_pmchwt": (C.c_int, [_P, _P, _D, _D, _D, _I32, _P, _I64, _P, _I64, _P, _P, _I64, _I32,
                                            C.POINTER(Opts), C.POINTER(_P)]),
     "fosb_level_formulation": (C.c_int, [_P, C.POINTER(_I32), C.POINTER(_D), C.POINTER(_D)]),
+    "fosb_level_factorization": (C.c_int, [_P, C.POINTER(_I32)]),
     "fosb_level_sd_weights": (C.c_int, [_P, _P, _I64, _P, _I64]),
     "fosb_level_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
     "fosb_level_workspace_size": (C.c_int, [_P, _I32, _I64, _I64, C.POINTER(_I64), C.POINTER(_I64)]),
@@ -401,6 +403,12 @@ class Level:
         f, e, m = _I32(), _D(), _D()
         _check(lib().fosb_level_formulation(self.h, C.byref(f), C.byref(e), C.byref(m)))
         return f.value, e.value, m.value
+
+    def factorization(self) -> int:
+        """fosb_level_factorization: FACTOR_LU or FACTOR_SYM."""
+        k = _I32()
+        _check(lib().fosb_level_factorization(self.h, C.byref(k)))
+        return k.value
 
     def solve(self, B, stats: Stats | None = None):
         import torch
