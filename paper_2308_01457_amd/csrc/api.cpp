@@ -430,21 +430,12 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     if (!pm && o.lu_pivoting == 0 && n >= 2048) {
       // symmetric EFIE matrix: no pivoting, half the trailing-update flops; kept when no
       // pivot vanished and the growth factor stays below 1e3
-      double zn[3];
-      DevBuf nrm(8 * sizeof(double));
-      matrix_norms<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, false, nrm.as<double>());
-      FOSB_HIP(hipMemcpyAsync(zn, nrm.p, sizeof(zn), hipMemcpyDeviceToHost, s));
-      FOSB_HIP(hipStreamSynchronize(s));
-      const double zmax = zn[0];
-      const double defect = sym_defect<float>(c, static_cast<const c64*>(Zlow), n, ldzlow);
-      if (zmax > 0 && defect <= 1e-5 * zmax) {
+      double defect = 0.0, zmax = 0.0;
+      sym_check<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, &defect, &zmax);
+      if (zmax > 0 && std::isfinite(zmax) && defect <= 1e-5 * zmax) {
         info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
                                 L->perm, L->inv_L.as<c64>(), true);
-        matrix_norms<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, true, nrm.as<double>());
-        double un[3];
-        FOSB_HIP(hipMemcpyAsync(un, nrm.p, sizeof(un), hipMemcpyDeviceToHost, s));
-        FOSB_HIP(hipStreamSynchronize(s));
-        const double growth = un[0] / zmax;
+        const double growth = absmax_upper<float>(c, static_cast<const c64*>(Zlow), n, ldzlow) / zmax;
         factored = info == 0 && std::isfinite(growth) && growth <= 1e3;
         L->sym_lu = factored ? 1 : 0;
         if (!factored) {  // start again from the assembled matrix with pivoting

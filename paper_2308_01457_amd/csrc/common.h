@@ -362,9 +362,13 @@ void gemm_ch(Context& ctx, int64_t M, int64_t N, int64_t K, double alpha, const 
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
                   std::vector<int32_t>& perm, cplx<T>* invL = nullptr, bool sym = false);
-// max over i, j of |A[i][j] - A[j][i]| (synchronises the stream)
+// *defect = max over i, j of |A[i][j] - A[j][i]|, *amax = max |A[i][j]|, in
+// one pass (rounded to float; synchronises the stream)
 template <typename T>
-double sym_defect(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda);
+void sym_check(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, double* defect, double* amax);
+// max |A[i][j]| over j >= i (rounded to float; synchronises the stream)
+template <typename T>
+double absmax_upper(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda);
 template <typename T>
 void trsm_lower_unit(Context& ctx, const cplx<T>* A, int64_t lda, const cplx<T>* dinvL, int64_t k0,
                      int64_t n, cplx<T>* B, int64_t ldb, int64_t nrhs);

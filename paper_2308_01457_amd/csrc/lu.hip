@@ -220,51 +220,49 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
   if (tid < wk && win[tid] < k + wk) inblk[win[tid] - k] = 1;
   for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
   if (zc >= 0 && tid == 0) atomicMin(info, (int)(k + zc + 1));
-  // Inverses of the diagonal factors (identity beyond wk) by Gauss-Jordan
-  // sweeps over the whole workgroup, one barrier per step: L X = I forward,
-  // then U Y = I backward.  At backward step r every thread forms row r's
-  // scaled entries Y[r][c] / U[r][r] (r <= c < wk) itself; the threads on row
-  // r store them to invU (they are final), the others eliminate column r from
-  // rows i < r with them.  Row r of Y is not read again after step r.
-  __shared__ cplx<T> sx[NB][NB + 1];
-  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
-  __syncthreads();
-  for (int r = 0; r < wk; ++r) {
-    // rows i > r: X[i][c] -= L[i][r] X[r][c], c <= r
-    const int cols = r + 1, rows = wk - r - 1;
-    for (int e = tid; e < rows * cols; e += NODE) {
-      const int i = r + 1 + e / cols, c = e % cols;
-      const cplx<T> l = tb[i][r], x = sx[r][c];
-      sx[i][c].re -= l.re * x.re - l.im * x.im;
-      sx[i][c].im -= l.re * x.im + l.im * x.re;
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < NB * NB; e += NODE) {  // each thread reads, then resets, its own entries
-    invL[e] = sx[e / NB][e % NB];
-    sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
-  }
-  __syncthreads();
-  for (int r = wk - 1; r >= 0; --r) {
-    // rows i < r: Y[i][c] -= U[i][r] (Y[r][c] / U[r][r]), c >= r
-    const int cols = wk - r;
-    const cplx<T> inv = cinv(tb[r][r]);
-    for (int e = tid; e < (r + 1) * cols; e += NODE) {
-      const int i = e / cols, c = r + e % cols;
-      const cplx<T> x = cmul(sx[r][c], inv);
-      if (i == r) {
-        invU[r * NB + c] = x;
-      } else {
-        const cplx<T> u = tb[i][r];
-        sx[i][c].re -= u.re * x.re - u.im * x.im;
-        sx[i][c].im -= u.re * x.im + u.im * x.re;
+  // Inverses of the diagonal factors (identity beyond wk), one column per lane
+  // of the first wavefront and no barrier: lane c < NB solves L x = e_c by
+  // forward substitution, lane NB + c solves U y = e_c by back substitution
+  // (entries of U^{-1} carry 1/U[i][i], zero for an exactly zero pivot).  The
+  // factor entries are broadcast reads of the block in LDS.
+  if (tid < 2 * NB) {
+    const int c = tid & (NB - 1);
+    const bool live = c < wk;
+    cplx<T> x[NB];
+    if (tid < NB) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        cplx<T> v{(i == c) ? T(1) : T(0), T(0)};
+        if (live && i < wk) {
+#pragma unroll
+          for (int j = 0; j < i; ++j) {
+            const cplx<T> l = tb[i][j];
+            v.re -= l.re * x[j].re - l.im * x[j].im;
+            v.im -= l.re * x[j].im + l.im * x[j].re;
+          }
+        }
+        x[i] = v;
       }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) invL[i * NB + c] = x[i];
+    } else {
+#pragma unroll
+      for (int i = NB - 1; i >= 0; --i) {
+        cplx<T> v{(i == c) ? T(1) : T(0), T(0)};
+        if (live && i < wk) {
+#pragma unroll
+          for (int j = i + 1; j < NB; ++j) {   // x[j] = 0 for j > c and for j >= wk
+            const cplx<T> u = tb[i][j];
+            v.re -= u.re * x[j].re - u.im * x[j].im;
+            v.im -= u.re * x[j].im + u.im * x[j].re;
+          }
+          v = cmul(v, cinv(tb[i][i]));
+        }
+        x[i] = v;
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) invU[i * NB + c] = x[i];
     }
-    __syncthreads();
-  }
-  for (int e = tid; e < NB * NB; e += NODE) {
-    const int r = e / NB, c = e % NB;
-    if (r >= wk || c < r || c >= wk) invU[e] = cplx<T>{(r == c) ? T(1) : T(0), T(0)};  // the rest stored above
   }
   // move list, built by the first wavefront (every thread reaches the barrier)
   __shared__ int vsorted[NB];
@@ -368,43 +366,66 @@ __global__ __launch_bounds__(Node<T>::size) void k_tslu_node(const cplx<T>* __re
   if (tid >= ncand && tid < NB) out[tid] = -1;
 }
 
+// Value of lane l of the wavefront (l uniform), through the scalar unit.
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Panel without pivoting (the symmetric factorisation below): LU of the
-// panel's top w x w block in LDS with the pivots in place, and the same
-// outputs as a tournament root (top block, inverses of both diagonal factors,
-// an empty row-move list, the first exactly zero pivot).
+// panel's top w x w block with the pivots in place, and the same outputs as a
+// tournament root (top block, inverses of both diagonal factors, an empty
+// row-move list, the first exactly zero pivot).  The first wavefront factors
+// the block in registers, lane r holding row r; at step j every lane takes
+// row j's entries from lane j (row j is final once step j starts).
 template <typename T>
 __global__ __launch_bounds__(Node<T>::size) void k_nopiv_root(const cplx<T>* __restrict__ A, int64_t lda, int64_t k,
                                                               int w, int32_t* __restrict__ moves,
                                                               int32_t* __restrict__ info, cplx<T>* __restrict__ top,
                                                               cplx<T>* __restrict__ invL, cplx<T>* __restrict__ invU) {
-  constexpr int NODE = Node<T>::size;
   __shared__ cplx<T> lu[NB][NB + 1];
   __shared__ int win[NB];
   __shared__ int szc;
   const int tid = threadIdx.x;
   raise_wave_priority();
-  for (int e = tid; e < NB * NB; e += NODE) {
-    const int r = e / NB, c = e % NB;
-    lu[r][c] = (r < w && c < w) ? A[(k + r) * lda + k + c] : cplx<T>{T(0), T(0)};
-  }
   if (tid < NB) win[tid] = (int)(k + tid);
-  if (tid == 0) szc = -1;
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    const cplx<T> p = lu[j][j];
-    if (tid == 0 && szc < 0 && p.re == T(0) && p.im == T(0)) szc = j;
-    const cplx<T> pi = cinv(p);   // zero for an exactly zero pivot (reported through info)
-    const int rows = w - j - 1;
-    for (int e = tid; e < rows; e += NODE) lu[j + 1 + e][j] = cmul(lu[j + 1 + e][j], pi);
-    __syncthreads();
-    for (int e = tid; e < rows * rows; e += NODE) {
-      const int i = j + 1 + e / rows, c = j + 1 + e % rows;
-      const cplx<T> l = lu[i][j], u = lu[j][c];
-      lu[i][c].re -= l.re * u.re - l.im * u.im;
-      lu[i][c].im -= l.re * u.im + l.im * u.re;
+  if (tid < 64) {
+    const int r = tid;
+    const bool row = r < w;
+    cplx<T> a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[c] = (row && c < w) ? A[(k + r) * lda + k + c] : cplx<T>{T(0), T(0)};
+    int zc = -1;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < w) {
+        const cplx<T> p{lane_value(a[j].re, j), lane_value(a[j].im, j)};
+        if (zc < 0 && p.re == T(0) && p.im == T(0)) zc = j;
+        const cplx<T> l = cmul(a[j], cinv(p));   // cinv(0) = 0: an exactly zero pivot is reported through info
+        const bool below = row && r > j;
+        if (below) a[j] = l;
+#pragma unroll
+        for (int c = j + 1; c < NB; ++c) {
+          const cplx<T> u{lane_value(a[c].re, j), lane_value(a[c].im, j)};
+          if (below) {
+            a[c].re -= l.re * u.re - l.im * u.im;
+            a[c].im -= l.re * u.im + l.im * u.re;
+          }
+        }
+      }
     }
-    __syncthreads();
+    if (r < NB) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) lu[r][c] = a[c];
+    }
+    if (tid == 0) szc = zc;
   }
+  __syncthreads();
   const int zc = szc;
   panel_root(lu, win, w, w, zc, k, tid, moves, info, top, invL, invU);
 }
@@ -441,32 +462,83 @@ static void sym_u12(hipStream_t s, cplx<T>* A, int64_t lda, int64_t kj, int64_t 
   FOSB_LAUNCH_CHECK();
 }
 
-// Largest |A[i][j] - A[j][i]| over the matrix, as float bits folded with
-// atomicMax (non-negative floats order like their bit patterns, and a maximum
-// does not depend on the order).  32 x 32 tile pairs through LDS.
+// |v| rounded to float; a non-finite magnitude (NaN included) becomes +inf, so
+// that the maxima below report it
 template <typename T>
-__global__ __launch_bounds__(256) void k_sym_defect(const cplx<T>* __restrict__ A, int64_t lda, int64_t n,
-                                                    unsigned* __restrict__ out) {
+__device__ __forceinline__ float mag_or_inf(T re, T im) {
+  const float f = (float)sqrt((double)re * re + (double)im * im);
+  return f <= 3.402823466e38f ? f : __builtin_inff();
+}
+
+// Symmetry check of a square matrix in one pass: out[0] receives the largest
+// |A[i][j] - A[j][i]| and out[1] the largest |A[i][j]|, as float bits folded
+// with atomicMax (non-negative floats order like their bit patterns, and a
+// maximum does not depend on the order).  Workgroups stride over the 32 x 32
+// tile pairs (bi >= bj) of the lower triangle; the mirrored tile goes through
+// LDS, both tiles are read row-wise, and each workgroup reduces its maxima
+// before one atomic per output.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_check(const cplx<T>* __restrict__ A, int64_t lda, int64_t n,
+                                                   unsigned* __restrict__ out) {
   __shared__ cplx<T> tile[32][33];
+  __shared__ float red[2][4];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int64_t bi = blockIdx.y, bj = blockIdx.x;
-  if (bj > bi) return;
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t i = bj * 32 + r, j = bi * 32 + tx;   // the mirrored tile, row-major
-    tile[r][tx] = (i < n && j < n) ? A[i * lda + j] : cplx<T>{T(0), T(0)};
-  }
-  __syncthreads();
-  float m = 0.f;
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
-    if (i < n && j < n) {
-      const cplx<T> a = A[i * lda + j], b = tile[tx][r];
-      const double dr = (double)a.re - (double)b.re, di = (double)a.im - (double)b.im;
-      m = fmaxf(m, (float)sqrt(dr * dr + di * di));
+  const int64_t nb = (n + 31) / 32, npairs = nb * (nb + 1) / 2;
+  float md = 0.f, ma = 0.f;
+  for (int64_t t = blockIdx.x; t < npairs; t += gridDim.x) {
+    int64_t bi = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > t) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int64_t bj = t - bi * (bi + 1) / 2;
+    __syncthreads();   // the previous pair's reads of the tile are done
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t i = bj * 32 + r, j = bi * 32 + tx;   // the mirrored tile, row-major
+      const cplx<T> v = (i < n && j < n) ? A[i * lda + j] : cplx<T>{T(0), T(0)};
+      tile[r][tx] = v;
+      ma = fmaxf(ma, mag_or_inf(v.re, v.im));
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+      if (i < n && j < n) {
+        const cplx<T> a = A[i * lda + j], b = tile[tx][r];
+        md = fmaxf(md, mag_or_inf((double)a.re - (double)b.re, (double)a.im - (double)b.im));
+        ma = fmaxf(ma, mag_or_inf(a.re, a.im));
+      }
     }
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    md = fmaxf(md, __shfl_xor(md, o, 64));
+    ma = fmaxf(ma, __shfl_xor(ma, o, 64));
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = md;
+    red[1][wave] = ma;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const float m = fmaxf(fmaxf(red[threadIdx.x][0], red[threadIdx.x][1]), fmaxf(red[threadIdx.x][2], red[threadIdx.x][3]));
+    atomicMax(out + threadIdx.x, __float_as_uint(m));
+  }
+}
+
+// Largest |A[i][j]| over the upper triangle (j >= i) into *out (float bits,
+// atomicMax): workgroups stride over the rows, their threads along a row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_absmax_upper(const cplx<T>* __restrict__ A, int64_t lda, int64_t n,
+                                                      unsigned* __restrict__ out) {
+  __shared__ float red[4];
+  float m = 0.f;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+    for (int64_t j = i + threadIdx.x; j < n; j += 256) {
+      const cplx<T> v = A[i * lda + j];
+      m = fmaxf(m, mag_or_inf(v.re, v.im));
+    }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
 }
 
 // Apply npl consecutive row-move lists (list q at plist + q * kMoveStride, in
@@ -1134,27 +1206,53 @@ template int64_t lu_factor<double>(Context&, c128*, int64_t, int64_t, c128*, c12
                                    bool);
 template int64_t lu_factor<float>(Context&, c64*, int64_t, int64_t, c64*, c64*, std::vector<int32_t>&, c64*, bool);
 
-__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+__global__ void k_zero_u32(unsigned* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
 
-template <typename T>
-double sym_defect(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda) {
-  hipStream_t s = ctx.stream;
-  ctx.norms.reserve(64);
-  unsigned* d = reinterpret_cast<unsigned*>(ctx.norms.p);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, d);
-  FOSB_LAUNCH_CHECK();
-  const unsigned nb = (unsigned)((n + 31) / 32);
-  hipLaunchKernelGGL(k_sym_defect<T>, dim3(nb, nb), dim3(256), 0, s, A, lda, n, d);
-  FOSB_LAUNCH_CHECK();
-  unsigned h = 0;
-  FOSB_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
-  FOSB_HIP(hipStreamSynchronize(s));
+static double float_bits(unsigned h) {
   float f;
   std::memcpy(&f, &h, sizeof(f));
   return (double)f;
 }
-template double sym_defect<float>(Context&, const c64*, int64_t, int64_t);
-template double sym_defect<double>(Context&, const c128*, int64_t, int64_t);
+
+template <typename T>
+void sym_check(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda, double* defect, double* amax) {
+  hipStream_t s = ctx.stream;
+  ctx.norms.reserve(64);
+  unsigned* d = reinterpret_cast<unsigned*>(ctx.norms.p);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d, 2);
+  FOSB_LAUNCH_CHECK();
+  const int64_t nb = (n + 31) / 32, npairs = nb * (nb + 1) / 2;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(npairs, 8LL * ctx.n_cu));
+  hipLaunchKernelGGL(k_sym_check<T>, dim3(grid), dim3(256), 0, s, A, lda, n, d);
+  FOSB_LAUNCH_CHECK();
+  unsigned h[2] = {0u, 0u};
+  FOSB_HIP(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+  FOSB_HIP(hipStreamSynchronize(s));
+  *defect = float_bits(h[0]);
+  *amax = float_bits(h[1]);
+}
+template void sym_check<float>(Context&, const c64*, int64_t, int64_t, double*, double*);
+template void sym_check<double>(Context&, const c128*, int64_t, int64_t, double*, double*);
+
+template <typename T>
+double absmax_upper(Context& ctx, const cplx<T>* A, int64_t n, int64_t lda) {
+  hipStream_t s = ctx.stream;
+  ctx.norms.reserve(64);
+  unsigned* d = reinterpret_cast<unsigned*>(ctx.norms.p);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, d, 1);
+  FOSB_LAUNCH_CHECK();
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 8LL * ctx.n_cu));
+  hipLaunchKernelGGL(k_absmax_upper<T>, dim3(grid), dim3(256), 0, s, A, lda, n, d);
+  FOSB_LAUNCH_CHECK();
+  unsigned h = 0u;
+  FOSB_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+  FOSB_HIP(hipStreamSynchronize(s));
+  return float_bits(h);
+}
+template double absmax_upper<float>(Context&, const c64*, int64_t, int64_t);
+template double absmax_upper<double>(Context&, const c128*, int64_t, int64_t);
 template void trsm_lower_unit<double>(Context&, const c128*, int64_t, const c128*, int64_t, int64_t, c128*,
                                       int64_t, int64_t);
 template void trsm_lower_unit<float>(Context&, const c64*, int64_t, const c64*, int64_t, int64_t, c64*, int64_t,
