@@ -221,15 +221,16 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
   for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
   if (zc >= 0 && tid == 0) atomicMin(info, (int)(k + zc + 1));
   // Inverses of the diagonal factors (identity beyond wk), one column per lane
-  // of the first wavefront and no barrier: lane c < NB solves L x = e_c by
-  // forward substitution, lane NB + c solves U y = e_c by back substitution
-  // (entries of U^{-1} carry 1/U[i][i], zero for an exactly zero pivot).  The
-  // factor entries are broadcast reads of the block in LDS.
-  if (tid < 2 * NB) {
-    const int c = tid & (NB - 1);
+  // and no barrier: lane c of the first wavefront solves L x = e_c by forward
+  // substitution while lane c of the second solves U y = e_c by back
+  // substitution (entries of U^{-1} carry 1/U[i][i], zero for an exactly zero
+  // pivot).  The factor entries are broadcast reads of the block in LDS.
+  static_assert(Node<T>::size >= 128, "the inverses take two wavefronts");
+  if ((tid & 63) < NB && tid < 128) {
+    const int c = tid & 63;
     const bool live = c < wk;
     cplx<T> x[NB];
-    if (tid < NB) {
+    if (tid < 64) {
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         cplx<T> v{(i == c) ? T(1) : T(0), T(0)};
