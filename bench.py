@@ -71,8 +71,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--max-level", type=int, default=5)
-    ap.add_argument("--ir-tol", type=float, default=1e-8,
-                    help="mixed path: target relative error of the refined solves")
+    ap.add_argument("--ir-tol", type=float, default=1e-7,
+                    help="mixed path: target relative error of the refined solves (an order below the 1e-6 "
+                         "agreement with the FP64 path that the metric asks for)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--progress", action="store_true", help="print a line after every stage of every step")

@@ -220,13 +220,16 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
   if (tid < wk && win[tid] < k + wk) inblk[win[tid] - k] = 1;
   for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
   if (zc >= 0 && tid == 0) atomicMin(info, (int)(k + zc + 1));
-  // Inverses of the diagonal factors (identity beyond wk), one column per lane
-  // and no barrier: lane c of the first wavefront solves L x = e_c by forward
-  // substitution while lane c of the second solves U y = e_c by back
-  // substitution (entries of U^{-1} carry 1/U[i][i], zero for an exactly zero
-  // pivot).  The factor entries are broadcast reads of the block in LDS.
+  // Inverses of the diagonal factors (identity beyond wk; entries of U^{-1}
+  // carry 1/U[i][i], zero for an exactly zero pivot).
+  // FP32: one column per lane and no barrier.  Lane c of the first wavefront
+  // solves L x = e_c by forward substitution while lane c of the second solves
+  // U y = e_c by back substitution; the factor entries are broadcast reads of
+  // the block in LDS.  FP64 keeps the Gauss-Jordan sweeps over the whole
+  // workgroup below: its per-lane columns (128 registers of x alone) ran slower.
   static_assert(Node<T>::size >= 128, "the inverses take two wavefronts");
-  if ((tid & 63) < NB && tid < 128) {
+  if constexpr (sizeof(T) == 4) {
+   if ((tid & 63) < NB && tid < 128) {
     const int c = tid & 63;
     const bool live = c < wk;
     cplx<T> x[NB];
@@ -264,6 +267,53 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
 #pragma unroll
       for (int i = 0; i < NB; ++i) invU[i * NB + c] = x[i];
     }
+  }
+  } else {
+  // Gauss-Jordan sweeps over the whole workgroup, one barrier per step: L X = I forward,
+  // then U Y = I backward.  At backward step r every thread forms row r's
+  // scaled entries Y[r][c] / U[r][r] (r <= c < wk) itself; the threads on row
+  // r store them to invU (they are final), the others eliminate column r from
+  // rows i < r with them.  Row r of Y is not read again after step r.
+  __shared__ cplx<T> sx[NB][NB + 1];
+  for (int e = tid; e < NB * NB; e += NODE) sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  __syncthreads();
+  for (int r = 0; r < wk; ++r) {
+    // rows i > r: X[i][c] -= L[i][r] X[r][c], c <= r
+    const int cols = r + 1, rows = wk - r - 1;
+    for (int e = tid; e < rows * cols; e += NODE) {
+      const int i = r + 1 + e / cols, c = e % cols;
+      const cplx<T> l = tb[i][r], x = sx[r][c];
+      sx[i][c].re -= l.re * x.re - l.im * x.im;
+      sx[i][c].im -= l.re * x.im + l.im * x.re;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += NODE) {  // each thread reads, then resets, its own entries
+    invL[e] = sx[e / NB][e % NB];
+    sx[e / NB][e % NB] = cplx<T>{(e / NB == e % NB) ? T(1) : T(0), T(0)};
+  }
+  __syncthreads();
+  for (int r = wk - 1; r >= 0; --r) {
+    // rows i < r: Y[i][c] -= U[i][r] (Y[r][c] / U[r][r]), c >= r
+    const int cols = wk - r;
+    const cplx<T> inv = cinv(tb[r][r]);
+    for (int e = tid; e < (r + 1) * cols; e += NODE) {
+      const int i = e / cols, c = r + e % cols;
+      const cplx<T> x = cmul(sx[r][c], inv);
+      if (i == r) {
+        invU[r * NB + c] = x;
+      } else {
+        const cplx<T> u = tb[i][r];
+        sx[i][c].re -= u.re * x.re - u.im * x.im;
+        sx[i][c].im -= u.re * x.im + u.im * x.re;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += NODE) {
+    const int r = e / NB, c = e % NB;
+    if (r >= wk || c < r || c >= wk) invU[e] = cplx<T>{(r == c) ? T(1) : T(0), T(0)};  // the rest stored above
+  }
   }
   // move list, built by the first wavefront (every thread reaches the barrier)
   __shared__ int vsorted[NB];

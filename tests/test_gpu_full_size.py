@@ -8,7 +8,7 @@ L0 = 2, L = 5, 181 angles), in the launch configuration bench.py times.
   sampled first moments and each level's first-moment far field against
   tests/golden/mixed_k5_oracle.json, which make_mixed_k5_golden.py wrote from
   the oracle alone.  FP64 path: 1e-9; mixed path (bench tolerance: refined
-  solves to an estimated 1e-8): 1e-6 on the variance, 1e-5 on sampled entries (C is
+  solves to an estimated 1e-7): 1e-6 on the variance, 1e-5 on sampled entries (C is
   built from the first moments, so it carries their accuracy).
 * The CT variance against the mesh-free spectral Mie shape derivative
   (tests/golden/mie_shape_oracle.json): within 0.2%, the discretisation and
@@ -28,7 +28,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "mixed_k5_oracle.json")
-BENCH_IR_TOL = 1e-8   # bench.py's default target error of the refined solves
+BENCH_IR_TOL = 1e-7   # bench.py's default target error of the refined solves
 
 
 def _c(d):
@@ -173,7 +173,7 @@ def test_full_size_properties(fz):
     nz2 = torch.linalg.matrix_norm(Z[2]).item()
     bwd = torch.linalg.matrix_norm(R).item() / (nz5 * torch.linalg.matrix_norm(S).item() * nz2)
     print(f"[gpu]   (5,2): ||Z5 S Z2^H - C||_F / (||Z5||_F ||S||_F ||Z2||_F) = {bwd:.2e}", flush=True)
-    assert bwd < 1e-8      # refined to an estimated relative error of 1e-8
+    assert bwd < 1e-7      # refined to an estimated relative error of 1e-7
     C33 = fosb.rhs_correlation(ctx, lv[3], lv[3], cov)
     herm = (torch.linalg.matrix_norm(C33 - C33.conj().T) / torch.linalg.matrix_norm(C33)).item()
     print(f"[gpu]   C(3,3) Hermitian defect {herm:.2e}", flush=True)

@@ -217,7 +217,7 @@ def test_batch_against_oracle_golden(fz, precision, tol):
     tests/golden/ellipsoids_oracle.json written by make_ellipsoids_golden.py
     from the oracle alone (one incidence at a time).  Per incidence: relative
     2-norm of the variance over (component, angle); the mixed path refines to
-    the benchmark's 1e-8."""
+    the benchmark's 1e-7."""
     fosb, ctx, torch = fz
     import json
     import os
@@ -234,7 +234,7 @@ def test_batch_against_oracle_golden(fz, precision, tol):
         items.append({"meshes": ms, "L0": 0, "L": 2, "k": w.k, "dirs": w.dirs, "pols": w.pols,
                       "cov": fosb.make_cov("matern32", w.sigma, w.ell)})
     print(f"[gpu] batch golden {precision}: shapes {[r['index'] for r in gold['shapes']]}", flush=True)
-    opts = fosb.opts_default(ir_tol=1e-8) if prec == fosb.MIXED else None
+    opts = fosb.opts_default(ir_tol=1e-7) if prec == fosb.MIXED else None
     out = fosb.second_moment_batch(ctx, items, prec, xh, opts=opts, n_workers=2)
     for rec, v in zip(gold["shapes"], out):
         v = v.cpu().numpy()
