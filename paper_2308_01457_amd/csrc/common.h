@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -198,6 +199,14 @@ struct Context {
   std::unique_ptr<Context> la;
   Context& la_context();
   hipEvent_t lu_ev[2] = {nullptr, nullptr};
+  // Progress mark of the next blocked factorisation on this context, for a
+  // caller that orders other streams' work behind part of it: with lu_mark_cb
+  // set, the factorisation records lu_mark_ev on its update stream when it
+  // starts block step floor(lu_mark_frac * blocks) (everything before that step
+  // done), then calls lu_mark_cb once on the host and clears it.
+  hipEvent_t lu_mark_ev = nullptr;
+  double lu_mark_frac = 0.0;
+  std::function<void()> lu_mark_cb;
   // batch workers: own streams, scratch and per-shape workspaces (Z, Zlow, blocks)
   std::vector<std::unique_ptr<Context>> workers;
   std::vector<DevBuf> ws_Z, ws_Zlow, ws_blocks;

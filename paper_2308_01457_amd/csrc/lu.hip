@@ -1054,8 +1054,15 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
   };
   panel_block(0, std::min(nb, n));
   const int64_t nblk = (n + nb - 1) / nb;
+  const int64_t mark_blk = P.lu_mark_cb ? std::min<int64_t>(nblk - 1, (int64_t)(P.lu_mark_frac * (double)nblk)) : -1;
   for (int64_t j = 0; j < nblk; ++j) {
     const int64_t kj = j * nb, wj = std::min(nb, n - kj);
+    if (j == mark_blk && P.lu_mark_cb) {
+      FOSB_HIP(hipEventRecord(P.lu_mark_ev, sb));
+      std::function<void()> cb = std::move(P.lu_mark_cb);
+      P.lu_mark_cb = nullptr;
+      cb();
+    }
     FOSB_HIP(hipStreamWaitEvent(sb, ev_panel, 0));
     if (R.invL) block_inverses<T, true>(U, A, n, lda, R.dinvL, R.invL, kj / NL, (wj + NL - 1) / NL);
     if (!R.sym) {
