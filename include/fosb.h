@@ -16,8 +16,8 @@
  *   - Handles (context, mesh, level) are owned by the library until *_destroy.
  *     The library allocates its own O(N) tables (a MIXED level also keeps the
  *     inverses of the 256 x 256 diagonal blocks of its factors, 4 KiB per
- *     unknown) and work buffers (O(N*nrhs) for solves, up to 1 GiB for the
- *     assembly's column band) on the context's device; O(N^2) matrices are
+ *     unknown) and work buffers (O(N*nrhs) for solves, up to 2 GiB for the
+ *     assembly's two column bands) on the context's device; O(N^2) matrices are
  *     always caller buffers.  These device blocks come from a caching pool
  *     per context (and per stream the context creates): a released block is
  *     kept and handed out again, so once a pass has run, repeating it on

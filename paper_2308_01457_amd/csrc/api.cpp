@@ -1064,7 +1064,7 @@ fosb_status fosb_level_workspace_size(const fosb_mesh* mesh, int32_t precision, 
   REQUIRE(n_dirs >= 1 && n_dirs <= 4096, "need 1..4096 incidence directions");
   if (nrhs <= 0) nrhs = n_dirs;
   if (level_b) *level_b = level_bytes(mesh->h.ne, mesh->h.nt, precision, n_dirs);
-  if (work_b) *work_b = std::max<int64_t>((int64_t)1 << 30, solve_work_bytes(mesh->h.ne, precision, nrhs));
+  if (work_b) *work_b = std::max<int64_t>((int64_t)2 << 30, solve_work_bytes(mesh->h.ne, precision, nrhs));
   API_END
 }
 
@@ -1693,7 +1693,7 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   const fosb_opts o = opts_or_default(opts);
   bind(*ctx);
   {
-    int64_t need = (int64_t)1 << 30;  // assembly band
+    int64_t need = (int64_t)2 << 30;  // the assembly's two band buffers
     for (int32_t i = 0; i < n_levels; ++i) {
       need += level_bytes(meshes[i]->h.ne, meshes[i]->h.nt, precision, n_dirs);
       if (!Z[i]) need += (int64_t)8 << 30;  // bands of the re-assembled residual

@@ -397,11 +397,16 @@ __global__ __launch_bounds__(256) void k_assemble_gather_c64(int ne, const int32
 namespace {
 // Triangle-column bands of the local EFIE blocks.  For each band [j0, j1) of
 // column triangles, the regular and touching-pair kernels fill Zc (3 nt x 3 w
-// local blocks, row stride ldc) and sink(j0, j1, Zc, ldc, cols, ncols) consumes
-// it; cols lists the RWG columns whose T+ or T- lies in the band.  The band
-// buffer holds about `budget` bytes.
+// local blocks, row stride ldc) and sink(stream, j0, j1, Zc, ldc, cols, ncols)
+// consumes it on the given stream; cols lists the RWG columns whose T+ or T-
+// lies in the band.  The band buffer holds about `budget` bytes.  With a
+// second context `sg`, two band buffers alternate and the sink runs on sg's
+// stream: band b + 1 is integrated (VALU-bound) while band b is consumed
+// (memory-bound), and a buffer is refilled only after its previous sink ran.
+// The sinks still run in band order, on one stream.
 template <typename Sink>
-void assemble_bands(Context& ctx, const Mesh& m, double k, int n_gauss, int64_t budget, Sink&& sink) {
+void assemble_bands(Context& ctx, const Mesh& m, double k, int n_gauss, int64_t budget, Sink&& sink,
+                    Context* sg = nullptr) {
   hipStream_t s = ctx.stream;
   const MeshHost& h = m.h;
   const int nt = (int)h.nt, ne = (int)h.ne;
@@ -424,8 +429,22 @@ void assemble_bands(Context& ctx, const Mesh& m, double k, int n_gauss, int64_t 
   if (jc < nt) jc = std::max(64, jc / 64 * 64);
   jc = std::min(jc, nt);
   const int64_t ldc = 3LL * jc;
-  DevBuf band((size_t)(3LL * nt) * ldc * sizeof(c128));
-  c128* Zc = band.as<c128>();
+  const size_t band_bytes = (size_t)(3LL * nt) * ldc * sizeof(c128);
+  DevBuf band(band_bytes), band2;
+  c128* Zbuf[2] = {band.as<c128>(), nullptr};
+  struct Events {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;   // [0, 1]: band buffer filled; [2, 3]: band buffer consumed
+  const bool two = sg != nullptr && nt > jc;
+  if (two) {
+    band2.alloc(band_bytes);
+    Zbuf[1] = band2.as<c128>();
+    for (hipEvent_t& x : ev.e) FOSB_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  }
   // column lists per band (host): edges whose T+ or T- lies in the band
   std::vector<int32_t> cols;
   std::vector<int64_t> cbeg;
@@ -445,6 +464,9 @@ void assemble_bands(Context& ctx, const Mesh& m, double k, int n_gauss, int64_t 
   for (int j0 = 0; j0 < nt; j0 += jc, ++bi) {
     const int j1 = std::min(nt, j0 + jc);
     const int w = j1 - j0;
+    const int buf = two ? (bi & 1) : 0;
+    c128* Zc = Zbuf[buf];
+    if (two && bi >= 2) FOSB_HIP(hipStreamWaitEvent(s, ev.e[2 + buf], 0));   // band bi - 2 consumed
     dim3 g1((w + 63) / 64, (nt + 3) / 4);
     hipLaunchKernelGGL(k_assemble_regular, g1, dim3(256), 0, s, md, R, k, j0, w, Zc, ldc);
     FOSB_LAUNCH_CHECK();
@@ -458,9 +480,19 @@ void assemble_bands(Context& ctx, const Mesh& m, double k, int n_gauss, int64_t 
                          ctx.ss_cnt[n_gauss][0], ctx.ss_cnt[n_gauss][1], ctx.ss_cnt[n_gauss][2], k, j0, Zc, ldc);
       FOSB_LAUNCH_CHECK();
     }
-    sink(j0, j1, (const c128*)Zc, ldc, dcols.as<int32_t>() + cbeg[bi], (int)(cbeg[bi + 1] - cbeg[bi]));
+    const int32_t* bc = dcols.as<int32_t>() + cbeg[bi];
+    const int nbc = (int)(cbeg[bi + 1] - cbeg[bi]);
+    if (two) {
+      FOSB_HIP(hipEventRecord(ev.e[buf], s));
+      FOSB_HIP(hipStreamWaitEvent(sg->stream, ev.e[buf], 0));
+      sink(sg->stream, j0, j1, (const c128*)Zc, ldc, bc, nbc);
+      FOSB_HIP(hipEventRecord(ev.e[2 + buf], sg->stream));
+    } else {
+      sink(s, j0, j1, (const c128*)Zc, ldc, bc, nbc);
+    }
   }
-  // the band buffer and the column lists must live until the kernels ran
+  if (two) FOSB_HIP(hipStreamWaitEvent(s, ev.e[2 + ((bi - 1) & 1)], 0));   // the last band consumed
+  // the band buffers and the column lists must live until the kernels ran
   FOSB_HIP(hipStreamSynchronize(s));
 }
 }  // namespace
@@ -469,27 +501,31 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
   // 1 GiB bands: at nt = 20480 these assembled faster than 256 and 512 MiB ones, and about as fast as 2 GiB
   const int ne = (int)m.h.ne;
   const MeshDev md = m.dev();
-  assemble_bands(ctx, m, k, n_gauss, (int64_t)1024 << 20,
-                 [&](int j0, int j1, const c128* Zc, int64_t ldc, const int32_t* cols, int nc) {
-                   if (nc <= 0) return;
-                   dim3 g3((nc + 63) / 64, (ne + 3) / 4);
-                   hipLaunchKernelGGL(k_assemble_gather, g3, dim3(256), 0, ctx.stream, ne, md.edge_tri,
-                                      md.edge_loc, j0, j1, cols, nc, Zc, ldc, Z, ldz);
-                   FOSB_LAUNCH_CHECK();
-                 });
+  assemble_bands(
+      ctx, m, k, n_gauss, (int64_t)1024 << 20,
+      [&](hipStream_t st, int j0, int j1, const c128* Zc, int64_t ldc, const int32_t* cols, int nc) {
+        if (nc <= 0) return;
+        dim3 g3((nc + 63) / 64, (ne + 3) / 4);
+        hipLaunchKernelGGL(k_assemble_gather, g3, dim3(256), 0, st, ne, md.edge_tri, md.edge_loc, j0, j1, cols, nc,
+                           Zc, ldc, Z, ldz);
+        FOSB_LAUNCH_CHECK();
+      },
+      &ctx.la_context());
 }
 
 void assemble_efie_c64(Context& ctx, const Mesh& m, double k, int n_gauss, c64* Z, int64_t ldz) {
   const int ne = (int)m.h.ne;
   const MeshDev md = m.dev();
-  assemble_bands(ctx, m, k, n_gauss, (int64_t)1024 << 20,
-                 [&](int j0, int j1, const c128* Zc, int64_t ldc, const int32_t* cols, int nc) {
-                   if (nc <= 0) return;
-                   dim3 g3((nc + 63) / 64, (ne + 3) / 4);
-                   hipLaunchKernelGGL(k_assemble_gather_c64, g3, dim3(256), 0, ctx.stream, ne, md.edge_tri,
-                                      md.edge_loc, j0, j1, cols, nc, Zc, ldc, Z, ldz);
-                   FOSB_LAUNCH_CHECK();
-                 });
+  assemble_bands(
+      ctx, m, k, n_gauss, (int64_t)1024 << 20,
+      [&](hipStream_t st, int j0, int j1, const c128* Zc, int64_t ldc, const int32_t* cols, int nc) {
+        if (nc <= 0) return;
+        dim3 g3((nc + 63) / 64, (ne + 3) / 4);
+        hipLaunchKernelGGL(k_assemble_gather_c64, g3, dim3(256), 0, st, ne, md.edge_tri, md.edge_loc, j0, j1, cols,
+                           nc, Zc, ldc, Z, ldz);
+        FOSB_LAUNCH_CHECK();
+      },
+      &ctx.la_context());
 }
 
 // ------------------------------------------------------------------ PMCHWT (dielectric) blocks
@@ -1325,7 +1361,7 @@ void efie_residual(Context& ctx, const Mesh& m, double k, int n_gauss, const c12
   jc = std::min(jc, nt);
   DevBuf zr((size_t)ne * 3 * jc * sizeof(c128)), xt((size_t)3 * jc * nrhs * sizeof(c128));
   assemble_bands(ctx, m, k, n_gauss, budget,
-                 [&](int j0, int j1, const c128* Zc, int64_t ldc, const int32_t*, int) {
+                 [&](hipStream_t, int j0, int j1, const c128* Zc, int64_t ldc, const int32_t*, int) {
                    const int w = j1 - j0, ncol = 3 * w;
                    dim3 g1((ncol + 63) / 64, (ne + 3) / 4);
                    hipLaunchKernelGGL(k_band_rows, g1, dim3(256), 0, ctx.stream, ne, md.edge_tri, md.edge_loc,
