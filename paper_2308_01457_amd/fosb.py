@@ -232,8 +232,8 @@ class Context:
             lib().fosb_context_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():   # process teardown: the driver reclaims everything
+    def __del__(self, _finalizing=sys.is_finalizing):   # bound now: `sys` may be gone at teardown
+        if _finalizing():   # process teardown: the driver reclaims everything
             return
         try:
             self.close()
@@ -299,8 +299,8 @@ class Mesh:
             lib().fosb_mesh_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():   # process teardown: the driver reclaims everything
+    def __del__(self, _finalizing=sys.is_finalizing):   # bound now: `sys` may be gone at teardown
+        if _finalizing():   # process teardown: the driver reclaims everything
             return
         try:
             self.close()
@@ -452,8 +452,8 @@ class Level:
             lib().fosb_level_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():   # process teardown: the driver reclaims everything
+    def __del__(self, _finalizing=sys.is_finalizing):   # bound now: `sys` may be gone at teardown
+        if _finalizing():   # process teardown: the driver reclaims everything
             return
         try:
             self.close()
@@ -594,8 +594,8 @@ class LowRank:
             lib().fosb_lowrank_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):   # bound now: `sys` may be gone at teardown
+        if _finalizing():
             return
         try:
             self.close()
