@@ -97,7 +97,7 @@ typedef enum fosb_formulation {
 /* How a level's matrix was factored (fosb_level_factorization). */
 typedef enum fosb_factorization {
   FOSB_FACTOR_LU = 0,    /* partial (tournament) pivoting at the level's precision */
-  FOSB_FACTOR_SYM = 1    /* MIXED EFIE levels: the symmetric FP32 factorisation
+  FOSB_FACTOR_SYM = 1    /* MIXED levels: the symmetric FP32 factorisation
                             without pivoting described for fosb_opts.lu_pivoting */
 } fosb_factorization;
 
@@ -123,13 +123,16 @@ typedef struct fosb_opts {
   int32_t lu_pivoting;      /* MIXED levels' FP32 factorisation: 0 (default) uses
                                the matrix's symmetry when N >= 2048 and
                                max|Z - Z^T| <= 1e-5 max|Z| (the EFIE matrix is
-                               complex symmetric up to quadrature): no pivoting,
-                               U = D L^T from the multipliers, trailing updates of
-                               the lower triangle only (about half the flops),
-                               and partial (tournament) pivoting instead when a
-                               pivot vanishes or the growth factor exceeds 1e3;
-                               1: always partial pivoting.  FP64 levels always
-                               pivot.                                            */
+                               complex symmetric up to quadrature; for PMCHWT the
+                               test and the factorisation apply to S Z with
+                               S = diag(I, -I) on the [J; M] halves, which is
+                               symmetric, and the solves use Z^{-1} = (S Z)^{-1} S):
+                               no pivoting, U = D L^T from the multipliers,
+                               trailing updates of the lower triangle only (about
+                               half the flops), and partial (tournament) pivoting
+                               instead when a pivot vanishes or the growth factor
+                               exceeds 1e3; 1: always partial pivoting.  FP64
+                               levels always pivot.                              */
 } fosb_opts;
 
 /* Counters of a call; accumulate over calls (zero-initialise before the first).
@@ -300,8 +303,8 @@ fosb_status fosb_level_sd_weights(fosb_context* ctx, const fosb_level* level, in
 fosb_status fosb_level_formulation(const fosb_level* level, int32_t* form, double* eps_r, double* mu_r);
 /* The factorisation the level's construction kept (fosb_factorization) in
  * *kind: FOSB_FACTOR_SYM when the symmetric attempt succeeded, FOSB_FACTOR_LU
- * otherwise (FP64 levels, PMCHWT levels, N < 2048, lu_pivoting = 1, or the
- * attempt fell back).  Host-only. */
+ * otherwise (FP64 levels, N < 2048, lu_pivoting = 1, or the attempt fell
+ * back).  Host-only. */
 fosb_status fosb_level_factorization(const fosb_level* level, int32_t* kind);
 fosb_status fosb_level_info(const fosb_level* level, int64_t* n, int32_t* precision, int64_t* n_dirs);
 /* Device bytes a level built on mesh with this precision and n_dirs

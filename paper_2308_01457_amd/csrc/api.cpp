@@ -129,6 +129,7 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
     if (!adjoint) {
       permute_rows_gather(s, perm, R, nrhs, T, nrhs, n, nrhs);
       copy_c128_to_c64(s, T, nrhs, R32, nrhs, n, nrhs);
+      if (L.sym_sign) negate_rows_c64(s, R32, nrhs, n / 2, n, nrhs);   // (S Z)^{-1} S R
       trsm_lower_unit_inv<float>(ctx, A32, L.ldzlow, L.inv_L.as<c64>(), n, R32, nrhs, Y32, nrhs, nrhs);
       trsm_upper_inv<float>(ctx, A32, L.ldzlow, L.inv_U.as<c64>(), n, Y32, nrhs, R32, nrhs, nrhs);
       copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
@@ -137,6 +138,7 @@ void level_solve_inplace(Context& ctx, const Level& L, c128* B, int64_t ldb, int
       copy_c128_to_c64(s, R, nrhs, R32, nrhs, n, nrhs);
       trsm_upper_ch<float>(ctx, A32, L.ldzlow, L.dinv_U.as<c64>(), 0, n, R32, nrhs, nrhs);
       trsm_lower_unit_ch<float>(ctx, A32, L.ldzlow, L.dinv_L.as<c64>(), 0, n, R32, nrhs, nrhs);
+      if (L.sym_sign) negate_rows_c64(s, R32, nrhs, n / 2, n, nrhs);   // Z^{-H} = S (S Z)^{-H}
       copy_c64_to_c128(s, R32, nrhs, T, nrhs, n, nrhs);
       permute_rows_scatter(s, perm, T, nrhs, Rw, nrhs, n, nrhs);  // R (if it was Rw) is consumed
       D = Rw;
@@ -427,23 +429,29 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     L->inv_L.alloc(bytes);
     L->inv_U.alloc(bytes);
     bool factored = false;
-    if (!pm && o.lu_pivoting == 0 && n >= 2048) {
-      // symmetric EFIE matrix: no pivoting, half the trailing-update flops; kept when no
-      // pivot vanished and the growth factor stays below 1e3
+    if (o.lu_pivoting == 0 && n >= 2048) {
+      // symmetric matrix: no pivoting, half the trailing-update flops; kept when no
+      // pivot vanished and the growth factor stays below 1e3.  The EFIE matrix is
+      // symmetric; the PMCHWT matrix [[A, K], [-K, D]] (A, D, K symmetric) is not,
+      // but S Z = [[A, K], [K, -D]] is, with S = diag(I, -I) on the [J; M] halves:
+      // its factors serve Z^{-1} = (S Z)^{-1} S.
+      if (pm) negate_rows_c64(s, static_cast<c64*>(Zlow), ldzlow, n / 2, n, n);
       double defect = 0.0, zmax = 0.0;
       sym_check<float>(c, static_cast<const c64*>(Zlow), n, ldzlow, &defect, &zmax);
-      if (zmax > 0 && std::isfinite(zmax) && defect <= 1e-5 * zmax) {
+      const bool symmetric = zmax > 0 && std::isfinite(zmax) && defect <= 1e-5 * zmax;
+      if (symmetric) {
         info = lu_factor<float>(c, static_cast<c64*>(Zlow), n, ldzlow, L->dinv_L.as<c64>(), L->dinv_U.as<c64>(),
                                 L->perm, L->inv_L.as<c64>(), true);
         const double growth = absmax_upper<float>(c, static_cast<const c64*>(Zlow), n, ldzlow) / zmax;
         factored = info == 0 && std::isfinite(growth) && growth <= 1e3;
         L->sym_lu = factored ? 1 : 0;
-        if (!factored) {  // start again from the assembled matrix with pivoting
-          if (Z)
-            copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
-          else
-            assemble_efie_c64(c, *mesh, k, o.n_gauss_singular, static_cast<c64*>(Zlow), ldzlow);
-        }
+        L->sym_sign = factored && pm ? 1 : 0;
+      }
+      if (!factored && (symmetric || pm)) {  // start again from the assembled matrix with pivoting
+        if (Z)
+          copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
+        else
+          assemble_efie_c64(c, *mesh, k, o.n_gauss_singular, static_cast<c64*>(Zlow), ldzlow);
       }
     }
     if (!factored)

@@ -315,6 +315,7 @@ struct Level {
   int sd_field = -1;           // PMCHWT: field of the shape-derivative weights (-1: none built)
   int sd_streamed = 0;         // PMCHWT: weights recomputed by source bands when used, none stored
   int sym_lu = 0;              // MIXED: factored without pivoting (symmetric form)
+  int sym_sign = 0;            // MIXED PMCHWT: the FP32 factors are of S Z, S = diag(I, -I) on [J; M]
   DevBuf Wsd;                  // PMCHWT: c128 [n_dirs][n][6 nt] shape-derivative weights (with nu)
   const void* lu() const { return precision == FOSB_PREC_FP64 ? Z : Zlow; }
 };
@@ -413,6 +414,8 @@ void permute_rows_gather(hipStream_t s, const int32_t* perm, const c128* src, in
 void permute_rows_scatter(hipStream_t s, const int32_t* perm, const c128* src, int64_t lds, c128* dst,
                           int64_t ldd, int64_t n, int64_t ncols);
 void copy_c128_to_c64(hipStream_t s, const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows, int64_t cols);
+// rows [r0, r1) of a complex64 matrix (row stride ld, cols columns) <- their negatives
+void negate_rows_c64(hipStream_t s, c64* p, int64_t ld, int64_t r0, int64_t r1, int64_t cols);
 void copy_c64_to_c128(hipStream_t s, const c64* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int64_t cols);
 void copy_c128(hipStream_t s, const c128* src, int64_t lds, c128* dst, int64_t ldd, int64_t rows, int64_t cols);
 // dst = diag(row_scale) src^H (row_scale: device, one per dst row, or nullptr)

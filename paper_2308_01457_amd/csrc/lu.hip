@@ -1353,6 +1353,23 @@ static void copy2d(hipStream_t s, const cplx<S>* src, int64_t lds, cplx<D>* dst,
   FOSB_LAUNCH_CHECK();
 }
 
+__global__ void k_negate_rows(c64* __restrict__ p, int64_t ld, int64_t r0, int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    c64& v = p[(r0 + e / cols) * ld + e % cols];
+    v = c64{-v.re, -v.im};
+  }
+}
+
+void negate_rows_c64(hipStream_t s, c64* p, int64_t ld, int64_t r0, int64_t r1, int64_t cols) {
+  const int64_t rows = r1 - r0;
+  if (rows <= 0 || cols <= 0) return;
+  const int64_t total = rows * cols;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_negate_rows, dim3(grid), dim3(256), 0, s, p, ld, r0, rows, cols);
+  FOSB_LAUNCH_CHECK();
+}
+
 void copy_c128_to_c64(hipStream_t s, const c128* src, int64_t lds, c64* dst, int64_t ldd, int64_t rows,
                       int64_t cols) {
   copy2d<double, float>(s, src, lds, dst, ldd, rows, cols);

@@ -266,3 +266,45 @@ def test_sd_lowrank_route(fz):
         fosb.correlation(ctx, streamed, 2, 3, cov, 0)
     lr1.close()
     lr2.close()
+
+
+def test_pmchwt_symmetric_factorisation(fz):
+    """A MIXED PMCHWT level with 2N >= 2048 (s = 3: 2N = 3840) factors S Z,
+    S = diag(I, -I) on the [J; M] halves, which is symmetric, without pivoting;
+    its refined solves, adjoint solves and first moment agree with the FP64
+    level's and with those of the pivoted FP32 factorisation (lu_pivoting = 1)."""
+    fosb, ctx, torch = fz
+    V, F = workloads.icosphere(3)
+    m = fosb.Mesh(ctx, V, F)
+    Z = fosb.assemble_pmchwt(ctx, m, K0, EPS, MU)
+    n = Z.shape[0]
+    S = torch.ones(n, dtype=torch.complex128, device=Z.device)
+    S[n // 2:] = -1.0
+    SZ = S[:, None] * Z
+    asym = float((SZ - SZ.T).abs().max() / SZ.abs().max())
+    opts = lambda piv: fosb.opts_default(ir_tol=1e-12, ir_max_sweeps=30, lu_pivoting=piv)
+    lv = {name: fosb.Level.pmchwt(ctx, m, K0, EPS, MU, Z, fosb.MIXED, dirs=[D], pols=[P], opts=opts(piv))
+          for name, piv in (("sym", 0), ("piv", 1))}
+    lv["fp64"] = fosb.Level.pmchwt(ctx, m, K0, EPS, MU, Z.clone(), fosb.FP64, dirs=[D], pols=[P])
+    print(f"[gpu] PMCHWT s=3 (2N={n}): max|SZ - (SZ)^T| / max|SZ| = {asym:.2e}, factorisations "
+          f"{ {k: l.factorization() for k, l in lv.items()} }", flush=True)
+    assert lv["sym"].factorization() == fosb.FACTOR_SYM
+    assert lv["piv"].factorization() == fosb.FACTOR_LU
+    g = torch.Generator(device="cpu").manual_seed(13)
+    B = torch.randn((n, 3), dtype=torch.complex128, generator=g).to(Z.device)
+    for adjoint in (False, True):
+        X = {}
+        for name, l in lv.items():
+            st = fosb.Stats()
+            X[name] = (l.solve_adjoint if adjoint else l.solve)(B.clone(), st)
+        for name in ("sym", "piv"):
+            rel = float((X[name] - X["fp64"]).norm() / X["fp64"].norm())
+            print(f"[gpu]   {'adjoint ' if adjoint else ''}solve {name} vs FP64 {rel:.2e}", flush=True)
+            assert rel < 1e-10
+        Zop = Z.conj().T if adjoint else Z
+        res = float((Zop @ X["sym"] - B).norm() / (Z.norm() * X["sym"].norm()))
+        assert res < 1e-13
+    u = {name: l.first_moment(0) for name, l in lv.items()}
+    assert float((u["sym"] - u["fp64"]).norm() / u["fp64"].norm()) < 1e-10
+    for l in lv.values():
+        l.close()
