@@ -990,10 +990,7 @@ static void rec_lu(LuRun<T>& R, int64_t k, int64_t w) {
   rec_lu(R, k, w1);
   cplx<T>* A = R.A;
   const int64_t lda = R.lda;
-  if (R.sym)  // symmetric form: U12 = D L21^T from the left half's multipliers, no triangular solve
-    sym_u12<T>(R.ctx->stream, A, lda, k, w1, k + w1, w - w1);
-  else
-    trsm_lower_unit<T>(*R.ctx, A, lda, R.dinvL, k, w1, A + k * lda + (k + w1), lda, w - w1);
+  trsm_lower_unit<T>(*R.ctx, A, lda, R.dinvL, k, w1, A + k * lda + (k + w1), lda, w - w1);
   gemm<T>(*R.ctx, R.n - k - w1, w - w1, w1, -1.0, A + (k + w1) * lda + k, lda, A + k * lda + (k + w1), lda, 1.0,
           A + (k + w1) * lda + (k + w1), lda);
   rec_lu(R, k + w1, w - w1);
