@@ -1758,7 +1758,9 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   std::mutex mu;
   std::condition_variable cv;
   bool coarse_ready = false, mark_ready = false;
-  std::exception_ptr aux_err;
+  // build_err is written before coarse_ready is published; pair_err only
+  // before the worker ends, and read after the join
+  std::exception_ptr build_err, pair_err;
   struct MarkEvent {
     hipEvent_t ev = nullptr;
     ~MarkEvent() {
@@ -1772,14 +1774,14 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
       bind(aux);
       for (int i = top - 1; i >= 0; --i) build(aux, i);
     } catch (...) {
-      aux_err = std::current_exception();
+      build_err = std::current_exception();
     }
     {
       std::lock_guard<std::mutex> lk(mu);
       coarse_ready = true;
     }
     cv.notify_all();
-    if (aux_err) return;
+    if (build_err) return;
     try {
       {
         std::unique_lock<std::mutex> lk(mu);
@@ -1790,7 +1792,7 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
         if (v[p][0] != L) pair(aux, p, &st_aux);
       FOSB_HIP(hipStreamSynchronize(aux.stream));
     } catch (...) {
-      aux_err = std::current_exception();
+      pair_err = std::current_exception();
     }
   });
   struct Joiner {
@@ -1832,12 +1834,13 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
     std::unique_lock<std::mutex> lk(mu);
     cv.wait(lk, [&] { return coarse_ready; });
   }
-  if (!aux_err)
+  if (!build_err)
     for (size_t p = 0; p < v.size(); ++p)
       if (v[p][0] == L) pair(*ctx, p, &st_main);
   FOSB_HIP(hipStreamSynchronize(ctx->stream));
   worker.join();
-  if (aux_err) std::rethrow_exception(aux_err);
+  if (build_err) std::rethrow_exception(build_err);
+  if (pair_err) std::rethrow_exception(pair_err);
 
   std::vector<const fosb_level*> lp(n_levels);
   for (int i = 0; i < n_levels; ++i) {
@@ -1893,6 +1896,15 @@ fosb_status fosb_second_moment_batch(fosb_context* ctx, const fosb_batch_shape* 
   std::vector<fosb_stats> st(nw);
   for (auto& x : st) x = fosb_stats{};
   std::vector<std::thread> pool;
+  struct PoolJoiner {   // joins the started workers also when starting another one throws
+    std::vector<std::thread>& p;
+    std::atomic<bool>& stop;
+    ~PoolJoiner() {
+      stop.store(true);
+      for (auto& t : p)
+        if (t.joinable()) t.join();
+    }
+  } pool_joiner{pool, stop};
   for (int w = 0; w < nw; ++w)
     pool.emplace_back([&, w] {
       Context& c = *ctx->workers[w];
