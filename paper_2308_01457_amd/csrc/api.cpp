@@ -371,7 +371,7 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
                                                const double* pols, int64_t n_dirs, int32_t field,
                                                const fosb_opts& o, int32_t form = FOSB_FORM_EFIE,
                                                double eps_r = 1.0, double mu_r = 1.0, int32_t sd_field = -1,
-                                               bool sd_streamed = false) {
+                                               bool sd_streamed = false, bool zlow_ready = false) {
   hipStream_t s = c.stream;
   const bool pm = form == FOSB_FORM_PMCHWT;
   const int64_t n = pm ? 2 * mesh->h.ne : mesh->h.ne;
@@ -419,7 +419,8 @@ static std::unique_ptr<fosb_level> level_build(Context& c, const fosb_mesh* mesh
     L->dinv_L.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
     L->dinv_U.alloc((size_t)nblk * kPanel * kPanel * sizeof(c64));
     if (Z) {
-      copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
+      // zlow_ready: the assembly that wrote Z also stored it rounded to complex64
+      if (!zlow_ready) copy_c128_to_c64(s, static_cast<const c128*>(Z), ldz, static_cast<c64*>(Zlow), ldzlow, n, n);
     } else {  // no FP64 copy: assemble in FP64 column bands straight into complex64
       assemble_efie_c64(c, *mesh, k, o.n_gauss_singular, static_cast<c64*>(Zlow), ldzlow);
       if (o.certify) matrix_certificate(true);
@@ -687,10 +688,10 @@ static void far_field_impl(Context& c, const fosb_level* const* levels, int32_t 
     else
       level_far_field(s, *levels[i], dx.as<double>(), n_a, FF[i].as<c128>());
   }
-  FOSB_HIP(hipMemsetAsync(var, 0, nd * rows * sizeof(double), s));
+  zero_f64(s, var, nd * rows);
   if (cor) {
     if (nd != 1) fail(FOSB_E_UNSUPPORTED, "the angular correlation is computed for one incidence at a time");
-    FOSB_HIP(hipMemsetAsync(cor, 0, 3 * n_a * n_a * sizeof(c128), s));
+    zero_f64(s, static_cast<double*>(cor), 2 * 3 * n_a * n_a);
   }
   // one product FF_l1 [Sigma_0 | Sigma_1 | ...] per pair covers every incidence
   int64_t maxn2 = 0;
@@ -747,11 +748,12 @@ static void shape_pipeline(Context& c, const fosb_mesh* const* meshes, int32_t n
     c.ws_Z[i].reserve((size_t)n * n * sizeof(c128));
     if (mixed) c.ws_Zlow[i].reserve((size_t)n * n * sizeof(c64));
     {
-      ProfScope prof(c, FOSB_K_ASSEMBLE, 0.0, 16.0 * (double)n * (double)n);
-      assemble_efie(c, *meshes[i], k, o.n_gauss_singular, c.ws_Z[i].as<c128>(), n);
+      ProfScope prof(c, FOSB_K_ASSEMBLE, 0.0, (mixed ? 24.0 : 16.0) * (double)n * (double)n);
+      assemble_efie(c, *meshes[i], k, o.n_gauss_singular, c.ws_Z[i].as<c128>(), n,
+                    mixed ? c.ws_Zlow[i].as<c64>() : nullptr, mixed ? n : 0);
     }
     lv[i] = level_build(c, meshes[i], k, precision, c.ws_Z[i].p, n, mixed ? c.ws_Zlow[i].p : nullptr,
-                        mixed ? n : 0, dirs, pols, n_dirs, field, o);
+                        mixed ? n : 0, dirs, pols, n_dirs, field, o, FOSB_FORM_EFIE, 1.0, 1.0, -1, false, mixed);
   }
   std::vector<void*> bp(v.size());
   std::vector<int64_t> ldb(v.size());
@@ -1719,15 +1721,16 @@ fosb_status fosb_second_moment(fosb_context* ctx, const fosb_mesh* const* meshes
   std::vector<std::unique_ptr<fosb_level>> lv(n_levels);
   fosb_stats st_main{}, st_aux{};
 
+  const bool mixed = precision == FOSB_PREC_MIXED;
   auto build = [&](Context& c, int i) {
     if (Z[i]) {  // a MIXED level without Z assembles its complex64 copy itself
       const double ne = (double)meshes[i]->h.ne;
-      ProfScope prof(c, FOSB_K_ASSEMBLE, 0.0, 16.0 * ne * ne);
-      assemble_efie(c, *meshes[i], k, o.n_gauss_singular, static_cast<c128*>(Z[i]), ldz[i]);
+      ProfScope prof(c, FOSB_K_ASSEMBLE, 0.0, (mixed ? 24.0 : 16.0) * ne * ne);
+      assemble_efie(c, *meshes[i], k, o.n_gauss_singular, static_cast<c128*>(Z[i]), ldz[i],
+                    mixed ? static_cast<c64*>(Zlow[i]) : nullptr, mixed ? ldzlow[i] : 0);
     }
-    lv[i] = level_build(c, meshes[i], k, precision, Z[i], ldz[i],
-                        precision == FOSB_PREC_MIXED ? Zlow[i] : nullptr,
-                        precision == FOSB_PREC_MIXED ? ldzlow[i] : 0, dirs, pols, n_dirs, field, o);
+    lv[i] = level_build(c, meshes[i], k, precision, Z[i], ldz[i], mixed ? Zlow[i] : nullptr, mixed ? ldzlow[i] : 0,
+                        dirs, pols, n_dirs, field, o, FOSB_FORM_EFIE, 1.0, 1.0, -1, false, mixed && Z[i] != nullptr);
   };
   auto pair = [&](Context& c, size_t p, fosb_stats* st) {
     const fosb_level& a = *lv[v[p][0] - L0];

@@ -281,12 +281,14 @@ __global__ __launch_bounds__(256) void k_assemble_singular(MeshDev md, const int
 }
 
 // Z[m][n] for the columns n listed for this band: sum of the (up to) four local
-// blocks of the band; store when the band holds T+ of n, add otherwise.
+// blocks of the band; store when the band holds T+ of n, add otherwise.  With
+// Zl, the final entries are also stored rounded to complex64.
 __global__ __launch_bounds__(256) void k_assemble_gather(int ne, const int32_t* __restrict__ edge_tri,
                                                          const int32_t* __restrict__ edge_loc, int j0, int j1,
                                                          const int32_t* __restrict__ cols, int ncols,
                                                          const c128* __restrict__ Zc, int64_t ldc,
-                                                         c128* __restrict__ Z, int64_t ldz) {
+                                                         c128* __restrict__ Z, int64_t ldz,
+                                                         c64* __restrict__ Zl, int64_t ldl) {
   const int ci = blockIdx.x * 64 + (threadIdx.x & 63);
   const int m = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (ci >= ncols || m >= ne) return;
@@ -309,12 +311,15 @@ __global__ __launch_bounds__(256) void k_assemble_gather(int ne, const int32_t* 
     si += u.im + v.im;
   }
   c128* z = Z + (int64_t)m * ldz + n;
-  if (has_p) {
-    *z = c128{sr, si};
-  } else {
-    c128 o = *z;
-    *z = c128{o.re + sr, o.im + si};
+  c128 out{sr, si};
+  if (!has_p) {
+    const c128 o = *z;
+    out = c128{o.re + sr, o.im + si};
   }
+  *z = out;
+  // the optional complex64 copy receives the entry once it is final: T- lies
+  // in this band (T+ < T-, so an earlier band held T+ if this one does not)
+  if (Zl && tm < j1) Zl[(int64_t)m * ldl + n] = c64{(float)out.re, (float)out.im};
 }
 
 static void ensure_ss_table(Context& ctx, int n) {
@@ -497,7 +502,8 @@ void assemble_bands(Context& ctx, const Mesh& m, double k, int n_gauss, int64_t 
 }
 }  // namespace
 
-void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz) {
+void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz, c64* Zl,
+                   int64_t ldl) {
   // 1 GiB bands: at nt = 20480 these assembled faster than 256 and 512 MiB ones, and about as fast as 2 GiB
   const int ne = (int)m.h.ne;
   const MeshDev md = m.dev();
@@ -507,7 +513,7 @@ void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, 
         if (nc <= 0) return;
         dim3 g3((nc + 63) / 64, (ne + 3) / 4);
         hipLaunchKernelGGL(k_assemble_gather, g3, dim3(256), 0, st, ne, md.edge_tri, md.edge_loc, j0, j1, cols, nc,
-                           Zc, ldc, Z, ldz);
+                           Zc, ldc, Z, ldz, Zl, ldl);
         FOSB_LAUNCH_CHECK();
       },
       &ctx.la_context());

@@ -324,7 +324,9 @@ constexpr int kPanel = 32;   // LU panel width / TRSM diagonal block size
 
 // ------------------------------------------------------------------ kernels (host launchers)
 // assemble.hip
-void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz);
+// Zl (optional): also receives Z rounded to complex64, each entry written once it is final
+void assemble_efie(Context& ctx, const Mesh& m, double k, int n_gauss, c128* Z, int64_t ldz, c64* Zl = nullptr,
+                   int64_t ldl = 0);
 // the same matrix assembled in FP64 and stored rounded to complex64 (no complex128 copy)
 void assemble_efie_c64(Context& ctx, const Mesh& m, double k, int n_gauss, c64* Z, int64_t ldz);
 // R (N x nrhs) -= Z X in FP64 with Z re-assembled band by band and discarded

@@ -211,11 +211,14 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
                                            cplx<T>* __restrict__ invU) {
   constexpr int NODE = Node<T>::size;
   __shared__ int inblk[NB];   // 1 if row k + r is itself a pivot
+  __shared__ cplx<T> udinv[NB];   // 1 / U[i][i] for i < wk (FP32 back substitution)
   for (int e = tid; e < NB * NB; e += NODE) {
     const int r = e / NB, c = e % NB;
     if (r >= wk || c >= w) tb[r][c] = cplx<T>{T(0), T(0)};
   }
   if (tid < NB) inblk[tid] = 0;
+  // the zero fill above leaves the diagonal entries i < wk (<= w) alone
+  if (tid < NB) udinv[tid] = tid < wk ? cinv(tb[tid][tid]) : cplx<T>{T(0), T(0)};
   __syncthreads();
   if (tid < wk && win[tid] < k + wk) inblk[win[tid] - k] = 1;
   for (int e = tid; e < NB * NB; e += NODE) top[e] = tb[e / NB][e % NB];
@@ -260,7 +263,7 @@ __device__ __forceinline__ void panel_root(cplx<T> (*tb)[NB + 1], const int* win
             v.re -= u.re * x[j].re - u.im * x[j].im;
             v.im -= u.re * x[j].im + u.im * x[j].re;
           }
-          v = cmul(v, cinv(tb[i][i]));
+          v = cmul(v, udinv[i]);
         }
         x[i] = v;
       }
@@ -457,16 +460,17 @@ __global__ __launch_bounds__(Node<T>::size) void k_nopiv_root(const cplx<T>* __r
       if (j < w) {
         const cplx<T> p{lane_value(a[j].re, j), lane_value(a[j].im, j)};
         if (zc < 0 && p.re == T(0) && p.im == T(0)) zc = j;
-        const cplx<T> l = cmul(a[j], cinv(p));   // cinv(0) = 0: an exactly zero pivot is reported through info
+        // the multiplier, zero on the rows at and above the pivot (their
+        // entries then stay as they are); cinv_panel(0) = 0: an exactly zero
+        // pivot is reported through info
         const bool below = row && r > j;
+        const cplx<T> l = below ? cmul(a[j], cinv_panel(p)) : cplx<T>{T(0), T(0)};
         if (below) a[j] = l;
 #pragma unroll
         for (int c = j + 1; c < NB; ++c) {
           const cplx<T> u{lane_value(a[c].re, j), lane_value(a[c].im, j)};
-          if (below) {
-            a[c].re -= l.re * u.re - l.im * u.im;
-            a[c].im -= l.re * u.im + l.im * u.re;
-          }
+          a[c].re -= l.re * u.re - l.im * u.im;
+          a[c].im -= l.re * u.im + l.im * u.re;
         }
       }
     }
@@ -1112,6 +1116,10 @@ static void blocked_lu(LuRun<T>& R, Context& U, int64_t nb) {
   FOSB_HIP(hipStreamWaitEvent(sa, ev_look, 0));
 }
 
+__global__ void k_set_i32(int32_t* p, int32_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
 template <typename T>
 int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* dinvL, cplx<T>* dinvU,
                   std::vector<int32_t>& perm, cplx<T>* invL, bool sym) {
@@ -1139,7 +1147,8 @@ int64_t lu_factor(Context& ctx, cplx<T>* A, int64_t n, int64_t lda, cplx<T>* din
   R.invL = invL;
   R.sym = sym && n >= kLookaheadMinN;
   // first zero pivot, reduced with atomicMin: starts above every index (0x7f7f7f7f)
-  FOSB_HIP(hipMemsetAsync(R.info, 0x7f, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, s, R.info, (int32_t)0x7f7f7f7f);
+  FOSB_LAUNCH_CHECK();
   if (n >= kLookaheadMinN) {
     Context& U = ctx.la_context();
     // the update stream starts after everything already queued on the panel stream

@@ -253,10 +253,12 @@ def autotune_table(ctx: "Context") -> dict:
     """fosb_autotune_table: the tuned table as {bucket key: tile variant}."""
     n = _I64()
     _check(lib().fosb_autotune_table(ctx.h, None, None, 0, C.byref(n)))
-    keys = (_I64 * max(n.value, 1))()
-    var = (_I32 * max(n.value, 1))()
-    _check(lib().fosb_autotune_table(ctx.h, keys, var, n.value, C.byref(n)))
-    return {int(keys[i]): int(var[i]) for i in range(n.value)}
+    cap = n.value
+    keys = (_I64 * max(cap, 1))()
+    var = (_I32 * max(cap, 1))()
+    _check(lib().fosb_autotune_table(ctx.h, keys, var, cap, C.byref(n)))
+    # the table may have grown between the two calls (tuning on another thread)
+    return {int(keys[i]): int(var[i]) for i in range(min(n.value, cap))}
 
 
 def autotune_load(ctx: "Context", table: dict) -> None:

@@ -58,6 +58,32 @@ def test_pipeline_equals_step_by_step(fz, oracle_levels, precision):
     assert st.n_solves == 3
 
 
+def test_pipeline_equals_step_by_step_symmetric_top(fz):
+    """The same exact equality, mixed precision, with the finest level (s = 4,
+    N = 7680, k = 5) in the symmetric FP32 factorisation: the pass takes that
+    level's complex64 copy from the assembly's gather, the step-by-step calls
+    convert the assembled matrix, and the two copies must agree bit for bit."""
+    fosb, ctx, torch = fz
+    k = 5.0
+    xh = workloads.angles_xz(61)
+    cov = fosb.make_cov("gaussian", SIG, ELL)
+    meshes = [fosb.Mesh(ctx, *workloads.icosphere(s)) for s in (2, 3, 4)]
+    print("[gpu] pipeline mixed s=2..4, k=5 (symmetric top level)", flush=True)
+    var, blocks, lv = fosb.second_moment(ctx, meshes, 2, 4, k, fosb.MIXED, cov, xh, keep_levels=True)
+    ref = []
+    for m in meshes:
+        Z = fosb.assemble(ctx, m, k)
+        ref.append(fosb.Level(ctx, m, k, Z, fosb.MIXED))
+    assert lv[-1].factorization() == fosb.FACTOR_SYM and ref[-1].factorization() == fosb.FACTOR_SYM
+    for a, b in zip(lv, ref):
+        assert torch.equal(a.first_moment(0), b.first_moment(0))
+    b_ref = fosb.correlation(ctx, ref, 2, 4, cov)
+    v_ref = fosb.far_field_moments(ctx, ref, 2, 4, b_ref, xh)
+    assert torch.equal(var, v_ref)
+    for b, r in zip(blocks, b_ref):
+        assert torch.equal(b, r)
+
+
 def test_pipeline_single_level_and_handles(fz):
     """L0 = L (no auxiliary work), and the returned handles serve the adjoint."""
     fosb, ctx, torch = fz
