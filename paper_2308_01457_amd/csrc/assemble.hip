@@ -69,10 +69,22 @@ __device__ __forceinline__ void sincos_phase(double x, double* sn, double* cs) {
   pc = fma(pc, r2, 0.041666666666666664);
   pc = fma(pc, r2, -0.5);
   pc = fma(pc, r2, 1.0);
-  const int q = (int)n & 3;  // two's complement: n mod 4 also for n < 0
+  const int q = (int)n;  // two's complement: its low bits are n mod 4 also for n < 0
   const double s0 = (q & 1) ? pc : ps, c0 = (q & 1) ? ps : pc;
-  *sn = (q & 2) ? -s0 : s0;
-  *cs = ((q + 1) & 2) ? -c0 : c0;
+  // negation as a flip of the sign bit: sin for quadrants 2 and 3, cos for 1 and 2
+  const unsigned long long fs = (unsigned long long)(q & 2) << 62, fc = (unsigned long long)((q + 1) & 2) << 62;
+  *sn = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(s0) ^ fs));
+  *cs = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(c0) ^ fc));
+}
+
+// 1 / sqrt(x) for a positive finite x (the distance of two points of
+// non-touching triangles): the hardware estimate, then one step of the
+// second-order Newton iteration for the reciprocal square root,
+// y (1 + e/2 + 3e^2/8) with e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(y * -x, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 __device__ __forceinline__ void write_local_block(const MeshDev& md, int i, int j, int jj, double k,
@@ -164,7 +176,7 @@ __global__ __launch_bounds__(256) void k_assemble_regular(MeshDev md, Rule6 R, d
     for (int q = 0; q < 6; ++q) {
       const double d0 = e0 - yq[q][0], d1 = e1 - yq[q][1], d2 = e2 - yq[q][2];
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      const double ir = rsqrt(r2);
+      const double ir = rsqrt_pos(r2);
       const double r = r2 * ir;
       double sn, cs;
       sincos_phase(k * r, &sn, &cs);
@@ -643,7 +655,7 @@ __global__ __launch_bounds__(256) void k_pm_regular(MeshDev md, Rule6 R, double 
     for (int q = 0; q < 6; ++q) {
       const double d0 = e0 - yq[q][0], d1 = e1 - yq[q][1], d2 = e2 - yq[q][2];
       const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      const double ir = rsqrt(r2);
+      const double ir = rsqrt_pos(r2);
       const double r = r2 * ir;
       double sn, cs;
       sincos_phase(k * r, &sn, &cs);
