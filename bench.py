@@ -117,6 +117,9 @@ def parse():
                          "1e-13: backward error, 1-norm condition estimate and growth factor in the line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (HBM counter calibration)")
+    ap.add_argument("--assembly-only", type=int, default=0, metavar="R",
+                    help="only assemble the finest level of mixed_k5 (s = 5, k = 5) R times and print the times "
+                         "(the assembly kernels' rate alone, for a kernel trace)")
     return ap.parse_args()
 
 
@@ -571,6 +574,28 @@ def calibrate_copy():
                       "launches": 5}), flush=True)
 
 
+def assembly_only(reps):
+    """The finest level's EFIE assembly of mixed_k5 (unit icosphere s = 5,
+    N = 30720, k = 5), `reps` times on one context: the assembly kernels' rate
+    with nothing else on the chip."""
+    import torch
+
+    import workloads
+    from paper_2308_01457_amd import fosb
+    w = workloads.workload("mixed_k5")
+    ctx = fosb.Context(0)
+    mesh = fosb.Mesh(ctx, *w.meshes[-1])
+    Z = torch.empty((mesh.n_edges, mesh.n_edges), dtype=torch.complex128, device=ctx.torch_device)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fosb.assemble(ctx, mesh, w.k, Z=Z)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    print(json.dumps({"assembly": "mixed_k5 s=5", "n_edges": mesh.n_edges, "k": w.k, "seconds": times}), flush=True)
+
+
 def run_dielectric(args):
     """The sphere experiment's DE second moment: unit icosphere s = 2..L
     (2N up to 2 x 30 x 4^L), eps_r 2.1, mu_r 1, k0 3, incidence d = e_x,
@@ -703,6 +728,9 @@ def main():
     PROGRESS = args.progress
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.assembly_only > 0:
+        assembly_only(args.assembly_only)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
